@@ -1,0 +1,403 @@
+"""Pins for the CPU oracle: checks against closed forms, exact rational
+arithmetic, invariants and brute force, never against the oracle itself."""
+import itertools
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from paper_1210_5128_amd import datagen
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def tiny_data(n, N, arities, seed):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.integers(0, a, size=N) for a in arities], axis=1).astype(np.int8)
+
+
+# ---------------------------------------------------------------- local score
+
+def test_local_score_closed_form_two_samples():
+    # One binary node, no parents, data (0, 1), ESS = 1:
+    # lnG(1) - lnG(3) + 2 (lnG(1.5) - lnG(0.5)) = -ln 2 + 2 ln(1/2) = -3 ln 2.
+    data = np.array([[0], [1]], dtype=np.int8)
+    ls = oracle.local_score(data, [2], 0, 0, ess=1.0)
+    assert ls == pytest.approx(-3 * math.log(2), rel=0, abs=1e-14)
+
+
+@pytest.mark.parametrize("ess", [Fraction(1), Fraction(5, 2), Fraction(1, 3)])
+def test_local_score_matches_exact_polya_urn(ess):
+    arities = [2, 3, 4, 2]
+    data = tiny_data(4, 23, arities, seed=7)
+    n = 4
+    for i in range(n):
+        others = [m for m in range(n) if m != i]
+        for j in range(0, 4):
+            for pa in itertools.combinations(others, j):
+                mask = sum(1 << m for m in pa)
+                exact = brute.log_fraction(brute.exact_bd_local(data, arities, i, pa, ess))
+                got = oracle.local_score(data, arities, i, mask, ess=float(ess))
+                assert got == pytest.approx(exact, rel=1e-12, abs=1e-12), (i, pa)
+
+
+def test_local_score_structure_penalty_and_empty_data():
+    arities = [3, 2, 4]
+    data = tiny_data(3, 40, arities, seed=3)
+    for mask, size in [(0b010, 1), (0b110, 2), (0b000, 0)]:
+        base = oracle.local_score(data, arities, 0, mask)
+        pen = oracle.local_score(data, arities, 0, mask, log_gamma=-0.7)
+        assert pen - base == pytest.approx(-0.7 * size, abs=1e-12)
+    empty = np.zeros((0, 3), dtype=np.int8)
+    # N = 0: every Gamma ratio is 1, only |pi| ln gamma is left.
+    assert oracle.local_score(empty, arities, 0, 0b110, log_gamma=-1.25) == pytest.approx(-2.5, abs=0)
+    assert oracle.local_score(empty, arities, 2, 0, log_gamma=-1.25) == 0.0
+
+
+def test_prior_function_rules():
+    ln10 = math.log(10.0)
+    # Eq. (10) on R in [0,1] (mode 1): zero at 0.5, sign follows R - 0.5, +-12.5 (log10) at the ends.
+    assert oracle.ppf_nats(0.5, 1) == 0.0
+    assert oracle.ppf_nats(1.0, 1) == pytest.approx(12.5 * ln10, rel=1e-15)
+    assert oracle.ppf_nats(0.0, 1) == pytest.approx(-12.5 * ln10, rel=1e-15)
+    assert oracle.ppf_nats(0.7, 1) > 0 > oracle.ppf_nats(0.3, 1)
+    assert oracle.ppf_nats(0.75, 1) == pytest.approx(100 * 0.25 ** 3 * ln10, rel=1e-14)
+    # Weight form (mode 0): R = (1 + w) / 2.
+    for w in [-1.0, -0.3, 0.0, 0.4, 1.0]:
+        assert oracle.ppf_nats(w, 0) == pytest.approx(oracle.ppf_nats(0.5 * (1 + w), 1), rel=1e-15, abs=0)
+
+
+def test_prior_adds_one_term_per_present_edge():
+    arities = [2, 3, 2, 2]
+    data = tiny_data(4, 30, arities, seed=11)
+    prior = np.zeros((4, 4), dtype=np.float32)
+    prior[2, 0] = 0.8      # edge 0 -> 2
+    prior[2, 3] = -0.6     # edge 3 -> 2
+    prior[0, 2] = 0.9      # edge 2 -> 0 (reverse direction: must not count for node 2)
+    base = oracle.local_score(data, arities, 2, 0b1001)
+    with_p = oracle.local_score(data, arities, 2, 0b1001, prior=prior)
+    want = oracle.ppf_nats(np.float32(0.8), 0) + oracle.ppf_nats(np.float32(-0.6), 0)
+    assert with_p - base == pytest.approx(want, abs=1e-12)
+    assert oracle.local_score(data, arities, 2, 0b0010, prior=prior) == oracle.local_score(data, arities, 2, 0b0010)
+
+
+# ---------------------------------------------------------------- counts
+
+def test_counts_hand_example():
+    # Node 0 (binary) with parent 1 (ternary): k = x1, cell = k * 2 + x0.
+    data = np.array([[0, 0], [1, 0], [1, 2], [1, 2], [0, 1]], dtype=np.int8)
+    c = oracle.counts(data, [2, 3], 0, 0b10)
+    assert c.tolist() == [1, 1, 1, 0, 0, 2]
+    # Two parents 1 (ternary) and 2 (binary), lowest id most significant: k = x1 * 2 + x2.
+    data = np.array([[1, 2, 1], [0, 0, 0], [1, 2, 1]], dtype=np.int8)
+    c = oracle.counts(data, [2, 3, 2], 0, 0b110)
+    want = np.zeros(12, dtype=np.uint32)
+    want[(2 * 2 + 1) * 2 + 1] = 2
+    want[0] = 1
+    assert c.tolist() == want.tolist()
+
+
+def test_counts_sum_and_marginalise():
+    arities = [3, 2, 4, 3, 2]
+    data = tiny_data(5, 200, arities, seed=5)
+    for i in range(5):
+        others = [m for m in range(5) if m != i]
+        for pa in itertools.combinations(others, 2):
+            c = oracle.counts(data, arities, i, sum(1 << m for m in pa)).astype(np.int64)
+            assert c.sum() == 200
+            # summing out the larger parent gives the counts of the smaller set
+            hi = pa[1]
+            lo_mask = 1 << pa[0]
+            c_small = oracle.counts(data, arities, i, lo_mask).astype(np.int64)
+            r_i, r_hi = arities[i], arities[hi]
+            resh = c.reshape(arities[pa[0]], r_hi, r_i).sum(axis=1).reshape(-1)
+            assert resh.tolist() == c_small.tolist()
+
+
+# ---------------------------------------------------------------- score equivalence
+
+def graph_score(data, arities, pa, prior=None):
+    return sum(oracle.local_score(data, arities, i, int(pa[i]), prior=prior) for i in range(len(pa)))
+
+
+def test_bdeu_score_equivalence_covered_edge_reversal():
+    arities = [2, 3, 2, 4]
+    data = tiny_data(4, 150, arities, seed=21)
+    dags = brute.enumerate_dags(4, 3)
+    rng = np.random.default_rng(0)
+    checked = 0
+    for gi in rng.permutation(len(dags))[:200]:
+        pa = [int(v) for v in dags[gi]]
+        for y in range(4):
+            for x in range(4):
+                if x == y or not (pa[y] >> x) & 1:
+                    continue
+                if pa[y] != pa[x] | (1 << x):      # x -> y covered?
+                    continue
+                pb = list(pa)
+                pb[y] = pa[y] & ~(1 << x)
+                pb[x] = pa[x] | (1 << y)
+                a = graph_score(data, arities, pa)
+                b = graph_score(data, arities, pb)
+                assert a == pytest.approx(b, rel=1e-12), (pa, pb)
+                checked += 1
+    assert checked > 20
+
+
+def test_markov_equivalent_three_node_structures():
+    arities = [3, 2, 4]
+    data = tiny_data(3, 120, arities, seed=2)
+    chain_fwd = [0, 1 << 0, 1 << 1]          # 0 -> 1 -> 2
+    chain_bwd = [1 << 1, 1 << 2, 0]          # 0 <- 1 <- 2
+    fork = [1 << 1, 0, 1 << 1]               # 0 <- 1 -> 2
+    collider = [0, (1 << 0) | (1 << 2), 0]   # 0 -> 1 <- 2
+    s = [graph_score(data, arities, g) for g in (chain_fwd, chain_bwd, fork, collider)]
+    assert s[0] == pytest.approx(s[1], rel=1e-12)
+    assert s[0] == pytest.approx(s[2], rel=1e-12)
+    assert abs(s[0] - s[3]) > 1e-6
+
+
+# ---------------------------------------------------------------- indexing / counts of sets
+
+def test_rank_unrank_bijection_and_set_counts():
+    # Worked example of Sec. V.B: 6 candidate parents, size limit 4 -> 57 subsets.
+    assert oracle.num_sets(6, 4) == 57
+    # The 60-node, s = 4 parent-set table of Sec. V.B is 7.99 MB: 523,686 subsets x 16 bytes.
+    assert oracle.num_sets(60, 4) * 16 / 2 ** 20 == pytest.approx(7.99, abs=0.005)
+    assert oracle.num_sets(19, 4) == 5036 and oracle.num_sets(59, 4) == 489406
+    n, K = 7, 3
+    for node in [0, 3, 6]:
+        S = oracle.num_sets(n - 1, K)
+        seen = set()
+        for r in range(S):
+            m = oracle.unrank(n, K, node, r)
+            assert not (m >> node) & 1 and bin(m).count("1") <= K and m < (1 << n)
+            assert oracle.rank(n, K, node, m) == r
+            seen.add(m)
+        assert len(seen) == S
+
+
+def test_table1_counts():
+    rows = []
+    with open(os.path.join(HERE, "golden", "table1_graph_order_counts.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                n, g, o = line.split()
+                rows.append((int(n), float(g), float(o)))
+    for n, g, o in rows:
+        exact = brute.count_dags_robinson(n)
+        if n == 4:
+            assert exact == 543 and g == 453          # misprint in the table
+        elif n == 10:
+            assert exact == pytest.approx(4.175e18, rel=1e-3)
+        else:
+            assert exact == pytest.approx(g, rel=5e-3)
+        assert math.factorial(n) == pytest.approx(o, rel=1e-2)
+    assert len(brute.enumerate_dags(4, 3)) == 543
+    assert len(brute.enumerate_dags(5, 4)) == 29281
+
+
+# ---------------------------------------------------------------- order scoring vs brute force
+
+def brute_setup(n, K, N, seed, with_prior):
+    arities = [2, 3, 2, 3, 2][:n]
+    data = tiny_data(n, N, arities, seed)
+    prior = None
+    if with_prior:
+        prior = np.random.default_rng(seed + 1).uniform(-1, 1, size=(n, n)).astype(np.float32)
+    table = oracle.build_table(data, arities, K, prior=prior)
+    dags = brute.enumerate_dags(n, K)
+    # score of each DAG = sum of its local scores
+    local = {}
+    for i in range(n):
+        for m in set(int(v) for v in dags[:, i]):
+            local[(i, m)] = oracle.local_score(data, arities, i, m, prior=prior)
+    gs = np.array([sum(local[(i, int(row[i]))] for i in range(n)) for row in dags])
+    return data, arities, prior, table, dags, gs
+
+
+@pytest.mark.parametrize("n,K,with_prior", [(4, 3, False), (4, 2, True), (5, 4, True), (5, 2, False)])
+def test_order_score_equals_brute_force_over_dags(n, K, with_prior):
+    data, arities, prior, table, dags, gs = brute_setup(n, K, 60, seed=100 + n + K, with_prior=with_prior)
+    global_best = gs.max()
+    best_over_orders = -np.inf
+    for order in itertools.permutations(range(n)):
+        ok = brute.consistent_with(dags, order)
+        n_cons = int(ok.sum())
+        assert n_cons == np.prod([oracle.num_sets(p, K) for p in range(n)])
+        sub = gs[ok]
+        m = sub.max()
+        want_lse = m + math.log(np.exp(sub - m).sum())
+        lse, mx, best, nl, nb, ns = oracle.score_order(table, K, order, round_f32=False)
+        assert lse == pytest.approx(want_lse, rel=1e-12, abs=1e-10)
+        assert mx == pytest.approx(m, rel=1e-12, abs=1e-10)
+        # the greedy graph is the exhaustive best DAG consistent with the order
+        arg = dags[ok][int(np.argmax(sub))]
+        assert [int(v) for v in best] == [int(v) for v in arg]
+        best_over_orders = max(best_over_orders, mx)
+    # the globally best graph is consistent with the best order (Sec. III.B)
+    assert best_over_orders == pytest.approx(global_best, rel=1e-12)
+
+
+def test_second_best_and_node_terms_by_listing():
+    arities = [2, 2, 3, 2, 2, 3]
+    data = tiny_data(6, 80, arities, seed=9)
+    K = 3
+    table = oracle.build_table(data, arities, K)
+    order = [3, 0, 5, 1, 4, 2]
+    lse, mx, best, nl, nb, ns = oracle.score_order(table, K, order, round_f32=False)
+    pred = 0
+    for v in order:
+        vals = []
+        for j in range(0, K + 1):
+            for c in itertools.combinations([m for m in range(6) if (pred >> m) & 1], j):
+                mask = sum(1 << m for m in c)
+                vals.append((oracle.local_score(data, arities, v, mask), mask))
+        vals.sort(key=lambda t: (-t[0], t[1]))
+        assert best[v] == vals[0][1]
+        assert nb[v] == pytest.approx(vals[0][0], abs=1e-12)
+        assert ns[v] == (vals[1][0] if len(vals) > 1 else -np.inf)
+        pred |= 1 << v
+    assert lse == pytest.approx(nl.sum(), abs=1e-9)
+
+
+def test_empty_data_closed_form():
+    # N = 0, no prior, gamma = 1: every local score is 0, LSE_i = ln S(p, K) at position p,
+    # the best graph is empty (tie rule: smallest mask).
+    for n, K, want in [(8, 3, 18.0215825), (12, 4, None)]:
+        data = np.zeros((0, n), dtype=np.int8)
+        ar = [2] * n
+        table = oracle.build_table(data, ar, K)
+        order = np.random.default_rng(n).permutation(n)
+        lse, mx, best, *_ = oracle.score_order(table, K, order)
+        closed = sum(math.log(oracle.num_sets(p, K)) for p in range(n))
+        assert lse == pytest.approx(closed, rel=1e-13)
+        if want is not None:
+            assert lse == pytest.approx(want, abs=5e-8)
+        assert mx == 0.0 and all(int(b) == 0 for b in best)
+    # with a structure penalty gamma: LSE_i = ln sum_j C(p, j) gamma^j
+    n, K, lg = 7, 2, -0.4
+    data = np.zeros((0, n), dtype=np.int8)
+    table = oracle.build_table(data, [3] * n, K, log_gamma=lg)
+    lse, mx, best, *_ = oracle.score_order(table, K, list(range(n)), round_f32=False)
+    closed = sum(math.log(sum(math.comb(p, j) * math.exp(lg * j) for j in range(K + 1))) for p in range(n))
+    assert lse == pytest.approx(closed, rel=1e-13)
+
+
+def test_K0_scores_do_not_depend_on_order():
+    arities = [2, 3, 4, 2, 3]
+    data = tiny_data(5, 50, arities, seed=4)
+    table = oracle.build_table(data, arities, 0)
+    vals = {oracle.score_order(table, 0, o)[0] for o in itertools.permutations(range(5))}
+    assert max(vals) - min(vals) < 1e-9
+
+
+def test_label_permutation_equivariance():
+    net, prior = datagen.make(datagen.Workload("t", 7, 120, (2, 3, 4), 3, 3, 33, 34))
+    K = 3
+    perm = np.random.default_rng(1).permutation(7)           # new label of old node v is perm[v]
+    inv = np.argsort(perm)
+    data2 = net.data[:, inv]
+    ar2 = net.arities[inv]
+    prior2 = prior[np.ix_(inv, inv)]
+    t1 = oracle.build_table(net.data, net.arities, K, prior=prior)
+    t2 = oracle.build_table(data2, ar2, K, prior=prior2)
+    order = np.array([3, 1, 6, 0, 2, 5, 4])
+    l1, m1, b1, *_ = oracle.score_order(t1, K, order, round_f32=False)
+    l2, m2, b2, *_ = oracle.score_order(t2, K, perm[order], round_f32=False)
+    assert l1 == pytest.approx(l2, rel=1e-12) and m1 == pytest.approx(m2, rel=1e-12)
+    for v in range(7):
+        mapped = sum(1 << int(perm[m]) for m in range(7) if (int(b1[v]) >> m) & 1)
+        assert int(b2[perm[v]]) == mapped
+
+
+# ---------------------------------------------------------------- random numbers
+
+def test_rng_pair_and_shuffle_are_uniform():
+    n = 5
+    counts = {}
+    T = 40000
+    for t in range(1, T + 1):
+        a, b = oracle.swap_pair(77, 3, n, t)
+        assert a != b and 0 <= a < n and 0 <= b < n
+        key = (min(a, b), max(a, b))
+        counts[key] = counts.get(key, 0) + 1
+    assert len(counts) == 10
+    exp = T / 10
+    chi2 = sum((c - exp) ** 2 / exp for c in counts.values())
+    assert chi2 < 30          # 9 dof, p ~ 4e-4
+    perms = {}
+    for c in range(6000):
+        o = tuple(oracle.initial_order(5, c, 3))
+        assert sorted(o) == [0, 1, 2]
+        perms[o] = perms.get(o, 0) + 1
+    assert len(perms) == 6
+    chi2 = sum((v - 1000) ** 2 / 1000 for v in perms.values())
+    assert chi2 < 25          # 5 dof
+    us = [oracle.accept_uniform(9, 1, t) for t in range(20000)]
+    assert 0 < min(us) and max(us) < 1
+    assert abs(np.mean(us) - 0.5) < 0.01
+
+
+# ---------------------------------------------------------------- Metropolis-Hastings
+
+@pytest.mark.parametrize("target", [0, 1])
+def test_mh_chain_is_stationary_at_exact_order_posterior(target):
+    n, K = 4, 3
+    arities = [2, 2, 3, 2]
+    data = tiny_data(n, 12, arities, seed=12)
+    table = oracle.build_table(data, arities, K)
+    orders = list(itertools.permutations(range(n)))
+    sc = np.array([oracle.score_order(table, K, o, round_f32=False)[target] for o in orders])
+    post = np.exp(sc - sc.max())
+    post /= post.sum()
+    iters = 200000
+    res = oracle.run_chain(table, K, seed=2024, chain=0, iters=iters, target=target, round_f32=False)
+    # replay the trajectory from the proposals and acceptance flags
+    cur = list(oracle.initial_order(2024, 0, n))
+    freq = np.zeros(len(orders))
+    idx = {o: k for k, o in enumerate(orders)}
+    burn = 2000
+    for t in range(1, iters + 1):
+        if res["acc"][t - 1]:
+            a, b = oracle.swap_pair(2024, 0, n, t)
+            cur[a], cur[b] = cur[b], cur[a]
+        if t > burn:
+            freq[idx[tuple(cur)]] += 1
+    assert tuple(cur) == tuple(res["order"])
+    freq /= freq.sum()
+    tv = 0.5 * np.abs(freq - post).sum()
+    assert tv < 0.03, tv
+
+
+def test_chain_best_graph_record_is_max_over_accepted_orders():
+    n, K = 6, 3
+    arities = [2, 3, 2, 2, 3, 2]
+    data = tiny_data(n, 100, arities, seed=8)
+    table = oracle.build_table(data, arities, K)
+    seed, chain, iters = 5, 2, 300
+    res = oracle.run_chain(table, K, seed, chain, iters, target=0)
+    cur = list(oracle.initial_order(seed, chain, n))
+    l, m, g, *_ = oracle.score_order(table, K, cur)
+    best, bg = m, g
+    assert res["trace"][0] == pytest.approx(l)
+    for t in range(1, iters + 1):
+        a, b = oracle.swap_pair(seed, chain, n, t)
+        prop = list(cur)
+        prop[a], prop[b] = prop[b], prop[a]
+        pl, pm, pg, *_ = oracle.score_order(table, K, prop)
+        u = oracle.accept_uniform(seed, chain, t)
+        ok = math.log(u) < pl - l
+        assert bool(res["acc"][t - 1]) == ok
+        if ok:
+            cur, l = prop, pl
+            if pm > best:
+                best, bg = pm, pg
+        assert res["trace"][t] == pytest.approx(l)
+    assert res["best_score"] == best
+    assert [int(v) for v in res["best_graph"]] == [int(v) for v in bg]
+    assert res["accepted"] == int(res["acc"].sum())
