@@ -1,0 +1,167 @@
+/*
+ * bnos — order-space MCMC Bayesian-network structure learning on MI355X.
+ *
+ * C ABI of libbnos.so.  All scores are natural logarithms.
+ *
+ * The method (Wang, Zhang, Qian, Yuan, "A Novel Learning Algorithm for
+ * Bayesian Network and Its Efficient Implementation on GPU"):
+ *   - data are complete samples of discrete variables (Sec. II);
+ *   - the local score of node i with parent set pi is the Bayesian-Dirichlet
+ *     marginal likelihood with structure penalty gamma^|pi| (Eq. (3), in log
+ *     form Eq. (4)), here with the BDeu parameters a_ijk = ess/(q_i r_i),
+ *     a_ik = ess/q_i, plus one pairwise-prior term per present edge
+ *     (Sec. IV, Eq. (7)-(9)) given by the cubic of Eq. (10);
+ *   - parent sets have at most K members (the size limit s of Sec. II/III.B);
+ *   - an order is scored by filtering every node's candidate parent sets to
+ *     those inside the node's predecessor set (Sec. III.B, Alg. 1), taking the
+ *     argmax (the greedy best graph, Eq. (6)) and the log-sum-exp (the
+ *     sum-over-consistent-graphs order score that Sec. III.B contrasts with
+ *     Eq. (6)) in one pass;
+ *   - orders are sampled by Metropolis-Hastings with two-position swaps,
+ *     keeping the best graph seen (Sec. III.C).
+ *
+ * Conventions for every call:
+ *   - Return value: BNOS_OK (0) or a negative status; bnos_last_error() then
+ *     gives a message (thread-local, valid until the next call on the thread).
+ *   - Arguments are validated before any device work; on a validation error
+ *     nothing is written.
+ *   - Node ids are 0..n-1 with n <= 64; a parent set is a uint64 bit mask of
+ *     node ids.  An order is int32[n] mapping position -> node id.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Handles are not thread-safe; distinct handles are independent.
+ */
+#ifndef BNOS_H
+#define BNOS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bnos_status;
+#define BNOS_OK        0
+#define BNOS_E_INVALID (-1)   /* NULL pointer, non-permutation order, state >= arity, ess <= 0, NaN prior */
+#define BNOS_E_RANGE   (-2)   /* n outside [1,64], K outside [0, min(n-1, 6)], arity outside [1,255],
+                                 q_i * r_i above 65536, N above 2^31 - 1, B outside [1, 2^20] */
+#define BNOS_E_NOMEM   (-3)   /* host or device allocation failed */
+#define BNOS_E_DEVICE  (-4)   /* a HIP runtime call failed; the message names it */
+#define BNOS_E_STATE   (-5)   /* handle is NULL or already freed */
+
+const char *bnos_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t bnos_version(void);
+
+typedef struct bnos_table_s *bnos_table;
+
+typedef struct {
+    double log_gamma;      /* ln(gamma), the per-parent structure penalty of Eq. (3); default 0 */
+    int32_t prior_mode;    /* 0: prior entries are weights w in [-1,1], R = (1 + w)/2;
+                              1: prior entries are the paper's R in [0,1] (Sec. IV).
+                              Either way the added term is ln(10) * 100 * (R - 0.5)^3. */
+    int32_t reserved[7];   /* must be zero */
+} bnos_build_opts;         /* all-zero = defaults */
+
+/*
+ * Build the local-score table of one dataset on the device (Sec. III.A:
+ * every (node, parent set) scored once, before sampling).
+ *   data       host int8 [N][n], row-major, data[t*n + v] in [0, arities[v]).
+ *   N          number of samples, 0 <= N <= 2^31 - 1 (N = 0 is allowed).
+ *   n          number of nodes, 1..64.
+ *   arities    host int32 [n], each 1..255.
+ *   K          max parents, 0..min(n-1, 6).
+ *   ess        BDeu equivalent sample size, > 0 and finite.
+ *   prior      host float [n][n] or NULL; entry [i*n + m] is the confidence in
+ *              the edge m -> i (row = child, column = parent); the diagonal is
+ *              ignored; see bnos_build_opts.prior_mode.
+ *   opts       NULL for defaults.
+ *   stream     stream for the build kernels; the call returns after the build
+ *              has completed on it.
+ *   out        receives the handle; free with bnos_table_free.
+ * The library copies what it needs and keeps no caller pointer.
+ * Table layout (device): for node i, entries e = 0..S-1 with
+ * S = sum_{j<=K} C(n-1, j) hold (uint64 parent mask, float score); the
+ * entries are the parent sets of size <= K over the other n-1 nodes, listed
+ * in ascending order of their mask with node i's bit removed.
+ */
+bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int32_t n,
+                                   const int32_t *arities, int32_t K, double ess,
+                                   const float *prior, const bnos_build_opts *opts,
+                                   void *stream, bnos_table *out);
+
+/* Frees the table's device memory (synchronises the device first).  NULL is a no-op. */
+void bnos_table_free(bnos_table t);
+
+/*
+ * Shape of a table: n, K, S = entries per node (before padding), and the
+ * device bytes the table holds.  Any output pointer may be NULL.
+ */
+bnos_status bnos_table_info(bnos_table t, int32_t *n, int32_t *K, int64_t *entries_per_node,
+                            int64_t *device_bytes);
+
+/*
+ * Copy node `node`'s entries to host arrays masks[S], scores[S] (S from
+ * bnos_table_info; cap = capacity of both arrays in entries, must be >= S).
+ * Entry order as described at bnos_build_score_table.  Synchronous.
+ */
+bnos_status bnos_table_export(bnos_table t, int32_t node, uint64_t *masks, float *scores,
+                              int64_t cap);
+
+/*
+ * Contingency counts N_ijk on the device for Q queries (node[q], parent
+ * mask[q]), with the same counting kernel the table build uses.
+ *   nodes, masks   host arrays [Q]; masks must not contain the query's node
+ *                  and hold at most K members.
+ *   counts         host uint32 array with cap entries; query q's cells start
+ *                  at offset sum_{q'<q} cells(q'), cells = q_i * r_i.
+ * Cell layout: the parent ids ascending m1 < ... < md give the configuration
+ * k = ((x_m1 * r_m2 + x_m2) * r_m3 + ...), lowest id most significant; the
+ * cell of (k, child state j) is k * r_i + j.  Synchronous.
+ */
+bnos_status bnos_counts(bnos_table t, int32_t Q, const int32_t *nodes, const uint64_t *masks,
+                        uint32_t *counts, int64_t cap);
+
+/*
+ * Score B orders in one pass over the table (Alg. 1 scoring loop; Eq. (6)).
+ * All arrays are DEVICE pointers; the call is asynchronous on `stream`, and
+ * reads its inputs until the stream reaches it.
+ *   orders       int32 [B][n], position -> node id.
+ *   lse          double [B]: sum_i ln sum_{pi consistent} exp s(i,pi).
+ *   maxs         double [B]: sum_i max_{pi consistent} s(i,pi)  (Eq. (6)).
+ *   best         uint64 [B][n]: greedy best parent set of each node (by node
+ *                id); the argmax takes the larger FP32 score, on equal scores
+ *                the smaller mask.
+ *   node_lse     double [B][n] or NULL: per-node log-sum-exp.
+ *   node_second  float [B][n] or NULL: best score among the node's other
+ *                consistent sets (-inf if the empty set is the only one).
+ * An order that is not a permutation of 0..n-1 yields lse = maxs = NaN and
+ * best = 0 for that order; other orders are unaffected.
+ */
+bnos_status bnos_score_orders(bnos_table t, const int32_t *orders, int32_t B, double *lse,
+                              double *maxs, uint64_t *best, double *node_lse,
+                              float *node_second, void *stream);
+
+/*
+ * Host-pointer convenience for one order; synchronous on the null stream.
+ * order int32[n]; best_parents uint64[n] (may be NULL).  A non-permutation
+ * order is rejected with BNOS_E_INVALID.
+ */
+bnos_status bnos_score_order(bnos_table t, const int32_t *order, double *lse, double *maxs,
+                             uint64_t *best_parents);
+
+/*
+ * Kernel timing for measurement: while enabled, every order-scoring launch
+ * of this table is bracketed by HIP events recorded on the launch stream.
+ * bnos_table_timing_read waits for the recorded events and returns the sum of
+ * the scoring kernels' durations (ms) and the number of launches since the
+ * last enable, then keeps counting.
+ */
+bnos_status bnos_table_timing(bnos_table t, int32_t enable);
+bnos_status bnos_table_timing_read(bnos_table t, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BNOS_H */

@@ -1,0 +1,192 @@
+"""Thin ctypes binding of ``libbnos.so`` (C ABI in ``include/bnos.h``).
+
+Argument marshalling only: every step of table build and order scoring runs
+in the library's HIP kernels.  Device buffers and streams come from PyTorch
+(``tensor.data_ptr()``, ``torch.cuda.current_stream().cuda_stream``).
+Importing this module loads the library and raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbnos.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library first "
+        "(python -c 'import __graft_entry__ as g; g.build()')")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_STATE = 0, -1, -2, -3, -4, -5
+
+P = ctypes.c_void_p
+i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("log_gamma", ctypes.c_double), ("prior_mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+_SIGS = {
+    "bnos_last_error": (ctypes.c_char_p, []),
+    "bnos_version": (i32, []),
+    "bnos_build_score_table": (i32, [P, i64, i32, P, i32, f64, P, P, P, P]),
+    "bnos_table_free": (None, [P]),
+    "bnos_table_info": (i32, [P, P, P, P, P]),
+    "bnos_table_export": (i32, [P, i32, P, P, i64]),
+    "bnos_counts": (i32, [P, i32, P, P, P, i64]),
+    "bnos_score_orders": (i32, [P, P, i32, P, P, P, P, P, P]),
+    "bnos_score_order": (i32, [P, P, P, P, P]),
+    "bnos_table_timing": (i32, [P, i32]),
+    "bnos_table_timing_read": (i32, [P, P, P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class BnosError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"bnos status {status}: {msg}")
+        self.status = status
+
+
+def _check(status: int):
+    if status != OK:
+        raise BnosError(status, _lib.bnos_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(P)
+
+
+def _dptr(t) -> Optional[int]:
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Table:
+    """A device-resident local-score table of one dataset."""
+
+    def __init__(self, handle: int, n: int, K: int):
+        self._h = ctypes.c_void_p(handle)
+        self.n = n
+        self.K = K
+
+    # -- lifetime
+    def free(self):
+        if self._h:
+            _lib.bnos_table_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- info / export
+    def info(self):
+        n, K, S, b = i32(), i32(), i64(), i64()
+        _check(_lib.bnos_table_info(self._h, ctypes.byref(n), ctypes.byref(K), ctypes.byref(S),
+                                    ctypes.byref(b)))
+        return dict(n=n.value, K=K.value, entries_per_node=S.value, device_bytes=b.value)
+
+    def export(self, node: int):
+        S = self.info()["entries_per_node"]
+        masks = np.zeros(S, dtype=np.uint64)
+        scores = np.zeros(S, dtype=np.float32)
+        _check(_lib.bnos_table_export(self._h, node, _ptr(masks), _ptr(scores), S))
+        return masks, scores
+
+    def counts(self, nodes, masks, arities):
+        nodes = np.ascontiguousarray(nodes, dtype=np.int32)
+        masks = np.ascontiguousarray(masks, dtype=np.uint64)
+        sizes = []
+        for v, m in zip(nodes, masks):
+            c = int(arities[int(v)])
+            for b in range(self.n):
+                if (int(m) >> b) & 1:
+                    c *= int(arities[b])
+            sizes.append(c)
+        out = np.zeros(max(sum(sizes), 1), dtype=np.uint32)
+        _check(_lib.bnos_counts(self._h, len(nodes), _ptr(nodes), _ptr(masks), _ptr(out), out.size))
+        res = []
+        off = 0
+        for c in sizes:
+            res.append(out[off:off + c].copy())
+            off += c
+        return res
+
+    # -- scoring
+    def score_orders(self, orders, lse, maxs, best, node_lse=None, node_second=None, stream=None):
+        """Asynchronous batched scoring on device tensors (see bnos_score_orders)."""
+        B = int(orders.shape[0])
+        _check(_lib.bnos_score_orders(self._h, _dptr(orders), B, _dptr(lse), _dptr(maxs), _dptr(best),
+                                      _dptr(node_lse), _dptr(node_second), _stream(stream)))
+
+    def score_order(self, order):
+        """Synchronous host-side scoring of one order -> (lse, max, best_parents[n])."""
+        order = np.ascontiguousarray(order, dtype=np.int32)
+        lse, mx = f64(), f64()
+        best = np.zeros(self.n, dtype=np.uint64)
+        _check(_lib.bnos_score_order(self._h, _ptr(order), ctypes.byref(lse), ctypes.byref(mx), _ptr(best)))
+        return lse.value, mx.value, best
+
+    # -- timing
+    def timing(self, enable: bool):
+        _check(_lib.bnos_table_timing(self._h, int(enable)))
+
+    def timing_read(self):
+        ms, cnt = f64(), i64()
+        _check(_lib.bnos_table_timing_read(self._h, ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
+
+
+def build_score_table(data, arities, K: int, ess: float = 1.0, prior=None, prior_mode: int = 0,
+                      log_gamma: float = 0.0, stream=None) -> Table:
+    """Build the local-score table (host inputs; see bnos_build_score_table)."""
+    data = np.ascontiguousarray(data, dtype=np.int8)
+    if data.ndim != 2:
+        raise ValueError("data must be [N][n]")
+    N, n = data.shape
+    ar = np.ascontiguousarray(arities, dtype=np.int32)
+    pr = None if prior is None else np.ascontiguousarray(prior, dtype=np.float32)
+    opts = BuildOpts()
+    opts.log_gamma = log_gamma
+    opts.prior_mode = prior_mode
+    h = ctypes.c_void_p()
+    st = ctypes.c_void_p(0) if stream is None else _stream(stream)
+    _check(_lib.bnos_build_score_table(_ptr(data) if N else None, N, n, _ptr(ar), K, ess,
+                                       None if pr is None else _ptr(pr), ctypes.byref(opts), st,
+                                       ctypes.byref(h)))
+    return Table(h.value, n, K)
+
+
+def version() -> int:
+    return int(_lib.bnos_version())
+
+
+def exported_symbols():
+    return list(_SIGS)

@@ -1,0 +1,80 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "bnos.h"
+
+namespace bnos {
+
+// Largest contingency table (q_i * r_i cells) a build supports; the counting
+// kernel keeps one such histogram per wavefront in LDS.
+constexpr int kMaxCells = 16384;
+constexpr int kMaxK = 6;
+
+// Order-scoring geometry: 256 threads, 4 entries per thread per step, so a
+// block consumes 1024 entries per step; a chunk is 1..8 steps.
+constexpr int kScoreThreads = 256;
+constexpr int kEntriesPerStep = 1024;
+constexpr int kMaxStepsPerChunk = 8;
+
+struct TableT {
+    uint32_t magic = 0;
+    int n = 0, K = 0;
+    int64_t N = 0, N_pad = 0;
+    int64_t S = 0, S_pad = 0;       // entries per node before / after padding
+    int chunk_entries = 0;          // entries per scoring block
+    int chunks = 0;                 // scoring blocks per node = S_pad / chunk_entries
+    int max_cells = 0;
+    double ess = 1.0, log_gamma = 0.0;
+    int device = 0;
+
+    uint8_t *d_data = nullptr;      // column-major [n][N_pad]
+    int32_t *d_ar = nullptr;        // [n]
+    double *d_prior = nullptr;      // [n][n] prior term in nats (0 where none)
+    int64_t *d_nsets = nullptr;     // [64][8] number of masks over `bit` bits with <= k members
+    uint64_t *d_masks = nullptr;    // [n][S_pad]
+    float *d_scores = nullptr;      // [n][S_pad]
+
+    // order-scoring workspace: per (order, node, chunk) partial reductions
+    void *d_part = nullptr;
+    int64_t part_orders = 0;        // capacity in orders
+
+    // kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_start, ev_stop;
+    size_t ev_used = 0;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+
+    int64_t device_bytes() const;
+};
+
+constexpr uint32_t kMagic = 0xB0A5C0DEu;
+
+void set_error(const std::string &msg);
+bool handle_live(const TableT *t);
+void register_handle(TableT *t);
+void unregister_handle(TableT *t);
+
+// Partial-reduction record written by each scoring block (one per order).
+struct Partial {
+    float m, s;          // running max and sum of exp(x - m) over consistent entries
+    float best, second;  // top-1 score and best score among the others
+    uint64_t bmask;      // mask of the top-1 entry
+};
+
+}  // namespace bnos
+
+#define BNOS_HIP(call)                                                               \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            bnos::set_error(std::string(#call) + ": " + hipGetErrorString(e_));     \
+            return BNOS_E_DEVICE;                                                    \
+        }                                                                            \
+    } while (0)

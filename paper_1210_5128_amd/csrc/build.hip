@@ -1,0 +1,560 @@
+// Local-score table build on the device: data ingest, parent-set
+// enumeration, contingency counting in LDS and the BDeu + pairwise-prior
+// score (Sec. II Eq. (3); Sec. III.A Eq. (4); Sec. IV Eq. (9)-(10)).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "bnos_internal.h"
+
+namespace bnos {
+
+// ------------------------------------------------------------------ errors, handles
+
+static thread_local std::string g_err;
+static std::mutex g_handles_mu;
+static std::set<const TableT *> g_handles;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+bool handle_live(const TableT *t)
+{
+    std::lock_guard<std::mutex> lk(g_handles_mu);
+    return t && g_handles.count(t) && t->magic == kMagic;
+}
+
+void register_handle(TableT *t)
+{
+    std::lock_guard<std::mutex> lk(g_handles_mu);
+    g_handles.insert(t);
+}
+
+void unregister_handle(TableT *t)
+{
+    std::lock_guard<std::mutex> lk(g_handles_mu);
+    g_handles.erase(t);
+}
+
+int64_t TableT::device_bytes() const
+{
+    return (int64_t)n * S_pad * (int64_t)(sizeof(uint64_t) + sizeof(float)) + (int64_t)n * N_pad +
+           (int64_t)n * (int64_t)(sizeof(int32_t) + n * sizeof(double)) + 64 * 8 * 8 +
+           part_orders * (int64_t)n * chunks * (int64_t)sizeof(Partial);
+}
+
+// ------------------------------------------------------------------ device helpers
+
+// Orders LDS traffic of one wavefront between phases (zero / count / read).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Mask over the n-1 candidate slots -> mask over node ids: a zero bit is
+// inserted at position `node` (slot s < node is node s, slot s >= node is s+1).
+__device__ __forceinline__ uint64_t slot_to_node_mask(uint64_t m, int node)
+{
+    uint64_t lo = m & ((1ull << node) - 1ull);
+    uint64_t hi = (node >= 63) ? 0ull : ((m >> node) << (node + 1));
+    return hi | lo;
+}
+
+// The e-th mask, in ascending numeric order, among masks over `bits` bits with
+// at most K set bits.  nsets[b*8 + k] = number of masks over b bits with <= k
+// set bits; the masks whose top bit is clear come first.
+__device__ __forceinline__ uint64_t unrank_ascending(int64_t e, int bits, int K,
+                                                      const int64_t *__restrict__ nsets)
+{
+    uint64_t m = 0;
+    int k = K;
+    for (int b = bits - 1; b >= 0 && k > 0; --b) {
+        int64_t c = nsets[b * 8 + k];
+        if (e >= c) {
+            m |= 1ull << b;
+            e -= c;
+            --k;
+        }
+    }
+    return m;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Parent members of a node mask, ascending, with the cell weights of the
+// counting layout: cell = x_child + r_child * sum_t x_{m_t} * prod_{t'>t} r_{m_t'}.
+struct Members {
+    int id[kMaxK];
+    int w[kMaxK];
+    int cnt;
+    int q;
+};
+
+__device__ __forceinline__ Members decode_members(uint64_t mask, int r_child,
+                                                  const int32_t *__restrict__ ar)
+{
+    Members M;
+    M.cnt = 0;
+    uint64_t m = mask;
+#pragma unroll
+    for (int t = 0; t < kMaxK; ++t) {
+        M.id[t] = 0;
+        M.w[t] = 0;
+        if (m) {
+            int b = __builtin_ctzll(m);
+            m &= m - 1;
+            M.id[t] = b;
+            M.cnt = t + 1;
+        }
+    }
+    int acc = r_child;
+#pragma unroll
+    for (int t = kMaxK - 1; t >= 0; --t) {
+        if (t < M.cnt) {
+            M.w[t] = acc;
+            acc *= ar[M.id[t]];
+        }
+    }
+    M.q = acc / r_child;
+    return M;
+}
+
+// Histogram of the N samples into hist[0 .. q*r) (one wavefront; hist is this
+// wavefront's private LDS region).  Each lane takes 4 consecutive samples per
+// step from 32-bit loads of the column-major data.
+__device__ __forceinline__ void wave_count(const uint8_t *__restrict__ data, int64_t N, int64_t N_pad,
+                                           int child, const Members &M, int cells, uint32_t *hist,
+                                           int lane)
+{
+    for (int c = lane; c < cells; c += 64) hist[c] = 0u;
+    wave_lds_sync();
+    const uint32_t *colc = reinterpret_cast<const uint32_t *>(data + (int64_t)child * N_pad);
+    const uint32_t *colm[kMaxK];
+#pragma unroll
+    for (int t = 0; t < kMaxK; ++t)
+        colm[t] = reinterpret_cast<const uint32_t *>(data + (int64_t)M.id[t] * N_pad);
+    for (int64_t base = (int64_t)lane * 4; base < N; base += 256) {
+        uint32_t xc = colc[base >> 2];
+        uint32_t xm[kMaxK];
+#pragma unroll
+        for (int t = 0; t < kMaxK; ++t) xm[t] = (t < M.cnt) ? colm[t][base >> 2] : 0u;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            int cell = (int)((xc >> (8 * b)) & 0xffu);
+#pragma unroll
+            for (int t = 0; t < kMaxK; ++t) cell += M.w[t] * (int)((xm[t] >> (8 * b)) & 0xffu);
+            if (base + b < N) atomicAdd(&hist[cell], 1u);
+        }
+    }
+    wave_lds_sync();
+}
+
+// ------------------------------------------------------------------ kernels
+
+// Row-major int8 [N][n] -> column-major uint8 [n][N_pad] (padding already zero).
+__global__ void k_ingest(const int8_t *__restrict__ src, int64_t N, int n, int64_t N_pad,
+                         uint8_t *__restrict__ dst)
+{
+    int64_t total = N * n;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        int64_t t = g / n;
+        int v = (int)(g - t * n);
+        dst[(int64_t)v * N_pad + t] = (uint8_t)src[g];
+    }
+}
+
+// Prior term in nats per (child i, parent m): ln(10) * 100 * (R - 0.5)^3 (Eq. (10),
+// a log10 quantity in Eq. (9)); R = (1 + w)/2 in mode 0, R given in mode 1.
+__global__ void k_prior(const float *__restrict__ src, int n, int mode, double *__restrict__ dst)
+{
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n * n) return;
+    int i = g / n, m = g - (g / n) * n;
+    double v = 0.0;
+    if (src && i != m) {
+        double x = (double)src[g];
+        double R = (mode == 0) ? 0.5 * (1.0 + x) : x;
+        double d = R - 0.5;
+        v = 2.302585092994045684 * 100.0 * d * d * d;
+    }
+    dst[g] = v;
+}
+
+// One wavefront per (node, entry): enumerate the entry's parent set, count
+// N_ijk in LDS, reduce the BDeu terms in FP64, add the structure penalty and
+// the prior terms, store (mask, FP32 score).  Padding entries get (~0, -inf),
+// which no predecessor set can contain.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_build(
+    const uint8_t *__restrict__ data, int64_t N, int64_t N_pad, const int32_t *__restrict__ ar,
+    const double *__restrict__ prior, const int64_t *__restrict__ nsets, int n, int K, double ess,
+    double log_gamma, int64_t S, int64_t S_pad, int cells_cap, uint64_t *__restrict__ masks,
+    float *__restrict__ scores)
+{
+    extern __shared__ uint32_t lds_hist[];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    uint32_t *hist = lds_hist + wave * cells_cap;
+    const int64_t total = (int64_t)n * S_pad;
+    for (int64_t g = (int64_t)blockIdx.x * WAVES + wave; g < total; g += (int64_t)gridDim.x * WAVES) {
+        const int node = (int)(g / S_pad);
+        const int64_t e = g - (int64_t)node * S_pad;
+        if (e >= S) {
+            if (lane == 0) {
+                masks[g] = ~0ull;
+                scores[g] = -INFINITY;
+            }
+            continue;
+        }
+        const uint64_t mask = slot_to_node_mask(unrank_ascending(e, n - 1, K, nsets), node);
+        const int r = ar[node];
+        Members M = decode_members(mask, r, ar);
+        const int cells = M.q * r;
+        wave_count(data, N, N_pad, node, M, cells, hist, lane);
+
+        const double a_ijk = ess / (double)cells;
+        const double a_ik = ess / (double)M.q;
+        const double lg_ijk = lgamma(a_ijk);
+        const double lg_ik = lgamma(a_ik);
+        double acc = 0.0;
+        for (int k = lane; k < M.q; k += 64) {
+            uint32_t nik = 0;
+            double part = 0.0;
+            for (int j = 0; j < r; ++j) {
+                uint32_t c = hist[k * r + j];
+                nik += c;
+                if (c) part += lgamma((double)c + a_ijk) - lg_ijk;
+            }
+            if (nik) part += lg_ik - lgamma(a_ik + (double)nik);
+            acc += part;
+        }
+        acc = wave_sum_f64(acc);
+        wave_lds_sync();   // every lane has read hist before the next entry clears it
+        if (lane == 0) {
+            double s = acc + (double)M.cnt * log_gamma;
+#pragma unroll
+            for (int t = 0; t < kMaxK; ++t)
+                if (t < M.cnt) s += prior[(int64_t)node * n + M.id[t]];
+            masks[g] = mask;
+            scores[g] = (float)s;   // round to nearest even
+        }
+    }
+}
+
+// Counts for explicit (node, parent mask) queries, with the build's counting code.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_counts(
+    const uint8_t *__restrict__ data, int64_t N, int64_t N_pad, const int32_t *__restrict__ ar,
+    int Q, const int32_t *__restrict__ qnode, const uint64_t *__restrict__ qmask,
+    const int64_t *__restrict__ qoff, int cells_cap, uint32_t *__restrict__ out)
+{
+    extern __shared__ uint32_t lds_hist[];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    uint32_t *hist = lds_hist + wave * cells_cap;
+    for (int qi = blockIdx.x * WAVES + wave; qi < Q; qi += gridDim.x * WAVES) {
+        const int node = qnode[qi];
+        const int r = ar[node];
+        Members M = decode_members(qmask[qi], r, ar);
+        const int cells = M.q * r;
+        wave_count(data, N, N_pad, node, M, cells, hist, lane);
+        for (int c = lane; c < cells; c += 64) out[qoff[qi] + c] = hist[c];
+        wave_lds_sync();
+    }
+}
+
+// ------------------------------------------------------------------ host side
+
+static int64_t binom_host(int a, int b)
+{
+    if (b < 0 || a < 0 || b > a) return 0;
+    int64_t r = 1;
+    for (int t = 1; t <= b; ++t) r = r * (a - b + t) / t;
+    return r;
+}
+
+static int64_t sets_upto(int m, int K)
+{
+    int64_t s = 0;
+    for (int j = 0; j <= K && j <= m; ++j) s += binom_host(m, j);
+    return s;
+}
+
+static int waves_for_cells(int cells_cap) { return cells_cap <= 4096 ? 4 : 1; }
+
+template <int W>
+static hipError_t launch_build(TableT *t, hipStream_t st, int cells_cap)
+{
+    int64_t total = (int64_t)t->n * t->S_pad;
+    int64_t blocks = (total + W - 1) / W;
+    if (blocks > (1 << 22)) blocks = 1 << 22;
+    size_t lds = (size_t)W * cells_cap * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_build<W>, dim3((unsigned)blocks), dim3(W * 64), lds, st, t->d_data, t->N,
+                       t->N_pad, t->d_ar, t->d_prior, t->d_nsets, t->n, t->K, t->ess, t->log_gamma,
+                       t->S, t->S_pad, cells_cap, t->d_masks, t->d_scores);
+    return hipGetLastError();
+}
+
+static int cells_cap_for(int max_cells)
+{
+    int c = 64;
+    while (c < max_cells) c <<= 1;
+    return c;
+}
+
+static void free_device(TableT *t)
+{
+    hipFree(t->d_data);
+    hipFree(t->d_ar);
+    hipFree(t->d_prior);
+    hipFree(t->d_nsets);
+    hipFree(t->d_masks);
+    hipFree(t->d_scores);
+    hipFree(t->d_part);
+    for (auto e : t->ev_start) hipEventDestroy(e);
+    for (auto e : t->ev_stop) hipEventDestroy(e);
+}
+
+}  // namespace bnos
+
+using namespace bnos;
+
+extern "C" const char *bnos_last_error(void) { return g_err.c_str(); }
+
+extern "C" int32_t bnos_version(void) { return 100; }
+
+extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int32_t n,
+                                              const int32_t *arities, int32_t K, double ess,
+                                              const float *prior, const bnos_build_opts *opts,
+                                              void *stream, bnos_table *out)
+{
+    if (!out) { set_error("out is NULL"); return BNOS_E_INVALID; }
+    if (!arities) { set_error("arities is NULL"); return BNOS_E_INVALID; }
+    if (N < 0 || N > 2147483647LL) { set_error("N outside [0, 2^31-1]"); return BNOS_E_RANGE; }
+    if (N > 0 && !data) { set_error("data is NULL"); return BNOS_E_INVALID; }
+    if (n < 1 || n > 64) { set_error("n outside [1, 64]"); return BNOS_E_RANGE; }
+    if (K < 0 || K > n - 1 || K > kMaxK) { set_error("K outside [0, min(n-1, 6)]"); return BNOS_E_RANGE; }
+    if (!(ess > 0.0) || !std::isfinite(ess)) { set_error("ess must be finite and > 0"); return BNOS_E_INVALID; }
+    bnos_build_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    for (int r = 0; r < 7; ++r)
+        if (o.reserved[r] != 0) { set_error("opts.reserved must be zero"); return BNOS_E_INVALID; }
+    if (o.prior_mode != 0 && o.prior_mode != 1) { set_error("prior_mode must be 0 or 1"); return BNOS_E_INVALID; }
+    if (!std::isfinite(o.log_gamma)) { set_error("log_gamma must be finite"); return BNOS_E_INVALID; }
+    for (int v = 0; v < n; ++v)
+        if (arities[v] < 1 || arities[v] > 255) { set_error("arity outside [1, 255]"); return BNOS_E_RANGE; }
+    for (int64_t t = 0; t < N; ++t)
+        for (int v = 0; v < n; ++v) {
+            int x = data[t * n + v];
+            if (x < 0 || x >= arities[v]) {
+                char buf[128];
+                std::snprintf(buf, sizeof buf, "state %d of node %d in sample %lld is outside [0, %d)", x, v,
+                              (long long)t, arities[v]);
+                set_error(buf);
+                return BNOS_E_INVALID;
+            }
+        }
+    if (prior) {
+        for (int i = 0; i < n; ++i)
+            for (int m = 0; m < n; ++m) {
+                if (i == m) continue;
+                float x = prior[i * n + m];
+                bool ok = std::isfinite(x) && (o.prior_mode == 0 ? (x >= -1.f && x <= 1.f) : (x >= 0.f && x <= 1.f));
+                if (!ok) { set_error("prior entry NaN or out of range"); return BNOS_E_INVALID; }
+            }
+    }
+    // Largest contingency table: r_i times the K largest arities among the other nodes.
+    int max_cells = 1;
+    for (int i = 0; i < n; ++i) {
+        std::vector<int> o2;
+        for (int m = 0; m < n; ++m) if (m != i) o2.push_back(arities[m]);
+        std::sort(o2.rbegin(), o2.rend());
+        int64_t c = arities[i];
+        for (int j = 0; j < K && j < (int)o2.size(); ++j) c *= o2[j];
+        if (c > kMaxCells) { set_error("q_i * r_i above 16384"); return BNOS_E_RANGE; }
+        if (c > max_cells) max_cells = (int)c;
+    }
+
+    TableT *t = new (std::nothrow) TableT();
+    if (!t) { set_error("host allocation failed"); return BNOS_E_NOMEM; }
+    t->n = n;
+    t->K = K;
+    t->N = N;
+    t->N_pad = ((N + 255) / 256) * 256;
+    if (t->N_pad == 0) t->N_pad = 256;
+    t->S = sets_upto(n - 1, K);
+    int64_t steps = (t->S + kEntriesPerStep - 1) / kEntriesPerStep;
+    if (steps > kMaxStepsPerChunk) steps = kMaxStepsPerChunk;
+    t->chunk_entries = (int)(steps * kEntriesPerStep);
+    t->S_pad = ((t->S + t->chunk_entries - 1) / t->chunk_entries) * t->chunk_entries;
+    t->chunks = (int)(t->S_pad / t->chunk_entries);
+    t->max_cells = max_cells;
+    t->ess = ess;
+    t->log_gamma = o.log_gamma;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+
+    auto fail = [&](bnos_status s) {
+        free_device(t);
+        delete t;
+        return s;
+    };
+    hipError_t e;
+    if ((e = hipGetDevice(&t->device)) != hipSuccess) { set_error(std::string("hipGetDevice: ") + hipGetErrorString(e)); return fail(BNOS_E_DEVICE); }
+#define ALLOC(ptr, bytes)                                                               \
+    if ((e = hipMalloc((void **)&(ptr), (bytes))) != hipSuccess) {                      \
+        set_error(std::string("hipMalloc " #ptr ": ") + hipGetErrorString(e));          \
+        return fail(e == hipErrorOutOfMemory ? BNOS_E_NOMEM : BNOS_E_DEVICE);           \
+    }
+    ALLOC(t->d_data, (size_t)n * t->N_pad);
+    ALLOC(t->d_ar, sizeof(int32_t) * n);
+    ALLOC(t->d_prior, sizeof(double) * n * n);
+    ALLOC(t->d_nsets, sizeof(int64_t) * 64 * 8);
+    ALLOC(t->d_masks, sizeof(uint64_t) * (size_t)n * t->S_pad);
+    ALLOC(t->d_scores, sizeof(float) * (size_t)n * t->S_pad);
+#undef ALLOC
+    int8_t *d_rows = nullptr;
+    float *d_prior_in = nullptr;
+    std::vector<int64_t> nsets(64 * 8, 0);
+    for (int b = 0; b < 64; ++b)
+        for (int k = 0; k < 8; ++k) nsets[b * 8 + k] = sets_upto(b, k);
+#define CK(call)                                                                         \
+    if ((e = (call)) != hipSuccess) {                                                     \
+        set_error(std::string(#call) + ": " + hipGetErrorString(e));                      \
+        hipFree(d_rows); hipFree(d_prior_in);                                             \
+        return fail(BNOS_E_DEVICE);                                                       \
+    }
+    if (N > 0) CK(hipMalloc((void **)&d_rows, (size_t)N * n));
+    if (prior) CK(hipMalloc((void **)&d_prior_in, sizeof(float) * n * n));
+    CK(hipMemsetAsync(t->d_data, 0, (size_t)n * t->N_pad, st));
+    if (N > 0) CK(hipMemcpyAsync(d_rows, data, (size_t)N * n, hipMemcpyHostToDevice, st));
+    if (prior) CK(hipMemcpyAsync(d_prior_in, prior, sizeof(float) * n * n, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(t->d_ar, arities, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(t->d_nsets, nsets.data(), sizeof(int64_t) * 64 * 8, hipMemcpyHostToDevice, st));
+    if (N > 0) {
+        int64_t tot = N * n;
+        int blocks = (int)std::min<int64_t>((tot + 255) / 256, 1 << 16);
+        hipLaunchKernelGGL(k_ingest, dim3(blocks), dim3(256), 0, st, d_rows, N, n, t->N_pad, t->d_data);
+        CK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_prior, dim3((n * n + 255) / 256), dim3(256), 0, st, d_prior_in, n, o.prior_mode,
+                       t->d_prior);
+    CK(hipGetLastError());
+    int cap = cells_cap_for(max_cells);
+    if (waves_for_cells(cap) == 4) { CK(launch_build<4>(t, st, cap)); }
+    else { CK(launch_build<1>(t, st, cap)); }
+    CK(hipStreamSynchronize(st));
+    hipFree(d_rows);
+    hipFree(d_prior_in);
+#undef CK
+    t->magic = kMagic;
+    register_handle(t);
+    *out = reinterpret_cast<bnos_table>(t);
+    return BNOS_OK;
+}
+
+extern "C" void bnos_table_free(bnos_table h)
+{
+    TableT *t = reinterpret_cast<TableT *>(h);
+    if (!t || !handle_live(t)) return;
+    unregister_handle(t);
+    hipDeviceSynchronize();
+    t->magic = 0;
+    free_device(t);
+    delete t;
+}
+
+extern "C" bnos_status bnos_table_info(bnos_table h, int32_t *n, int32_t *K, int64_t *S, int64_t *bytes)
+{
+    TableT *t = reinterpret_cast<TableT *>(h);
+    if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
+    if (n) *n = t->n;
+    if (K) *K = t->K;
+    if (S) *S = t->S;
+    if (bytes) *bytes = t->device_bytes();
+    return BNOS_OK;
+}
+
+extern "C" bnos_status bnos_table_export(bnos_table h, int32_t node, uint64_t *masks, float *scores, int64_t cap)
+{
+    TableT *t = reinterpret_cast<TableT *>(h);
+    if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
+    if (!masks || !scores) { set_error("output is NULL"); return BNOS_E_INVALID; }
+    if (node < 0 || node >= t->n) { set_error("node out of range"); return BNOS_E_RANGE; }
+    if (cap < t->S) { set_error("cap below entries per node"); return BNOS_E_RANGE; }
+    BNOS_HIP(hipSetDevice(t->device));
+    BNOS_HIP(hipMemcpy(masks, t->d_masks + (int64_t)node * t->S_pad, sizeof(uint64_t) * t->S, hipMemcpyDeviceToHost));
+    BNOS_HIP(hipMemcpy(scores, t->d_scores + (int64_t)node * t->S_pad, sizeof(float) * t->S, hipMemcpyDeviceToHost));
+    return BNOS_OK;
+}
+
+extern "C" bnos_status bnos_counts(bnos_table h, int32_t Q, const int32_t *nodes, const uint64_t *masks,
+                                   uint32_t *counts, int64_t cap)
+{
+    TableT *t = reinterpret_cast<TableT *>(h);
+    if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
+    if (Q < 0) { set_error("Q < 0"); return BNOS_E_RANGE; }
+    if (Q == 0) return BNOS_OK;
+    if (!nodes || !masks || !counts) { set_error("NULL argument"); return BNOS_E_INVALID; }
+    std::vector<int32_t> ar(t->n);
+    BNOS_HIP(hipSetDevice(t->device));
+    BNOS_HIP(hipMemcpy(ar.data(), t->d_ar, sizeof(int32_t) * t->n, hipMemcpyDeviceToHost));
+    std::vector<int64_t> off(Q);
+    int64_t tot = 0;
+    int maxc = 1;
+    for (int q = 0; q < Q; ++q) {
+        int v = nodes[q];
+        if (v < 0 || v >= t->n) { set_error("query node out of range"); return BNOS_E_RANGE; }
+        uint64_t m = masks[q];
+        if (t->n < 64 && (m >> t->n)) { set_error("query mask names a node >= n"); return BNOS_E_INVALID; }
+        if ((m >> v) & 1ull) { set_error("query mask contains its own node"); return BNOS_E_INVALID; }
+        if (__builtin_popcountll(m) > t->K) { set_error("query mask has more than K members"); return BNOS_E_RANGE; }
+        int64_t c = ar[v];
+        for (int b = 0; b < t->n; ++b) if ((m >> b) & 1ull) c *= ar[b];
+        off[q] = tot;
+        tot += c;
+        if (c > maxc) maxc = (int)c;
+    }
+    if (tot > cap) { set_error("cap below total cells"); return BNOS_E_RANGE; }
+    int32_t *d_nodes = nullptr;
+    uint64_t *d_masks = nullptr;
+    int64_t *d_off = nullptr;
+    uint32_t *d_out = nullptr;
+    hipError_t e = hipSuccess;
+    auto cleanup = [&]() { hipFree(d_nodes); hipFree(d_masks); hipFree(d_off); hipFree(d_out); };
+#define CK(call) if ((e = (call)) != hipSuccess) { set_error(std::string(#call) + ": " + hipGetErrorString(e)); cleanup(); return BNOS_E_DEVICE; }
+    CK(hipMalloc((void **)&d_nodes, sizeof(int32_t) * Q));
+    CK(hipMalloc((void **)&d_masks, sizeof(uint64_t) * Q));
+    CK(hipMalloc((void **)&d_off, sizeof(int64_t) * Q));
+    CK(hipMalloc((void **)&d_out, sizeof(uint32_t) * tot));
+    CK(hipMemcpy(d_nodes, nodes, sizeof(int32_t) * Q, hipMemcpyHostToDevice));
+    CK(hipMemcpy(d_masks, masks, sizeof(uint64_t) * Q, hipMemcpyHostToDevice));
+    CK(hipMemcpy(d_off, off.data(), sizeof(int64_t) * Q, hipMemcpyHostToDevice));
+    int cap_cells = cells_cap_for(maxc);
+    int blocks = (int)std::min<int64_t>((Q + 3) / 4, 1 << 16);
+    if (waves_for_cells(cap_cells) == 4) {
+        hipLaunchKernelGGL(k_counts<4>, dim3(blocks), dim3(256), 4 * cap_cells * sizeof(uint32_t), 0, t->d_data,
+                           t->N, t->N_pad, t->d_ar, Q, d_nodes, d_masks, d_off, cap_cells, d_out);
+    } else {
+        hipLaunchKernelGGL(k_counts<1>, dim3(blocks * 4), dim3(64), cap_cells * sizeof(uint32_t), 0, t->d_data,
+                           t->N, t->N_pad, t->d_ar, Q, d_nodes, d_masks, d_off, cap_cells, d_out);
+    }
+    CK(hipGetLastError());
+    CK(hipMemcpy(counts, d_out, sizeof(uint32_t) * tot, hipMemcpyDeviceToHost));
+#undef CK
+    cleanup();
+    return BNOS_OK;
+}

@@ -1,0 +1,307 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded inputs.
+
+Bars: counts and argmax parent sets bit-exact; stored FP32 scores within
+2 ulp of the oracle's FP64 value; log-scores within 1e-5 relative.  The
+oracle takes its argmax on its own scores rounded to FP32, the precision in
+which the library stores scores and decides the argmax.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_1210_5128_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def bnos():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1210_5128_amd import bnos as b
+    return b
+
+
+def ulp32(x):
+    x = np.abs(np.asarray(x, dtype=np.float64)).astype(np.float32)
+    return np.spacing(x).astype(np.float64)
+
+
+def dev_score(table, orders, want_nodes=True):
+    dev = torch.device("cuda")
+    B, n = orders.shape
+    o = torch.from_numpy(np.ascontiguousarray(orders, dtype=np.int32)).to(dev)
+    lse = torch.empty(B, dtype=torch.float64, device=dev)
+    mx = torch.empty(B, dtype=torch.float64, device=dev)
+    best = torch.empty((B, n), dtype=torch.int64, device=dev)
+    nl = torch.empty((B, n), dtype=torch.float64, device=dev) if want_nodes else None
+    ns = torch.empty((B, n), dtype=torch.float32, device=dev) if want_nodes else None
+    table.score_orders(o, lse, mx, best, nl, ns)
+    torch.cuda.synchronize()
+    out = dict(lse=lse.cpu().numpy(), max=mx.cpu().numpy(),
+               best=best.cpu().numpy().view(np.uint64))
+    if want_nodes:
+        out["node_lse"] = nl.cpu().numpy()
+        out["node_second"] = ns.cpu().numpy()
+    return out
+
+
+def check_orders_against_oracle(got, orc_table, K, orders):
+    ulp_ties = 0
+    for b in range(orders.shape[0]):
+        wl, wm, wb, wnl, wnb, wns = oracle.score_order(orc_table, K, orders[b], round_f32=True)
+        assert abs(got["lse"][b] - wl) <= REL * max(1.0, abs(wl)), (b, got["lse"][b], wl)
+        assert abs(got["max"][b] - wm) <= REL * max(1.0, abs(wm)), (b, got["max"][b], wm)
+        for i in range(orders.shape[1]):
+            if int(got["best"][b, i]) != int(wb[i]):
+                # allowed only when the oracle's FP64 scores of the two picks are within 2 ulp32
+                from oracle import rank
+                a = orc_table[i, rank(orders.shape[1], K, i, int(got["best"][b, i]))]
+                c = orc_table[i, rank(orders.shape[1], K, i, int(wb[i]))]
+                assert abs(a - c) <= 2 * ulp32(c), (b, i, got["best"][b, i], wb[i], a, c)
+                ulp_ties += 1
+        if "node_lse" in got:
+            np.testing.assert_allclose(got["node_lse"][b], wnl, rtol=REL, atol=1e-6)
+            sec = got["node_second"][b].astype(np.float64)
+            fin = np.isfinite(wns)
+            assert np.array_equal(np.isfinite(sec), fin)
+            np.testing.assert_allclose(sec[fin], wns[fin], rtol=0, atol=0)
+            assert math.isclose(got["node_lse"][b].sum(), got["lse"][b], rel_tol=1e-12, abs_tol=1e-9)
+    return ulp_ties
+
+
+# ------------------------------------------------------------------ fixtures per workload
+
+def make_tables(bnos, wname, with_oracle=True):
+    w = datagen.WORKLOADS[wname]
+    net, prior = datagen.make(w)
+    t = bnos.build_score_table(net.data, net.arities, w.K, ess=w.ess, prior=prior)
+    orc = oracle.build_table(net.data, net.arities, w.K, ess=w.ess, prior=prior) if with_oracle else None
+    return w, net, prior, t, orc
+
+
+@pytest.fixture(scope="module")
+def tiny8(bnos):
+    r = make_tables(bnos, "tiny8")
+    yield r
+    r[3].free()
+
+
+@pytest.fixture(scope="module")
+def prior20(bnos):
+    r = make_tables(bnos, "prior20")
+    yield r
+    r[3].free()
+
+
+# ------------------------------------------------------------------ counts
+
+@pytest.mark.parametrize("wname", ["tiny8", "prior20"])
+def test_counts_bit_exact(bnos, wname, request):
+    w, net, prior, t, orc = request.getfixturevalue(wname)
+    rng = np.random.default_rng(3)
+    S = oracle.num_sets(w.n - 1, w.K)
+    nodes, masks = [], []
+    if wname == "tiny8":
+        for i in range(w.n):
+            for r in range(S):
+                nodes.append(i)
+                masks.append(oracle.unrank(w.n, w.K, i, r))
+    else:
+        for _ in range(3000):
+            i = int(rng.integers(w.n))
+            nodes.append(i)
+            masks.append(oracle.unrank(w.n, w.K, i, int(rng.integers(S))))
+    got = t.counts(nodes, masks, net.arities)
+    for i, m, g in zip(nodes, masks, got):
+        want = oracle.counts(net.data, net.arities, i, m)
+        assert np.array_equal(g, want), (i, m)
+
+
+# ------------------------------------------------------------------ table
+
+@pytest.mark.parametrize("wname", ["tiny8", "prior20"])
+def test_table_entries_and_scores(bnos, wname, request):
+    w, net, prior, t, orc = request.getfixturevalue(wname)
+    info = t.info()
+    S = oracle.num_sets(w.n - 1, w.K)
+    assert info["entries_per_node"] == S and info["n"] == w.n and info["K"] == w.K
+    not_rne = 0
+    for i in range(w.n):
+        masks, scores = t.export(i)
+        # every parent set of size <= K over the other nodes, once, ascending after removing bit i
+        slot = [(int(m) & ((1 << i) - 1)) | ((int(m) >> (i + 1)) << i) for m in masks]
+        assert slot == sorted(slot) and len(set(slot)) == S
+        assert all(not (int(m) >> i) & 1 and bin(int(m)).count("1") <= w.K for m in masks)
+        ranks = np.array([oracle.rank(w.n, w.K, i, int(m)) for m in masks])
+        want = orc[i, ranks]
+        diff = np.abs(scores.astype(np.float64) - want)
+        assert np.all(diff <= 2 * ulp32(want)), (i, diff.max())
+        not_rne += int(np.sum(scores != want.astype(np.float32)))
+    assert not_rne <= max(2, S * w.n // 10000)
+
+
+# ------------------------------------------------------------------ order scoring
+
+@pytest.mark.parametrize("B", [1, 2, 3, 4, 5, 64])
+def test_score_orders_tiny8(bnos, tiny8, B):
+    w, net, prior, t, orc = tiny8
+    orders = datagen.random_orders(w.n, B, seed=100 + B)
+    got = dev_score(t, orders)
+    assert check_orders_against_oracle(got, orc, w.K, orders) == 0
+
+
+@pytest.mark.parametrize("B", [1, 7, 32])
+def test_score_orders_prior20(bnos, prior20, B):
+    w, net, prior, t, orc = prior20
+    orders = datagen.random_orders(w.n, B, seed=200 + B)
+    got = dev_score(t, orders)
+    assert check_orders_against_oracle(got, orc, w.K, orders) == 0
+
+
+def test_host_score_order_and_determinism(bnos, prior20):
+    w, net, prior, t, orc = prior20
+    orders = datagen.random_orders(w.n, 16, seed=5)
+    a = dev_score(t, orders)
+    b = dev_score(t, orders)
+    for k in a:
+        assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), k
+    l, m, best = t.score_order(orders[3])
+    assert l == a["lse"][3] and m == a["max"][3]
+    assert np.array_equal(best, a["best"][3])
+
+
+def test_invalid_orders(bnos, tiny8):
+    w, net, prior, t, orc = tiny8
+    orders = datagen.random_orders(w.n, 4, seed=9)
+    orders[1, 2] = orders[1, 5]          # duplicate id
+    orders[2, 0] = w.n + 3               # out of range
+    got = dev_score(t, orders)
+    assert np.isnan(got["lse"][1]) and np.isnan(got["max"][2])
+    assert np.all(got["best"][1] == 0) and np.all(got["best"][2] == 0)
+    ok = check_orders_against_oracle({k: v[[0, 3]] for k, v in got.items()}, orc, w.K, orders[[0, 3]])
+    assert ok == 0
+    with pytest.raises(bnos.BnosError) as e:
+        t.score_order(orders[1])
+    assert e.value.status == bnos.E_INVALID
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_empty_data_closed_form(bnos):
+    for n, K in [(8, 3), (20, 4)]:
+        data = np.zeros((0, n), dtype=np.int8)
+        t = bnos.build_score_table(data, [2] * n, K)
+        orders = datagen.random_orders(n, 3, seed=n)
+        got = dev_score(t, orders)
+        closed = sum(math.log(oracle.num_sets(p, K)) for p in range(n))
+        np.testing.assert_allclose(got["lse"], closed, rtol=REL)
+        assert np.all(got["max"] == 0.0) and np.all(got["best"] == 0)
+        t.free()
+
+
+@pytest.mark.parametrize("n,K,N,arities", [
+    (1, 0, 50, (3,)),            # single node, only the empty set
+    (6, 0, 100, (2, 3)),         # K = 0
+    (5, 4, 37, (2, 3, 4)),       # K = n - 1, N not a multiple of 4
+    (64, 2, 129, (2,)),          # the largest n, bit 63 in use
+    (12, 3, 1, (4,)),            # one sample
+])
+def test_edge_shapes(bnos, n, K, N, arities):
+    net = datagen.random_network(n, N, arities, min(3, n - 1), seed=n * 31 + K)
+    t = bnos.build_score_table(net.data, net.arities, K)
+    orc = oracle.build_table(net.data, net.arities, K)
+    orders = datagen.random_orders(n, 5, seed=N)
+    got = dev_score(t, orders)
+    assert check_orders_against_oracle(got, orc, K, orders) == 0
+    t.free()
+
+
+def test_constant_data_and_log_gamma(bnos):
+    n, K = 7, 3
+    data = np.ones((300, n), dtype=np.int8)
+    ar = [2, 3, 2, 2, 4, 2, 3]
+    t = bnos.build_score_table(data, ar, K, log_gamma=-0.5, prior=np.full((n, n), 0.9, np.float32),
+                               prior_mode=1)
+    orc = oracle.build_table(data, ar, K, log_gamma=-0.5, prior=np.full((n, n), 0.9, np.float32),
+                             prior_mode=1)
+    orders = datagen.random_orders(n, 6, seed=1)
+    got = dev_score(t, orders)
+    assert check_orders_against_oracle(got, orc, K, orders) == 0
+    t.free()
+
+
+def test_build_validation_errors(bnos):
+    data = np.zeros((4, 3), dtype=np.int8)
+    with pytest.raises(bnos.BnosError) as e:
+        bnos.build_score_table(data, [2, 2, 2], 3)            # K > n - 1
+    assert e.value.status == bnos.E_RANGE
+    bad = data.copy()
+    bad[2, 1] = 2
+    with pytest.raises(bnos.BnosError) as e:
+        bnos.build_score_table(bad, [2, 2, 2], 1)             # state >= arity
+    assert e.value.status == bnos.E_INVALID
+    with pytest.raises(bnos.BnosError) as e:
+        bnos.build_score_table(data, [2, 2, 2], 1, ess=0.0)
+    assert e.value.status == bnos.E_INVALID
+    with pytest.raises(bnos.BnosError) as e:
+        bnos.build_score_table(data, [2, 2, 2], 1, prior=np.full((3, 3), np.nan, np.float32))
+    assert e.value.status == bnos.E_INVALID
+
+
+# ------------------------------------------------------------------ full-size spot checks
+
+@pytest.fixture(scope="module")
+def mixed60(bnos):
+    w = datagen.WORKLOADS["mixed60"]
+    net, prior = datagen.make(w)
+    t = bnos.build_score_table(net.data, net.arities, w.K, prior=prior)
+    yield w, net, prior, t
+    t.free()
+
+
+def test_mixed60_counts_and_scores_sampled(bnos, mixed60):
+    w, net, prior, t = mixed60
+    rng = np.random.default_rng(60)
+    S = oracle.num_sets(w.n - 1, w.K)
+    assert t.info()["entries_per_node"] == S == 489406
+    nodes = rng.integers(0, w.n, size=300)
+    idx = rng.integers(0, S, size=300)
+    exported = {}
+    for i in sorted(set(int(v) for v in nodes)):
+        exported[i] = t.export(i)
+    masks = [int(exported[int(i)][0][int(e)]) for i, e in zip(nodes, idx)]
+    got = t.counts(nodes, masks, net.arities)
+    for i, m, g, e in zip(nodes, masks, got, idx):
+        want = oracle.counts(net.data, net.arities, int(i), m)
+        assert np.array_equal(g, want)
+        ls = oracle.local_score(net.data, net.arities, int(i), m, prior=prior)
+        s = float(exported[int(i)][1][int(e)])
+        assert abs(s - ls) <= 2 * ulp32(ls)
+
+
+def test_mixed60_orders_against_direct_oracle(bnos, mixed60):
+    w, net, prior, t = mixed60
+    orders = datagen.random_orders(w.n, 8, seed=61)
+    got = dev_score(t, orders)
+    # global properties at any size
+    assert np.all(got["lse"] >= got["max"])
+    np.testing.assert_allclose(got["node_lse"].sum(axis=1), got["lse"], rtol=1e-12)
+    # per-node spot checks against scoring straight from the data
+    checks = [(0, 12), (1, 20), (2, 27), (5, 59)]     # (order, position)
+    for b, p in checks:
+        node = int(orders[b, p])
+        pred = 0
+        for v in orders[b, :p]:
+            pred |= 1 << int(v)
+        l, best, bm, sec = oracle.score_node_direct(net.data, net.arities, w.K, node, pred,
+                                                    prior=prior, round_f32=True)
+        assert abs(got["node_lse"][b, node] - l) <= REL * max(1.0, abs(l))
+        assert int(got["best"][b, node]) == bm
+        assert float(got["node_second"][b, node]) == sec
