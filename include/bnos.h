@@ -43,7 +43,7 @@ typedef int32_t bnos_status;
 #define BNOS_OK        0
 #define BNOS_E_INVALID (-1)   /* NULL pointer, non-permutation order, state >= arity, ess <= 0, NaN prior */
 #define BNOS_E_RANGE   (-2)   /* n outside [1,64], K outside [0, min(n-1, 6)], arity outside [1,255],
-                                 q_i * r_i above 65536, N above 2^31 - 1, B outside [1, 2^20] */
+                                 q_i * r_i above 16384, N above 2^31 - 1, B outside [1, 2^20] */
 #define BNOS_E_NOMEM   (-3)   /* host or device allocation failed */
 #define BNOS_E_DEVICE  (-4)   /* a HIP runtime call failed; the message names it */
 #define BNOS_E_STATE   (-5)   /* handle is NULL or already freed */
@@ -154,11 +154,14 @@ bnos_status bnos_score_order(bnos_table t, const int32_t *order, double *lse, do
  * Kernel timing for measurement: while enabled, every order-scoring launch
  * of this table is bracketed by HIP events recorded on the launch stream.
  * bnos_table_timing_read waits for the recorded events and returns the sum of
- * the scoring kernels' durations (ms) and the number of launches since the
- * last enable, then keeps counting.
+ * the scoring kernels' durations (ms), the number of launches and the number
+ * of full passes over the table those launches made (a launch scoring B
+ * orders streams the table once per group of up to 4 orders) since the last
+ * enable, then keeps counting.  Any output pointer may be NULL.
  */
 bnos_status bnos_table_timing(bnos_table t, int32_t enable);
-bnos_status bnos_table_timing_read(bnos_table t, double *total_ms, int64_t *launches);
+bnos_status bnos_table_timing_read(bnos_table t, double *total_ms, int64_t *launches,
+                                   int64_t *table_passes);
 
 #ifdef __cplusplus
 }

@@ -57,6 +57,10 @@ def lib():
         L.orc_score_node_direct.restype = None
         L.orc_score_node_direct.argtypes = [P, i64, i32, P, i32, f64, f64, P, i32, i32, u64, i32,
                                             P, P, P, P]
+        L.orc_build_row.restype = None
+        L.orc_build_row.argtypes = [P, i64, i32, P, i32, f64, f64, P, i32, i32, i64, i64, P]
+        L.orc_score_node_row.restype = None
+        L.orc_score_node_row.argtypes = [P, i32, i32, i32, u64, i32, P, P, P, P]
         L.orc_draw.restype = u64
         L.orc_draw.argtypes = [u64, u64, u64, u64]
         L.orc_initial_order.restype = None
@@ -126,6 +130,42 @@ def build_table(data, arities, K: int, ess: float = 1.0, log_gamma: float = 0.0,
     lib().orc_build_table(_p(data), data.shape[0], n, _p(ar), K, ess, log_gamma,
                           None if pr is None else _p(pr), prior_mode, _p(out))
     return out
+
+
+def build_row(data, arities, K: int, node: int, ess: float = 1.0, log_gamma: float = 0.0, prior=None,
+              prior_mode: int = 0, threads: int = 1) -> np.ndarray:
+    """FP64 row of one node, indexed by the oracle's combinatorial rank.
+
+    ``threads`` > 1 splits the rank range over that many threads (the C call
+    releases the GIL); every entry is still computed by the same plain code.
+    """
+    data, ar, pr = _prep(data, arities, prior)
+    n = data.shape[1]
+    S = num_sets(n - 1, K)
+    out = np.zeros(S, dtype=np.float64)
+    L = lib()
+
+    def part(r0, r1):
+        L.orc_build_row(_p(data), data.shape[0], n, _p(ar), K, ess, log_gamma,
+                        None if pr is None else _p(pr), prior_mode, node, r0, r1, _p(out))
+
+    if threads <= 1:
+        part(0, S)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        cuts = [S * k // (4 * threads) for k in range(4 * threads + 1)]
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda k: part(cuts[k], cuts[k + 1]), range(4 * threads)))
+    return out
+
+
+def score_node_row(row: np.ndarray, n: int, K: int, node: int, pred: int, round_f32: bool = True):
+    """Returns (lse_i, best_i, best_mask_i, second_i) from one node's table row."""
+    row = np.ascontiguousarray(row, dtype=np.float64)
+    lse, best, bm, sec = ctypes.c_double(), ctypes.c_double(), ctypes.c_uint64(), ctypes.c_double()
+    lib().orc_score_node_row(_p(row), n, K, node, pred, int(round_f32), ctypes.byref(lse),
+                             ctypes.byref(best), ctypes.byref(bm), ctypes.byref(sec))
+    return lse.value, best.value, bm.value, sec.value
 
 
 def score_order(table: np.ndarray, K: int, order, round_f32: bool = True):

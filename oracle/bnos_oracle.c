@@ -187,6 +187,16 @@ uint64_t orc_unrank(int n, int K, int node, int64_t idx)
     return mask;
 }
 
+/* Part of one node's row: out[rank] = s(node, unrank(rank)) for r0 <= rank < r1. */
+void orc_build_row(const int8_t *data, int64_t N, int n, const int32_t *ar, int K, double ess,
+                   double log_gamma, const float *prior, int prior_mode, int node,
+                   int64_t r0, int64_t r1, double *out)
+{
+    for (int64_t r = r0; r < r1; ++r)
+        out[r] = orc_local_score(data, N, n, ar, node, orc_unrank(n, K, node, r), ess, log_gamma,
+                                 prior, prior_mode);
+}
+
 /* Full table: out[node * S + rank] = s(node, unrank(rank)), S = S(n-1, K). */
 void orc_build_table(const int8_t *data, int64_t N, int n, const int32_t *ar, int K,
                      double ess, double log_gamma, const float *prior, int prior_mode,
@@ -330,6 +340,15 @@ void orc_score_order(const double *table, int n, int K, const int32_t *order, in
     }
     *lse = tl;
     *mx = tm;
+}
+
+/* Score one node against its own table row, given its predecessor mask. */
+void orc_score_node_row(const double *row, int n, int K, int node, uint64_t pred, int round_f32,
+                        double *lse, double *best, uint64_t *best_mask, double *second)
+{
+    orc_ctx c = {0};
+    c.row = row; c.n = n; c.K = K; c.node = node; c.round_f32 = round_f32;
+    score_node(&c, pred, lse, best, best_mask, second);
 }
 
 /*

@@ -45,7 +45,7 @@ _SIGS = {
     "bnos_score_orders": (i32, [P, P, i32, P, P, P, P, P, P]),
     "bnos_score_order": (i32, [P, P, P, P, P]),
     "bnos_table_timing": (i32, [P, i32]),
-    "bnos_table_timing_read": (i32, [P, P, P]),
+    "bnos_table_timing_read": (i32, [P, P, P, P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -159,9 +159,10 @@ class Table:
         _check(_lib.bnos_table_timing(self._h, int(enable)))
 
     def timing_read(self):
-        ms, cnt = f64(), i64()
-        _check(_lib.bnos_table_timing_read(self._h, ctypes.byref(ms), ctypes.byref(cnt)))
-        return ms.value, cnt.value
+        """-> (total kernel ms, launches, table passes) since timing was enabled."""
+        ms, cnt, passes = f64(), i64(), i64()
+        _check(_lib.bnos_table_timing_read(self._h, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(passes)))
+        return ms.value, cnt.value, passes.value
 
 
 def build_score_table(data, arities, K: int, ess: float = 1.0, prior=None, prior_mode: int = 0,

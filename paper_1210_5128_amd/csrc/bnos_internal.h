@@ -17,10 +17,17 @@ constexpr int kMaxCells = 16384;
 constexpr int kMaxK = 6;
 
 // Order-scoring geometry: 256 threads, 4 entries per thread per step, so a
-// block consumes 1024 entries per step; a chunk is 1..8 steps.
+// block consumes 1024 entries per step; a chunk is 1..16 steps.
 constexpr int kScoreThreads = 256;
 constexpr int kEntriesPerStep = 1024;
-constexpr int kMaxStepsPerChunk = 8;
+constexpr int kMaxStepsPerChunk = 16;
+
+// Partial-reduction record written by each scoring block (one per order).
+struct Partial {
+    float m, s;          // running max and sum of exp(x - m) over consistent entries
+    float best, second;  // top-1 score and best score among the others
+    uint64_t bmask;      // mask of the top-1 entry
+};
 
 struct TableT {
     uint32_t magic = 0;
@@ -50,8 +57,14 @@ struct TableT {
     size_t ev_used = 0;
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
+    std::vector<int64_t> ev_passes;     // table passes of each recorded launch
+    int64_t timed_passes = 0;
 
     int64_t device_bytes() const;
+    int64_t workspace_bytes_per_order() const
+    {
+        return (int64_t)n * chunks * (int64_t)sizeof(Partial);
+    }
 };
 
 constexpr uint32_t kMagic = 0xB0A5C0DEu;
@@ -61,12 +74,6 @@ bool handle_live(const TableT *t);
 void register_handle(TableT *t);
 void unregister_handle(TableT *t);
 
-// Partial-reduction record written by each scoring block (one per order).
-struct Partial {
-    float m, s;          // running max and sum of exp(x - m) over consistent entries
-    float best, second;  // top-1 score and best score among the others
-    uint64_t bmask;      // mask of the top-1 entry
-};
 
 }  // namespace bnos
 

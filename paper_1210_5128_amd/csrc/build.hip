@@ -46,7 +46,7 @@ int64_t TableT::device_bytes() const
 {
     return (int64_t)n * S_pad * (int64_t)(sizeof(uint64_t) + sizeof(float)) + (int64_t)n * N_pad +
            (int64_t)n * (int64_t)(sizeof(int32_t) + n * sizeof(double)) + 64 * 8 * 8 +
-           part_orders * (int64_t)n * chunks * (int64_t)sizeof(Partial);
+           part_orders * workspace_bytes_per_order();
 }
 
 // ------------------------------------------------------------------ device helpers
@@ -397,11 +397,35 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     t->N_pad = ((N + 255) / 256) * 256;
     if (t->N_pad == 0) t->N_pad = 256;
     t->S = sets_upto(n - 1, K);
-    int64_t steps = (t->S + kEntriesPerStep - 1) / kEntriesPerStep;
-    if (steps > kMaxStepsPerChunk) steps = kMaxStepsPerChunk;
-    t->chunk_entries = (int)(steps * kEntriesPerStep);
-    t->S_pad = ((t->S + t->chunk_entries - 1) / t->chunk_entries) * t->chunk_entries;
-    t->chunks = (int)(t->S_pad / t->chunk_entries);
+    {
+        // Chunk length (in 1024-entry steps) for the scoring grid: the one that
+        // best fills whole rounds of resident blocks (8 blocks of 256 threads
+        // per compute unit) for a single-order pass; ties go to longer chunks.
+        int cus = 256;
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            int v = 0;
+            if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+                cus = v;
+        }
+        const int64_t slots = (int64_t)cus * 8;
+        const int64_t node_steps = (t->S + kEntriesPerStep - 1) / kEntriesPerStep;
+        int best_st = 1;
+        double best_eff = -1.0;
+        for (int st = 1; st <= kMaxStepsPerChunk && st <= node_steps; ++st) {
+            int64_t chunks = (node_steps + st - 1) / st;
+            int64_t blocks = (int64_t)n * chunks;
+            int64_t rounds = (blocks + slots - 1) / slots;
+            double eff = (double)(n * node_steps) / (double)(rounds * slots * st);
+            if (eff >= best_eff - 1e-12) {
+                best_eff = eff;
+                best_st = st;
+            }
+        }
+        t->chunk_entries = best_st * kEntriesPerStep;
+        t->chunks = (int)((node_steps + best_st - 1) / best_st);
+        t->S_pad = (int64_t)t->chunks * t->chunk_entries;
+    }
     t->max_cells = max_cells;
     t->ess = ess;
     t->log_gamma = o.log_gamma;

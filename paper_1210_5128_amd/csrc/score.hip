@@ -33,21 +33,21 @@ __device__ __forceinline__ void acc_init(Acc &a)
 }
 
 // Fold one consistent entry (x, mask) into the state.  Argmax tie rule: the
-// larger score wins; on equal scores the smaller mask wins.
-__device__ __forceinline__ void acc_push(Acc &a, float x, uint64_t mk, bool ok)
+// larger score wins; on equal scores the smaller mask wins.  Called under a
+// divergent branch on consistency, so a wavefront whose lanes hold no
+// consistent entry skips it entirely.
+__device__ __forceinline__ void acc_push(Acc &a, float x, uint64_t mk)
 {
     float d = x - a.m;
     float e = __expf(-fabsf(d));
-    bool up = d > 0.f;
-    float s_new = up ? fmaf(a.s, e, 1.f) : a.s + e;
-    float m_new = up ? x : a.m;
-    a.s = ok ? s_new : a.s;
-    a.m = ok ? m_new : a.m;
-    bool better = ok && (x > a.best || (x == a.best && mk < a.bm));
-    bool sec_up = ok && !better && x > a.sec;
-    a.sec = better ? a.best : (sec_up ? x : a.sec);
-    a.best = better ? x : a.best;
-    a.bm = better ? mk : a.bm;
+    a.s = (d > 0.f) ? fmaf(a.s, e, 1.f) : a.s + e;
+    a.m = fmaxf(a.m, x);
+    if (x >= a.sec) {
+        bool better = x > a.best || (x == a.best && mk < a.bm);
+        a.sec = better ? a.best : fmaxf(a.sec, x);
+        a.best = better ? x : a.best;
+        a.bm = better ? mk : a.bm;
+    }
 }
 
 // Combine two states (order-independent up to FP32 rounding; the callers fix the order).
@@ -76,7 +76,43 @@ __device__ __forceinline__ Acc acc_shfl_xor(const Acc &a, int off)
     return b;
 }
 
-// Predecessor mask of `node` in order b, computed by one wavefront (lane p
+// Butterfly merge over the 64 lanes.  In every pair the lower lane's state is
+// the left operand, so both lanes compute the same value and the result does
+// not depend on scheduling.
+__device__ __forceinline__ void acc_wave_reduce(Acc &a, int lane)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        Acc o = acc_shfl_xor(a, off);
+        const bool upper = (lane & off) != 0;
+        Acc lo, hi;
+        lo.m = upper ? o.m : a.m;
+        hi.m = upper ? a.m : o.m;
+        lo.s = upper ? o.s : a.s;
+        hi.s = upper ? a.s : o.s;
+        lo.best = upper ? o.best : a.best;
+        hi.best = upper ? a.best : o.best;
+        lo.sec = upper ? o.sec : a.sec;
+        hi.sec = upper ? a.sec : o.sec;
+        lo.bm = upper ? o.bm : a.bm;
+        hi.bm = upper ? a.bm : o.bm;
+        acc_merge(lo, hi);
+        a = lo;
+    }
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v, int lane)
+{
+    // fixed butterfly: the lower lane's value is the left operand
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        double o = __shfl_xor(v, off, 64);
+        v = (lane & off) ? (o + v) : (v + o);
+    }
+    return v;
+}
+
+// Predecessor mask of `node` in an order, computed by one wavefront (lane p
 // reads position p).  valid = the order is a permutation of 0..n-1.
 __device__ __forceinline__ uint64_t wave_pred(const int32_t *__restrict__ ord, int n, int node,
                                               int lane, bool &valid)
@@ -98,29 +134,49 @@ __device__ __forceinline__ uint64_t wave_pred(const int32_t *__restrict__ ord, i
     return valid ? before : 0ull;
 }
 
-// ------------------------------------------------------------------ kernels
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
 
-// Grid: x = node * chunks + chunk, y = group of BT orders.  Each block streams
-// one chunk of one node's entries once and folds every entry into BT order
-// states; it writes one Partial per (order, node, chunk).
+// ------------------------------------------------------------------ kernel
+
+struct ScoreArgs {
+    const uint64_t *masks;
+    const float *scores;
+    int64_t S_pad;
+    int chunks, chunk_entries;
+    const int32_t *orders;
+    int B, n;
+    Partial *part;          // [B][n][chunks]
+    double *lse, *maxs;
+    uint64_t *best;
+    double *node_lse;
+    float *node_second;
+};
+
+// Grid: x = node * chunks + chunk, y = group of BT orders.  Every block
+// streams one chunk of one node's entries once, folds each entry into BT order
+// states and writes one Partial per order.
 template <int BT>
-__global__ __launch_bounds__(kScoreThreads) void k_score_stream(
-    const uint64_t *__restrict__ masks, const float *__restrict__ scores, int64_t S_pad, int chunks,
-    int chunk_entries, const int32_t *__restrict__ orders, int B, int n, Partial *__restrict__ part)
+__global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
 {
     __shared__ uint64_t s_npred[BT];
     __shared__ Acc s_red[kScoreThreads / 64][BT];
-    const int node = blockIdx.x / chunks;
-    const int chunk = blockIdx.x - node * chunks;
+    const int node = blockIdx.x / A.chunks;
+    const int chunk = blockIdx.x - node * A.chunks;
     const int b0 = blockIdx.y * BT;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    const int n = A.n;
 
     for (int j = wave; j < BT; j += kScoreThreads / 64) {
-        uint64_t np = ~0ull;   // no order: nothing is consistent
-        if (b0 + j < B) {
+        uint64_t np = ~0ull;   // no order in this slot: nothing is consistent
+        if (b0 + j < A.B) {
             bool valid;
-            uint64_t pred = wave_pred(orders + (int64_t)(b0 + j) * n, n, node, lane, valid);
+            uint64_t pred = wave_pred(A.orders + (int64_t)(b0 + j) * n, n, node, lane, valid);
             np = ~pred;        // invalid order: only the empty set is consistent
         }
         if (lane == 0) s_npred[j] = np;
@@ -130,51 +186,48 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_stream(
     Acc a[BT];
 #pragma unroll
     for (int j = 0; j < BT; ++j) {
-        npred[j] = s_npred[j];
+        npred[j] = uniform_u64(s_npred[j]);
         acc_init(a[j]);
     }
 
-    const int64_t row = (int64_t)node * S_pad + (int64_t)chunk * chunk_entries;
-    const u64x2 *mp = reinterpret_cast<const u64x2 *>(masks + row);
-    const f32x4 *sp = reinterpret_cast<const f32x4 *>(scores + row);
-    const int steps = chunk_entries / kEntriesPerStep;
+    const int64_t row = (int64_t)node * A.S_pad + (int64_t)chunk * A.chunk_entries;
+    const u64x2 *mp = reinterpret_cast<const u64x2 *>(A.masks + row);
+    const f32x4 *sp = reinterpret_cast<const f32x4 *>(A.scores + row);
+    const int steps = A.chunk_entries / kEntriesPerStep;
+    // Software pipeline: the loads of step it+1 are in flight while step it is folded.
+    int q = threadIdx.x;                                     // this lane's 4-entry group
+    u64x2 n01 = __builtin_nontemporal_load(&mp[2 * q]);
+    u64x2 n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
+    f32x4 nsc = __builtin_nontemporal_load(&sp[q]);
     for (int it = 0; it < steps; ++it) {
-        const int q = it * kScoreThreads + threadIdx.x;      // index of this lane's 4-entry group
-        u64x2 m01 = __builtin_nontemporal_load(&mp[2 * q]);
-        u64x2 m23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
-        f32x4 sc = __builtin_nontemporal_load(&sp[q]);
+        const u64x2 m01 = n01, m23 = n23;
+        const f32x4 sc = nsc;
+        if (it + 1 < steps) {
+            q += kScoreThreads;
+            n01 = __builtin_nontemporal_load(&mp[2 * q]);
+            n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
+            nsc = __builtin_nontemporal_load(&sp[q]);
+        }
         const uint64_t mk[4] = {m01.x, m01.y, m23.x, m23.y};
         const float x[4] = {sc.x, sc.y, sc.z, sc.w};
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int j = 0; j < BT; ++j) {
 #pragma unroll
-            for (int j = 0; j < BT; ++j) acc_push(a[j], x[k], mk[k], (mk[k] & npred[j]) == 0ull);
+            for (int k = 0; k < 4; ++k) {
+                if ((mk[k] & npred[j]) == 0ull) acc_push(a[j], x[k], mk[k]);
+            }
         }
     }
 
 #pragma unroll
     for (int j = 0; j < BT; ++j) {
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            Acc o = acc_shfl_xor(a[j], off);
-            // fixed pairing: the lower lane's state is always the left operand,
-            // so both lanes of a pair compute the same result
-            const bool upper = (lane & off) != 0;
-            Acc lo, hi;
-            lo.m = upper ? o.m : a[j].m;       hi.m = upper ? a[j].m : o.m;
-            lo.s = upper ? o.s : a[j].s;       hi.s = upper ? a[j].s : o.s;
-            lo.best = upper ? o.best : a[j].best; hi.best = upper ? a[j].best : o.best;
-            lo.sec = upper ? o.sec : a[j].sec; hi.sec = upper ? a[j].sec : o.sec;
-            lo.bm = upper ? o.bm : a[j].bm;    hi.bm = upper ? a[j].bm : o.bm;
-            acc_merge(lo, hi);
-            a[j] = lo;
-        }
+        acc_wave_reduce(a[j], lane);
         if (lane == 0) s_red[wave][j] = a[j];
     }
     __syncthreads();
     if (threadIdx.x < BT) {
         const int j = threadIdx.x;
-        if (b0 + j < B) {
+        if (b0 + j < A.B) {
             Acc r;
             r.m = s_red[0][j].m;
             r.s = s_red[0][j].s;
@@ -197,74 +250,91 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_stream(
             p.best = r.best;
             p.second = r.sec;
             p.bmask = r.bm;
-            part[((int64_t)(b0 + j) * n + node) * chunks + chunk] = p;
+            A.part[((int64_t)(b0 + j) * n + node) * A.chunks + chunk] = p;
         }
     }
 }
 
-// One wavefront per order: lane i merges node i's chunk partials in chunk
-// order, then the per-node terms are summed in FP64 in node-id order.
-__global__ __launch_bounds__(64) void k_score_merge(const Partial *__restrict__ part, int chunks,
-                                                    const int32_t *__restrict__ orders, int B, int n,
-                                                    double *__restrict__ lse, double *__restrict__ maxs,
-                                                    uint64_t *__restrict__ best, double *__restrict__ node_lse,
-                                                    float *__restrict__ node_second)
+constexpr int kMergeWaves = 16;
+constexpr int kMergeNodesPerWave = 4;   // 16 waves x 4 nodes covers n <= 64
+
+__device__ __forceinline__ Acc load_partial(const Partial *p)
+{
+    Acc a;
+    a.m = p->m;
+    a.s = p->s;
+    a.best = p->best;
+    a.sec = p->second;
+    a.bm = p->bmask;
+    return a;
+}
+
+// One block per order.  Wave w merges the chunk partials of nodes w, w+16,
+// w+32, w+48 (lanes over chunks, then a fixed butterfly); the first partial
+// of every node is loaded before any merging so the loads overlap.  Wave 0
+// then sums the per-node terms in FP64 with a fixed butterfly.
+__global__ __launch_bounds__(kMergeWaves * 64) void k_merge(ScoreArgs A)
 {
     __shared__ double s_l[64], s_b[64];
     const int b = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int n = A.n;
+    const int chunks = A.chunks;
     bool valid;
-    (void)wave_pred(orders + (int64_t)b * n, n, 0, lane, valid);
-    double li = 0.0, bi = 0.0;
-    if (lane < n) {
-        const Partial *p = part + ((int64_t)b * n + lane) * chunks;
-        Acc a;
-        a.m = p[0].m;
-        a.s = p[0].s;
-        a.best = p[0].best;
-        a.sec = p[0].second;
-        a.bm = p[0].bmask;
-        for (int c = 1; c < chunks; ++c) {
-            Acc o;
-            o.m = p[c].m;
-            o.s = p[c].s;
-            o.best = p[c].best;
-            o.sec = p[c].second;
-            o.bm = p[c].bmask;
-            acc_merge(a, o);
-        }
-        li = (double)a.m + log((double)a.s);
-        bi = (double)a.best;
-        if (best) best[(int64_t)b * n + lane] = valid ? a.bm : 0ull;
-        if (node_lse) node_lse[(int64_t)b * n + lane] = valid ? li : NAN;
-        if (node_second) node_second[(int64_t)b * n + lane] = valid ? a.sec : NAN;
+    (void)wave_pred(A.orders + (int64_t)b * n, n, 0, lane, valid);
+
+    Acc r[kMergeNodesPerWave];
+#pragma unroll
+    for (int k = 0; k < kMergeNodesPerWave; ++k) {
+        const int i = wave + kMergeWaves * k;
+        acc_init(r[k]);
+        if (i < n && lane < chunks) r[k] = load_partial(A.part + ((int64_t)b * n + i) * chunks + lane);
     }
-    s_l[lane] = li;
-    s_b[lane] = bi;
-    __syncthreads();
-    if (lane == 0) {
-        double tl = 0.0, tb = 0.0;
-        for (int i = 0; i < n; ++i) {
-            tl += s_l[i];
-            tb += s_b[i];
+#pragma unroll
+    for (int k = 0; k < kMergeNodesPerWave; ++k) {
+        const int i = wave + kMergeWaves * k;
+        if (i >= n) break;
+        const Partial *pp = A.part + ((int64_t)b * n + i) * chunks;
+        for (int c = lane + 64; c < chunks; c += 64) acc_merge(r[k], load_partial(pp + c));
+        acc_wave_reduce(r[k], lane);
+        if (lane == 0) {
+            const double li = (double)r[k].m + log((double)r[k].s);
+            const int64_t o = (int64_t)b * n + i;
+            s_l[i] = li;
+            s_b[i] = (double)r[k].best;
+            A.best[o] = valid ? r[k].bm : 0ull;
+            if (A.node_lse) A.node_lse[o] = valid ? li : NAN;
+            if (A.node_second) A.node_second[o] = valid ? r[k].sec : NAN;
         }
-        lse[b] = valid ? tl : NAN;
-        maxs[b] = valid ? tb : NAN;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        double l = (lane < n) ? s_l[lane] : 0.0;
+        double m = (lane < n) ? s_b[lane] : 0.0;
+        l = wave_sum_f64(l, lane);
+        m = wave_sum_f64(m, lane);
+        if (lane == 0) {
+            A.lse[b] = valid ? l : NAN;
+            A.maxs[b] = valid ? m : NAN;
+        }
     }
 }
 
 // ------------------------------------------------------------------ host side
 
+// Orders per block: a block folds every streamed entry into this many order states.
+static int pick_bt(int B) { return B >= 8 ? 8 : (B >= 4 ? 4 : (B >= 2 ? 2 : 1)); }
+
 template <int BT>
-static void launch_stream(const TableT *t, const int32_t *orders, int B, hipStream_t st)
+static void launch_score(const ScoreArgs &A, int nblocks_x, hipStream_t st)
 {
-    dim3 grid((unsigned)(t->n * t->chunks), (unsigned)((B + BT - 1) / BT));
-    hipLaunchKernelGGL(k_score_stream<BT>, grid, dim3(kScoreThreads), 0, st, t->d_masks, t->d_scores,
-                       t->S_pad, t->chunks, t->chunk_entries, orders, B, t->n,
-                       reinterpret_cast<Partial *>(t->d_part));
+    dim3 grid((unsigned)nblocks_x, (unsigned)((A.B + BT - 1) / BT));
+    hipLaunchKernelGGL(k_score<BT>, grid, dim3(kScoreThreads), 0, st, A);
 }
 
-static bnos_status ensure_partials(TableT *t, int B)
+// Scoring workspace for up to `B` orders: the chunk partials.
+static bnos_status ensure_workspace(TableT *t, int B)
 {
     if (t->part_orders >= B) return BNOS_OK;
     // A launch still in flight may use the old buffer.
@@ -273,9 +343,9 @@ static bnos_status ensure_partials(TableT *t, int B)
     t->d_part = nullptr;
     t->part_orders = 0;
     int64_t want = B < 64 ? 64 : B;
-    hipError_t e = hipMalloc(&t->d_part, (size_t)want * t->n * t->chunks * sizeof(Partial));
+    hipError_t e = hipMalloc(&t->d_part, (size_t)want * t->workspace_bytes_per_order());
     if (e != hipSuccess) {
-        set_error(std::string("hipMalloc partials: ") + hipGetErrorString(e));
+        set_error(std::string("hipMalloc scoring workspace: ") + hipGetErrorString(e));
         t->d_part = nullptr;
         return e == hipErrorOutOfMemory ? BNOS_E_NOMEM : BNOS_E_DEVICE;
     }
@@ -298,22 +368,40 @@ static bnos_status record_event(TableT *t, bool start, hipStream_t st)
 static bnos_status score_impl(TableT *t, const int32_t *orders, int B, double *lse, double *maxs,
                               uint64_t *best, double *node_lse, float *node_second, hipStream_t st)
 {
-    bnos_status s = ensure_partials(t, B);
+    bnos_status s = ensure_workspace(t, B);
     if (s != BNOS_OK) return s;
+    ScoreArgs A;
+    A.masks = t->d_masks;
+    A.scores = t->d_scores;
+    A.S_pad = t->S_pad;
+    A.chunks = t->chunks;
+    A.chunk_entries = t->chunk_entries;
+    A.orders = orders;
+    A.B = B;
+    A.n = t->n;
+    A.part = reinterpret_cast<Partial *>(t->d_part);
+    A.lse = lse;
+    A.maxs = maxs;
+    A.best = best;
+    A.node_lse = node_lse;
+    A.node_second = node_second;
     if (t->timing) {
         if ((s = record_event(t, true, st)) != BNOS_OK) return s;
     }
-    // Orders per block: more orders share each streamed entry.
-    if (B >= 4) launch_stream<4>(t, orders, B, st);
-    else if (B >= 2) launch_stream<2>(t, orders, B, st);
-    else launch_stream<1>(t, orders, B, st);
+    const int bt = pick_bt(B);
+    const int nbx = t->n * t->chunks;
+    if (bt == 8) launch_score<8>(A, nbx, st);
+    else if (bt == 4) launch_score<4>(A, nbx, st);
+    else if (bt == 2) launch_score<2>(A, nbx, st);
+    else launch_score<1>(A, nbx, st);
     BNOS_HIP(hipGetLastError());
     if (t->timing) {
         if ((s = record_event(t, false, st)) != BNOS_OK) return s;
+        if (t->ev_passes.size() <= t->ev_used) t->ev_passes.resize(t->ev_used + 1);
+        t->ev_passes[t->ev_used] = (B + bt - 1) / bt;
         t->ev_used++;
     }
-    hipLaunchKernelGGL(k_score_merge, dim3(B), dim3(64), 0, st, reinterpret_cast<const Partial *>(t->d_part),
-                       t->chunks, orders, B, t->n, lse, maxs, best, node_lse, node_second);
+    hipLaunchKernelGGL(k_merge, dim3(B), dim3(kMergeWaves * 64), 0, st, A);
     BNOS_HIP(hipGetLastError());
     return BNOS_OK;
 }
@@ -380,10 +468,12 @@ extern "C" bnos_status bnos_table_timing(bnos_table h, int32_t enable)
     t->ev_used = 0;
     t->timed_ms = 0.0;
     t->timed_launches = 0;
+    t->timed_passes = 0;
     return BNOS_OK;
 }
 
-extern "C" bnos_status bnos_table_timing_read(bnos_table h, double *total_ms, int64_t *launches)
+extern "C" bnos_status bnos_table_timing_read(bnos_table h, double *total_ms, int64_t *launches,
+                                              int64_t *table_passes)
 {
     TableT *t = reinterpret_cast<TableT *>(h);
     if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
@@ -393,9 +483,11 @@ extern "C" bnos_status bnos_table_timing_read(bnos_table h, double *total_ms, in
         BNOS_HIP(hipEventElapsedTime(&ms, t->ev_start[k], t->ev_stop[k]));
         t->timed_ms += ms;
         t->timed_launches += 1;
+        t->timed_passes += t->ev_passes[k];
     }
     t->ev_used = 0;
     if (total_ms) *total_ms = t->timed_ms;
     if (launches) *launches = t->timed_launches;
+    if (table_passes) *table_passes = t->timed_passes;
     return BNOS_OK;
 }

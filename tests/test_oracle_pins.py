@@ -401,3 +401,21 @@ def test_chain_best_graph_record_is_max_over_accepted_orders():
     assert res["best_score"] == best
     assert [int(v) for v in res["best_graph"]] == [int(v) for v in bg]
     assert res["accepted"] == int(res["acc"].sum())
+
+
+def test_row_and_node_scoring_agree_with_full_table():
+    arities = [2, 3, 2, 4, 2, 3]
+    data = tiny_data(6, 70, arities, seed=31)
+    K = 3
+    table = oracle.build_table(data, arities, K)
+    order = [2, 5, 0, 4, 1, 3]
+    lse, mx, best, nl, nb, ns = oracle.score_order(table, K, order)
+    pred = 0
+    for v in order:
+        row = oracle.build_row(data, arities, K, v)
+        assert np.array_equal(row, table[v])
+        l, b, bm, s = oracle.score_node_row(row, 6, K, v, pred)
+        assert (l, b, bm, s) == (nl[v], nb[v], int(best[v]), ns[v])
+        d = oracle.score_node_direct(data, arities, K, v, pred)
+        assert d == (l, b, bm, s)
+        pred |= 1 << v
