@@ -151,6 +151,61 @@ bnos_status bnos_score_order(bnos_table t, const int32_t *order, double *lse, do
                              uint64_t *best_parents);
 
 /*
+ * Metropolis-Hastings over orders (Sec. III.C), many chains at once.
+ *
+ * Iteration t = 0 adopts each chain's initial order (a uniform permutation:
+ * Fisher-Yates from the identity with j drawn for p = n-1..1).  Every
+ * iteration t >= 1 swaps two distinct positions drawn uniformly, scores the
+ * new order on the table, and accepts iff ln u < new - old (u uniform in
+ * (0,1)); the best-graph record starts from the initial order's greedy graph
+ * and is replaced, after an accepted move, when the new order's max score
+ * (Eq. (6)) is strictly larger.  All C proposals of an iteration are scored
+ * in one pass over the table; sweep_len iterations are captured in one HIP
+ * graph and replayed.
+ *
+ * Random numbers: one 64-bit draw per (seed, chain, purpose, step) from the
+ * SplitMix64 finalizer mix(z) (Steele, Lea & Flood 2014):
+ *   key = mix(seed ^ mix(chain*8 + purpose + 1)),
+ *   draw = mix(key + (step+1) * 0x9E3779B97F4A7C15);
+ * purposes 0 = initial shuffle (step = p), 1/2 = first/second swap position,
+ * 3 = acceptance uniform; integers in [0,m) are ((draw >> 32) * m) >> 32; the
+ * second position y in [0,n-1) is shifted past the first (y >= x -> y+1);
+ * u = ((draw >> 11) + 0.5) * 2^-53.  The chain id is chain_offset + c.
+ */
+typedef struct {
+    int32_t chains;           /* C, 1..65536 */
+    int32_t target;           /* 0: log-sum-exp order score; 1: max order score (Eq. (6)) */
+    int64_t iterations;       /* MH iterations to run in this call, >= 0 */
+    int64_t first_iteration;  /* 0: fresh start; k > 0: resume, the state holds the chains after
+                                 iteration k and this call runs k+1 .. k+iterations */
+    uint64_t seed;
+    int64_t chain_offset;     /* chain c draws from RNG stream chain_offset + c */
+    int32_t trace_every;      /* >= 1; trace entry j is the score after iteration
+                                 first_iteration + j*trace_every, j = 0..iterations/trace_every */
+    int32_t sweep_len;        /* iterations per captured graph; 0 = 32 */
+    int32_t reserved[6];      /* must be zero */
+} bnos_chain_cfg;
+
+typedef struct {              /* DEVICE pointers; the chain state, read when resuming, written always */
+    int32_t *orders;          /* [C][n] current order of each chain */
+    double *scores;           /* [C] target score of the current order */
+    uint64_t *best_graphs;    /* [C][n] best graph seen: parent mask per node id */
+    double *best_scores;      /* [C] max score (Eq. (6)) of the best graph's order */
+    int64_t *accepted;        /* [C] accepted moves since iteration 0 */
+    double *trace;            /* [C][iterations/trace_every + 1] or NULL */
+    uint8_t *accept_flags;    /* [C][iterations] or NULL: move of iteration first_iteration+1+k accepted */
+} bnos_chain_state;
+
+/*
+ * Run cfg->iterations MH iterations of C chains on `stream` and return when
+ * they have completed.  The library allocates a per-call workspace
+ * (proposal orders and scores, plus the table's scoring partials for C
+ * orders) and frees the per-call part before returning.
+ */
+bnos_status bnos_run_chains(bnos_table t, const bnos_chain_cfg *cfg, bnos_chain_state *state,
+                            void *stream);
+
+/*
  * Kernel timing for measurement: while enabled, every order-scoring launch
  * of this table is bracketed by HIP events recorded on the launch stream.
  * bnos_table_timing_read waits for the recorded events and returns the sum of

@@ -34,6 +34,17 @@ class BuildOpts(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 7)]
 
 
+class ChainCfg(ctypes.Structure):
+    _fields_ = [("chains", ctypes.c_int32), ("target", ctypes.c_int32), ("iterations", ctypes.c_int64),
+                ("first_iteration", ctypes.c_int64), ("seed", ctypes.c_uint64), ("chain_offset", ctypes.c_int64),
+                ("trace_every", ctypes.c_int32), ("sweep_len", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
+class ChainState(ctypes.Structure):
+    _fields_ = [("orders", P), ("scores", P), ("best_graphs", P), ("best_scores", P), ("accepted", P),
+                ("trace", P), ("accept_flags", P)]
+
+
 _SIGS = {
     "bnos_last_error": (ctypes.c_char_p, []),
     "bnos_version": (i32, []),
@@ -44,6 +55,7 @@ _SIGS = {
     "bnos_counts": (i32, [P, i32, P, P, P, i64]),
     "bnos_score_orders": (i32, [P, P, i32, P, P, P, P, P, P]),
     "bnos_score_order": (i32, [P, P, P, P, P]),
+    "bnos_run_chains": (i32, [P, P, P, P]),
     "bnos_table_timing": (i32, [P, i32]),
     "bnos_table_timing_read": (i32, [P, P, P, P]),
 }
@@ -153,6 +165,48 @@ class Table:
         best = np.zeros(self.n, dtype=np.uint64)
         _check(_lib.bnos_score_order(self._h, _ptr(order), ctypes.byref(lse), ctypes.byref(mx), _ptr(best)))
         return lse.value, mx.value, best
+
+    # -- chains
+    def new_chain_state(self, chains: int, iterations: int, trace_every: int = 1, flags: bool = False,
+                        device=None):
+        """Device tensors holding the state of `chains` chains (see bnos_chain_state)."""
+        import torch
+        dev = device or torch.device("cuda")
+        n = self.n
+        st = dict(
+            orders=torch.zeros((chains, n), dtype=torch.int32, device=dev),
+            scores=torch.zeros(chains, dtype=torch.float64, device=dev),
+            best_graphs=torch.zeros((chains, n), dtype=torch.int64, device=dev),
+            best_scores=torch.zeros(chains, dtype=torch.float64, device=dev),
+            accepted=torch.zeros(chains, dtype=torch.int64, device=dev),
+            trace=(torch.zeros((chains, iterations // trace_every + 1), dtype=torch.float64, device=dev)
+                   if trace_every > 0 else None),
+            accept_flags=torch.zeros((chains, max(iterations, 1)), dtype=torch.uint8, device=dev) if flags else None,
+        )
+        return st
+
+    def run_chains(self, state: dict, iterations: int, seed: int, target: int = 0, first_iteration: int = 0,
+                   trace_every: int = 1, chain_offset: int = 0, sweep_len: int = 0, stream=None):
+        """Run MH chains in place on `state` (from new_chain_state); returns when done."""
+        chains = int(state["orders"].shape[0])
+        cfg = ChainCfg()
+        cfg.chains = chains
+        cfg.target = target
+        cfg.iterations = iterations
+        cfg.first_iteration = first_iteration
+        cfg.seed = seed
+        cfg.chain_offset = chain_offset
+        cfg.trace_every = max(1, trace_every)
+        cfg.sweep_len = sweep_len
+        st = ChainState()
+        for k in ("orders", "scores", "best_graphs", "best_scores", "accepted", "trace", "accept_flags"):
+            v = state.get(k)
+            setattr(st, k, None if v is None else v.data_ptr())
+        if state.get("trace") is not None and state["trace"].shape[1] < iterations // cfg.trace_every + 1:
+            raise ValueError("trace tensor too small")
+        if state.get("accept_flags") is not None and state["accept_flags"].shape[1] < iterations:
+            raise ValueError("accept_flags tensor too small")
+        _check(_lib.bnos_run_chains(self._h, ctypes.byref(cfg), ctypes.byref(st), _stream(stream)))
 
     # -- timing
     def timing(self, enable: bool):

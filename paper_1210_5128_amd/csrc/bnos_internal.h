@@ -60,6 +60,9 @@ struct TableT {
     std::vector<int64_t> ev_passes;     // table passes of each recorded launch
     int64_t timed_passes = 0;
 
+    // orders per scoring block picked by the autotuner per batch bucket (0 = default rule)
+    int tuned_bt[5] = {0, 0, 0, 0, 0};
+
     int64_t device_bytes() const;
     int64_t workspace_bytes_per_order() const
     {

@@ -1,0 +1,329 @@
+// Device code of order scoring shared by the scoring and the chain kernels:
+// per-entry fold (online log-sum-exp + top-2 argmax), fixed-order merges,
+// predecessor masks, the streaming kernel k_score<BT> and the per-order merge.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "bnos_internal.h"
+
+namespace bnos {
+
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ device helpers
+
+struct Acc {
+    float m, s;       // log-sum-exp state: max and sum of exp(x - m)
+    float best, sec;  // top-1 score and best score among the other entries
+    uint64_t bm;      // mask of the top-1 entry
+};
+
+__device__ __forceinline__ void acc_init(Acc &a)
+{
+    a.m = -INFINITY;
+    a.s = 0.f;
+    a.best = -INFINITY;
+    a.sec = -INFINITY;
+    a.bm = ~0ull;
+}
+
+// Fold one consistent entry (x, mask) into the state.  Argmax tie rule: the
+// larger score wins; on equal scores the smaller mask wins.  Called under a
+// divergent branch on consistency, so a wavefront whose lanes hold no
+// consistent entry skips it entirely.
+__device__ __forceinline__ void acc_push(Acc &a, float x, uint64_t mk)
+{
+    float d = x - a.m;
+    float e = __expf(-fabsf(d));
+    a.s = (d > 0.f) ? fmaf(a.s, e, 1.f) : a.s + e;
+    a.m = fmaxf(a.m, x);
+    if (x >= a.sec) {
+        bool better = x > a.best || (x == a.best && mk < a.bm);
+        a.sec = better ? a.best : fmaxf(a.sec, x);
+        a.best = better ? x : a.best;
+        a.bm = better ? mk : a.bm;
+    }
+}
+
+// Combine two states (order-independent up to FP32 rounding; the callers fix the order).
+__device__ __forceinline__ void acc_merge(Acc &a, const Acc &b)
+{
+    float M = fmaxf(a.m, b.m);
+    float sa = (a.m == -INFINITY) ? 0.f : a.s * __expf(a.m - M);
+    float sb = (b.m == -INFINITY) ? 0.f : b.s * __expf(b.m - M);
+    a.m = M;
+    a.s = sa + sb;
+    bool take = b.best > a.best || (b.best == a.best && b.bm < a.bm);
+    float sec = take ? fmaxf(a.best, b.sec) : fmaxf(a.sec, b.best);
+    a.best = take ? b.best : a.best;
+    a.bm = take ? b.bm : a.bm;
+    a.sec = sec;
+}
+
+__device__ __forceinline__ Acc acc_shfl_xor(const Acc &a, int off)
+{
+    Acc b;
+    b.m = __shfl_xor(a.m, off, 64);
+    b.s = __shfl_xor(a.s, off, 64);
+    b.best = __shfl_xor(a.best, off, 64);
+    b.sec = __shfl_xor(a.sec, off, 64);
+    b.bm = (uint64_t)__shfl_xor((unsigned long long)a.bm, off, 64);
+    return b;
+}
+
+// Butterfly merge over the 64 lanes.  In every pair the lower lane's state is
+// the left operand, so both lanes compute the same value and the result does
+// not depend on scheduling.
+__device__ __forceinline__ void acc_wave_reduce(Acc &a, int lane)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        Acc o = acc_shfl_xor(a, off);
+        const bool upper = (lane & off) != 0;
+        Acc lo, hi;
+        lo.m = upper ? o.m : a.m;
+        hi.m = upper ? a.m : o.m;
+        lo.s = upper ? o.s : a.s;
+        hi.s = upper ? a.s : o.s;
+        lo.best = upper ? o.best : a.best;
+        hi.best = upper ? a.best : o.best;
+        lo.sec = upper ? o.sec : a.sec;
+        hi.sec = upper ? a.sec : o.sec;
+        lo.bm = upper ? o.bm : a.bm;
+        hi.bm = upper ? a.bm : o.bm;
+        acc_merge(lo, hi);
+        a = lo;
+    }
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v, int lane)
+{
+    // fixed butterfly: the lower lane's value is the left operand
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        double o = __shfl_xor(v, off, 64);
+        v = (lane & off) ? (o + v) : (v + o);
+    }
+    return v;
+}
+
+// Predecessor mask of `node` in an order, computed by one wavefront (lane p
+// reads position p).  valid = the order is a permutation of 0..n-1.
+__device__ __forceinline__ uint64_t wave_pred(const int32_t *__restrict__ ord, int n, int node,
+                                              int lane, bool &valid)
+{
+    int v = (lane < n) ? ord[lane] : -1;
+    bool inr = (v >= 0 && v < n);
+    uint64_t bit = inr ? (1ull << v) : 0ull;
+    uint64_t here = __ballot(lane < n && v == node);
+    int pos = here ? __builtin_ctzll(here) : 0;
+    uint64_t before = (lane < pos) ? bit : 0ull;
+    uint64_t all = bit;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        before |= (uint64_t)__shfl_xor((unsigned long long)before, off, 64);
+        all |= (uint64_t)__shfl_xor((unsigned long long)all, off, 64);
+    }
+    uint64_t full = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
+    valid = (all == full) && (__ballot(lane < n && !inr) == 0ull);
+    return valid ? before : 0ull;
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// ------------------------------------------------------------------ kernel
+
+struct ScoreArgs {
+    const uint64_t *masks;
+    const float *scores;
+    int64_t S_pad;
+    int chunks, chunk_entries;
+    const int32_t *orders;
+    int B, n;
+    Partial *part;          // [B][n][chunks]
+    double *lse, *maxs;
+    uint64_t *best;
+    double *node_lse;
+    float *node_second;
+};
+
+// Grid: x = node * chunks + chunk, y = group of BT orders.  Every block
+// streams one chunk of one node's entries once, folds each entry into BT order
+// states and writes one Partial per order.
+template <int BT>
+__global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
+{
+    __shared__ uint64_t s_npred[BT];
+    __shared__ Acc s_red[kScoreThreads / 64][BT];
+    const int node = blockIdx.x / A.chunks;
+    const int chunk = blockIdx.x - node * A.chunks;
+    const int b0 = blockIdx.y * BT;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int n = A.n;
+
+    for (int j = wave; j < BT; j += kScoreThreads / 64) {
+        uint64_t np = ~0ull;   // no order in this slot: nothing is consistent
+        if (b0 + j < A.B) {
+            bool valid;
+            uint64_t pred = wave_pred(A.orders + (int64_t)(b0 + j) * n, n, node, lane, valid);
+            np = ~pred;        // invalid order: only the empty set is consistent
+        }
+        if (lane == 0) s_npred[j] = np;
+    }
+    __syncthreads();
+    uint64_t npred[BT];
+    Acc a[BT];
+#pragma unroll
+    for (int j = 0; j < BT; ++j) {
+        npred[j] = uniform_u64(s_npred[j]);
+        acc_init(a[j]);
+    }
+
+    const int64_t row = (int64_t)node * A.S_pad + (int64_t)chunk * A.chunk_entries;
+    const u64x2 *mp = reinterpret_cast<const u64x2 *>(A.masks + row);
+    const f32x4 *sp = reinterpret_cast<const f32x4 *>(A.scores + row);
+    const int steps = A.chunk_entries / kEntriesPerStep;
+    // Software pipeline: the loads of step it+1 are in flight while step it is folded.
+    int q = threadIdx.x;                                     // this lane's 4-entry group
+    u64x2 n01 = __builtin_nontemporal_load(&mp[2 * q]);
+    u64x2 n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
+    f32x4 nsc = __builtin_nontemporal_load(&sp[q]);
+    for (int it = 0; it < steps; ++it) {
+        const u64x2 m01 = n01, m23 = n23;
+        const f32x4 sc = nsc;
+        if (it + 1 < steps) {
+            q += kScoreThreads;
+            n01 = __builtin_nontemporal_load(&mp[2 * q]);
+            n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
+            nsc = __builtin_nontemporal_load(&sp[q]);
+        }
+        const uint64_t mk[4] = {m01.x, m01.y, m23.x, m23.y};
+        const float x[4] = {sc.x, sc.y, sc.z, sc.w};
+#pragma unroll
+        for (int j = 0; j < BT; ++j) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if ((mk[k] & npred[j]) == 0ull) acc_push(a[j], x[k], mk[k]);
+            }
+        }
+    }
+
+#pragma unroll
+    for (int j = 0; j < BT; ++j) {
+        acc_wave_reduce(a[j], lane);
+        if (lane == 0) s_red[wave][j] = a[j];
+    }
+    __syncthreads();
+    if (threadIdx.x < BT) {
+        const int j = threadIdx.x;
+        if (b0 + j < A.B) {
+            Acc r;
+            r.m = s_red[0][j].m;
+            r.s = s_red[0][j].s;
+            r.best = s_red[0][j].best;
+            r.sec = s_red[0][j].sec;
+            r.bm = s_red[0][j].bm;
+#pragma unroll
+            for (int w = 1; w < kScoreThreads / 64; ++w) {
+                Acc o;
+                o.m = s_red[w][j].m;
+                o.s = s_red[w][j].s;
+                o.best = s_red[w][j].best;
+                o.sec = s_red[w][j].sec;
+                o.bm = s_red[w][j].bm;
+                acc_merge(r, o);
+            }
+            Partial p;
+            p.m = r.m;
+            p.s = r.s;
+            p.best = r.best;
+            p.second = r.sec;
+            p.bmask = r.bm;
+            A.part[((int64_t)(b0 + j) * n + node) * A.chunks + chunk] = p;
+        }
+    }
+}
+
+constexpr int kMergeWaves = 16;
+constexpr int kMergeNodesPerWave = 4;   // 16 waves x 4 nodes covers n <= 64
+
+__device__ __forceinline__ Acc load_partial(const Partial *p)
+{
+    Acc a;
+    a.m = p->m;
+    a.s = p->s;
+    a.best = p->best;
+    a.sec = p->second;
+    a.bm = p->bmask;
+    return a;
+}
+
+// Merge of one order's chunk partials, run by a whole block of kMergeWaves
+// wavefronts.  Wave w merges nodes w, w+16, w+32, w+48 (lanes over chunks,
+// every node's first partial loaded before any merging so the loads overlap,
+// then a fixed butterfly); lane 0 forms LSE_i = m + ln s in FP64 and writes the
+// node outputs.  Wave 0 then sums the per-node terms in FP64 with a fixed
+// butterfly; the sums are valid in lane 0 of wave 0.
+__device__ __forceinline__ void merge_block(const ScoreArgs &A, int b, double *s_l, double *s_b,
+                                            bool &valid, double &lse_out, double &max_out)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int n = A.n;
+    const int chunks = A.chunks;
+    (void)wave_pred(A.orders + (int64_t)b * n, n, 0, lane, valid);
+
+    Acc r[kMergeNodesPerWave];
+#pragma unroll
+    for (int k = 0; k < kMergeNodesPerWave; ++k) {
+        const int i = wave + kMergeWaves * k;
+        acc_init(r[k]);
+        if (i < n && lane < chunks) r[k] = load_partial(A.part + ((int64_t)b * n + i) * chunks + lane);
+    }
+#pragma unroll
+    for (int k = 0; k < kMergeNodesPerWave; ++k) {
+        const int i = wave + kMergeWaves * k;
+        if (i >= n) break;
+        const Partial *pp = A.part + ((int64_t)b * n + i) * chunks;
+        for (int c = lane + 64; c < chunks; c += 64) acc_merge(r[k], load_partial(pp + c));
+        acc_wave_reduce(r[k], lane);
+        if (lane == 0) {
+            const double li = (double)r[k].m + log((double)r[k].s);
+            const int64_t o = (int64_t)b * n + i;
+            s_l[i] = li;
+            s_b[i] = (double)r[k].best;
+            A.best[o] = valid ? r[k].bm : 0ull;
+            if (A.node_lse) A.node_lse[o] = valid ? li : NAN;
+            if (A.node_second) A.node_second[o] = valid ? r[k].sec : NAN;
+        }
+    }
+    __syncthreads();
+    lse_out = 0.0;
+    max_out = 0.0;
+    if (wave == 0) {
+        double l = (lane < n) ? s_l[lane] : 0.0;
+        double m = (lane < n) ? s_b[lane] : 0.0;
+        lse_out = wave_sum_f64(l, lane);
+        max_out = wave_sum_f64(m, lane);
+    }
+}
+
+// ---- host-side helpers (score.hip)
+int pick_bt(const TableT *t, int B);
+bnos_status ensure_workspace(TableT *t, int B);
+ScoreArgs score_args(const TableT *t, const int32_t *orders, int B, double *lse, double *maxs,
+                     uint64_t *best, double *node_lse, float *node_second);
+bnos_status launch_stream(TableT *t, const ScoreArgs &A, hipStream_t st, int bt);
+
+}  // namespace bnos

@@ -1,0 +1,201 @@
+"""GPU Metropolis-Hastings chains against the oracle chain on the same RNG stream.
+
+The two sides take every accept decision from their own scores; a decision
+may legitimately differ only where the oracle's |ln u - delta| is within
+TAU of the threshold (the FP32 table and FP32 sums move delta by ~1e-5).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_1210_5128_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+TAU = 1e-3
+REL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def bnos():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1210_5128_amd import bnos as b
+    return b
+
+
+def gpu_chains(table, chains, iters, seed, target=0, sweep_len=0, chain_offset=0):
+    st = table.new_chain_state(chains, iters, trace_every=1, flags=True)
+    table.run_chains(st, iters, seed, target=target, sweep_len=sweep_len, chain_offset=chain_offset)
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if v is not None else None) for k, v in st.items()}
+
+
+def oracle_replay_delta(orc, K, seed, chain, t, res, target):
+    """The oracle's (ln u, delta) at iteration t of its own chain `res`."""
+    n = orc.shape[0]
+    cur = list(oracle.initial_order(seed, chain, n))
+    for s in range(1, t):
+        if res["acc"][s - 1]:
+            a, b = oracle.swap_pair(seed, chain, n, s)
+            cur[a], cur[b] = cur[b], cur[a]
+    a, b = oracle.swap_pair(seed, chain, n, t)
+    prop = list(cur)
+    prop[a], prop[b] = prop[b], prop[a]
+    l, m, *_ = oracle.score_order(orc, K, prop, round_f32=True)
+    new = l if target == 0 else m
+    return math.log(oracle.accept_uniform(seed, chain, t)), new - res["trace"][t - 1]
+
+
+def compare_chains(g, orc, K, seed, iters, target, chain_offset=0):
+    full = 0
+    C = g["orders"].shape[0]
+    for c in range(C):
+        chain = chain_offset + c
+        res = oracle.run_chain(orc, K, seed, chain, iters, target=target, round_f32=True)
+        flags = g["accept_flags"][c, :iters].astype(bool)
+        mism = np.nonzero(flags != res["acc"].astype(bool))[0]
+        if len(mism):
+            t = int(mism[0]) + 1
+            lu, d = oracle_replay_delta(orc, K, seed, chain, t, res, target)
+            assert abs(lu - d) <= TAU, (c, t, lu, d)
+            np.testing.assert_allclose(g["trace"][c, :t], res["trace"][:t], rtol=REL)
+            continue
+        full += 1
+        np.testing.assert_allclose(g["trace"][c, :iters + 1], res["trace"], rtol=REL, atol=1e-6)
+        assert list(g["orders"][c]) == list(res["order"]), c
+        assert [int(x) for x in g["best_graphs"][c].view(np.uint64)] == [int(x) for x in res["best_graph"]], c
+        assert abs(g["best_scores"][c] - res["best_score"]) <= REL * max(1.0, abs(res["best_score"]))
+        assert int(g["accepted"][c]) == res["accepted"]
+        assert abs(g["scores"][c] - res["trace"][-1]) <= REL * max(1.0, abs(res["trace"][-1]))
+    return full
+
+
+@pytest.fixture(scope="module")
+def tiny8(bnos):
+    w = datagen.WORKLOADS["tiny8"]
+    net, prior = datagen.make(w)
+    t = bnos.build_score_table(net.data, net.arities, w.K, prior=prior)
+    orc = oracle.build_table(net.data, net.arities, w.K, prior=prior)
+    yield w, t, orc
+    t.free()
+
+
+@pytest.fixture(scope="module")
+def prior20(bnos):
+    w = datagen.WORKLOADS["prior20"]
+    net, prior = datagen.make(w)
+    t = bnos.build_score_table(net.data, net.arities, w.K, prior=prior)
+    orc = oracle.build_table(net.data, net.arities, w.K, prior=prior)
+    yield w, t, orc
+    t.free()
+
+
+def test_chains_match_oracle_tiny8_lse(bnos, tiny8):
+    w, t, orc = tiny8
+    iters, C = 2000, 12
+    g = gpu_chains(t, C, iters, seed=100)
+    full = compare_chains(g, orc, w.K, 100, iters, 0)
+    assert full >= C - 1
+
+
+def test_chains_match_oracle_prior20_max_target(bnos, prior20):
+    w, t, orc = prior20
+    iters, C = 400, 6
+    g = gpu_chains(t, C, iters, seed=101, target=1, chain_offset=7)
+    full = compare_chains(g, orc, w.K, 101, iters, 1, chain_offset=7)
+    assert full >= C - 1
+
+
+def test_chains_prior20_lse(bnos, prior20):
+    w, t, orc = prior20
+    iters, C = 600, 5
+    g = gpu_chains(t, C, iters, seed=102)
+    assert compare_chains(g, orc, w.K, 102, iters, 0) >= C - 1
+
+
+def test_resume_and_graph_shapes_are_bitwise_identical(bnos, tiny8):
+    w, t, orc = tiny8
+    C, iters = 9, 301
+    ref = gpu_chains(t, C, iters, seed=5, sweep_len=0)
+    for sl in (1, 7, 1000):
+        g = gpu_chains(t, C, iters, seed=5, sweep_len=sl)
+        for k in ("orders", "scores", "best_graphs", "best_scores", "accepted", "trace", "accept_flags"):
+            assert np.array_equal(g[k], ref[k]), (sl, k)
+    # resume: 120 iterations, then 181 more from the saved state
+    st = t.new_chain_state(C, 120, trace_every=1, flags=True)
+    t.run_chains(st, 120, 5)
+    st2 = dict(st)
+    st2["trace"] = torch.zeros((C, 182), dtype=torch.float64, device="cuda")
+    st2["accept_flags"] = torch.zeros((C, 181), dtype=torch.uint8, device="cuda")
+    t.run_chains(st2, 181, 5, first_iteration=120)
+    torch.cuda.synchronize()
+    for k in ("orders", "scores", "best_graphs", "best_scores", "accepted"):
+        assert np.array_equal(st2[k].cpu().numpy(), ref[k]), k
+    assert np.array_equal(st["accept_flags"].cpu().numpy()[:, :120], ref["accept_flags"][:, :120])
+    assert np.array_equal(st2["accept_flags"].cpu().numpy(), ref["accept_flags"][:, 120:301])
+    assert np.array_equal(st2["trace"].cpu().numpy(), ref["trace"][:, 120:302])
+
+
+def test_gpu_chains_sample_the_exact_order_posterior(bnos):
+    # n = 4: 24 orders; many short independent chains, final states vs exact P(order)
+    rng = np.random.default_rng(12)
+    arities = [2, 2, 3, 2]
+    data = np.stack([rng.integers(0, a, size=12) for a in arities], axis=1).astype(np.int8)
+    K = 3
+    t = bnos.build_score_table(data, arities, K)
+    orc = oracle.build_table(data, arities, K)
+    for target in (0, 1):
+        orders = list(itertools.permutations(range(4)))
+        sc = np.array([oracle.score_order(orc, K, o)[target] for o in orders])
+        post = np.exp(sc - sc.max())
+        post /= post.sum()
+        C = 32768
+        st = t.new_chain_state(C, 200, trace_every=200)
+        t.run_chains(st, 200, seed=77 + target, target=target, trace_every=200)
+        fin = st["orders"].cpu().numpy()
+        idx = {o: k for k, o in enumerate(orders)}
+        freq = np.zeros(24)
+        for row in fin:
+            freq[idx[tuple(int(v) for v in row)]] += 1
+        freq /= C
+        tv = 0.5 * np.abs(freq - post).sum()
+        assert tv < 0.03, (target, tv)
+    t.free()
+
+
+def test_chain_validation(bnos, tiny8):
+    w, t, orc = tiny8
+    st = t.new_chain_state(2, 10)
+    with pytest.raises(bnos.BnosError) as e:
+        t.run_chains(st, 10, 1, target=3)
+    assert e.value.status == bnos.E_INVALID
+    with pytest.raises(bnos.BnosError) as e:
+        t.run_chains(st, -1, 1)
+    assert e.value.status == bnos.E_RANGE
+
+
+def test_mixed60_chain_properties(bnos):
+    w = datagen.WORKLOADS["mixed60"]
+    net, prior = datagen.make(w)
+    t = bnos.build_score_table(net.data, net.arities, w.K, prior=prior)
+    C, iters = 16, 60
+    st = t.new_chain_state(C, iters, trace_every=1, flags=True)
+    t.run_chains(st, iters, seed=9)
+    g = {k: v.cpu().numpy() for k, v in st.items() if v is not None}
+    for c in range(C):
+        assert sorted(g["orders"][c]) == list(range(60))
+        l, m, best = t.score_order(g["orders"][c])
+        assert abs(l - g["scores"][c]) <= REL * abs(l)
+        assert int(g["accepted"][c]) == int(g["accept_flags"][c].sum())
+        # the record starts at the initial order's max score and never decreases
+        init = oracle.initial_order(9, c, 60)
+        l0, m0, _ = t.score_order(init)
+        assert abs(l0 - g["trace"][c, 0]) <= REL * abs(l0)
+        assert g["best_scores"][c] >= m0
+    t.free()
