@@ -103,6 +103,37 @@ def measured_traffic(batch: int):
     return float(rec["bytes_per_launch"])
 
 
+def bench_chains(bnos, datagen, wname: str, chains: int, iters: int, seed: int = 102):
+    """Batched MH chains vs one chain on the same table: iterations/s and ESS/s of the
+    log-sum-exp score trace (Geyer initial-monotone ESS after 20% burn-in, summed over chains)."""
+    import torch
+    from paper_1210_5128_amd import ess as E
+    w = datagen.WORKLOADS[wname]
+    net, prior = datagen.make(w)
+    table = bnos.build_score_table(net.data, net.arities, w.K, ess=w.ess, prior=prior)
+    out = {"workload": f"{w.name}: n={w.n}, K={w.K}, N={w.N}", "iterations": iters}
+    for label, C in (("batched", chains), ("single", 1)):
+        st = table.new_chain_state(C, iters, trace_every=1)
+        table.run_chains(st, min(iters, 50), seed + 1000, sweep_len=32)     # warm-up (separate seed)
+        torch.cuda.synchronize()
+        st = table.new_chain_state(C, iters, trace_every=1)
+        t0 = time.perf_counter()
+        table.run_chains(st, iters, seed, sweep_len=32)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tr = st["trace"].cpu().numpy()
+        e = E.ess(tr)
+        out[label] = {"chains": C, "seconds": dt, "chain_iterations_per_s": C * iters / dt,
+                      "ess": e, "ess_per_s": e / dt,
+                      "accept_rate": float(st["accepted"].sum().item()) / (C * iters),
+                      "best_score_max": float(st["best_scores"].max().item()),
+                      "split_rhat": E.split_rhat(tr) if C > 1 else None}
+        print(f"# chains {label}: {C}x{iters} in {dt:.2f} s, ESS/s {e / dt:.1f}", file=sys.stderr, flush=True)
+    out["ess_per_s_ratio_batched_vs_single"] = out["batched"]["ess_per_s"] / max(out["single"]["ess_per_s"], 1e-30)
+    table.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +145,8 @@ def main():
                     help="also time steps of this many orders (0 = skip); reported under 'batched'")
     ap.add_argument("--workload", default="mixed60")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--chains", type=int, default=256, help="batched chains on the mixed40 table (0 = skip)")
+    ap.add_argument("--chain-iters", type=int, default=20000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (scale for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -231,6 +264,8 @@ def main():
         "paper_context": {"order_scores_per_s_n60": 2.92, "hardware": "Tesla M2090 (Fermi), 2012",
                           "note": "per-iteration time 0.3427 s at n=60, s=4; its data are not described"},
     }
+    if args.chains:
+        out["chains"] = bench_chains(bnos, datagen, "mixed40", args.chains, args.chain_iters)
     if not args.no_cpu:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(net, prior, K)

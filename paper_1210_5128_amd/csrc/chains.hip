@@ -62,9 +62,14 @@ struct ChainArgs {
     double *score;             // [C] target score of the current order (state)
     double *best_score;        // [C] (state)
     uint64_t *best_graph;      // [C][n] (state)
-    uint64_t *prop_best;       // [C][n] greedy graph of the proposal
     int64_t *accepted;         // [C] (state)
     int64_t *t;                // [C] iteration whose proposal is being scored
+    double *node_l;            // [C][n] per-node log-sum-exp of the current order
+    double *node_m;            // [C][n] per-node best score of the current order
+    uint64_t *node_best;       // [C][n] per-node best parent set of the current order
+    uint64_t *wmask;           // [C] nodes whose predecessor set the proposal changes
+    int32_t *wl_count;         // [n] chains listing each node in their window
+    int32_t *wl_list;          // [n][C]
     double *trace;             // [C][trace_len] or null
     int trace_every;
     int64_t trace_len;
@@ -72,8 +77,11 @@ struct ChainArgs {
     int64_t iterations;
 };
 
-// Block per chain: the initial order (fresh start) or the first proposal after
-// the saved state (resume).
+__device__ __forceinline__ uint64_t all_nodes(int n) { return n == 64 ? ~0ull : ((1ull << n) - 1ull); }
+
+// Block per chain.  Fresh start: the initial order (iteration 0 adopts it).
+// Resume: the saved current order is re-scored first to rebuild the per-node
+// caches (same arithmetic, so the same values), then iteration t_first+1 follows.
 __global__ __launch_bounds__(64) void k_chain_init(ChainArgs H)
 {
     const int c = blockIdx.x;
@@ -91,85 +99,164 @@ __global__ __launch_bounds__(64) void k_chain_init(ChainArgs H)
                 ord[j] = tmp;
             }
             for (int p = 0; p < n; ++p) H.prop[(int64_t)c * n + p] = ord[p];
-            H.t[c] = 0;
             H.accepted[c] = 0;
         }
     } else {
-        const int64_t t1 = H.t_first + 1;
-        int a = 0, b = 0;
-        rng_pair(H.seed, chain, n, (uint64_t)t1, a, b);
-        if (lane < n) {
-            const int src = (lane == a) ? b : ((lane == b) ? a : lane);
-            H.prop[(int64_t)c * n + lane] = H.cur[(int64_t)c * n + src];
-        }
-        if (lane == 0) {
-            H.t[c] = t1;
-            if (H.trace) H.trace[(int64_t)c * H.trace_len] = H.score[c];
-        }
+        if (lane < n) H.prop[(int64_t)c * n + lane] = H.cur[(int64_t)c * n + lane];
+        if (lane == 0 && H.trace) H.trace[(int64_t)c * H.trace_len] = H.score[c];
+    }
+    if (lane == 0) {
+        H.t[c] = H.t_first;
+        H.wmask[c] = all_nodes(n);
     }
 }
 
-// Block per chain: merge the proposal's chunk partials, take the MH decision,
-// update the best-graph record, and write the next proposal.
+// Block per node: the chains whose proposal window contains the node, in chain
+// order (deterministic compaction).
+constexpr int kListThreads = 1024;
+__global__ __launch_bounds__(kListThreads) void k_worklist(ChainArgs H)
+{
+    __shared__ int s_wave[kListThreads / 64];
+    __shared__ int s_base;
+    const int node = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_base = 0;
+    __syncthreads();
+    for (int base = 0; base < H.C; base += kListThreads) {
+        const int c = base + threadIdx.x;
+        const bool act = c < H.C && ((H.wmask[c] >> node) & 1ull);
+        const uint64_t bal = __ballot(act);
+        const int rank = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) s_wave[wave] = __popcll(bal);
+        __syncthreads();
+        int off = s_base;
+        for (int w = 0; w < wave; ++w) off += s_wave[w];
+        if (act) H.wl_list[(int64_t)node * H.C + off + rank] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int w = 0; w < kListThreads / 64; ++w) tot += s_wave[w];
+            s_base += tot;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) H.wl_count[node] = s_base;
+}
+
+// Block per chain: merge the chunk partials of the window nodes, combine with
+// the cached values of the other nodes (per-order sums in node order with a
+// fixed butterfly, as a full rescoring would), take the MH decision, update
+// the caches and the best-graph record, and write the next proposal.
 __global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(ScoreArgs A, ChainArgs H)
 {
     __shared__ double s_l[64], s_b[64];
-    __shared__ int s_acc, s_imp, s_a, s_b2, s_next;
+    __shared__ uint64_t s_bm[64];
+    __shared__ int s_nodes[64];
+    __shared__ int s_cnt;
     const int c = blockIdx.x;
     const int n = H.n;
-    bool valid;
-    double l, m;
-    merge_block(A, c, s_l, s_b, valid, l, m);
-    if (threadIdx.x == 0) {
-        const uint64_t chain = (uint64_t)(H.chain0 + c);
-        const int64_t t = H.t[c];
-        const double nv = H.target ? m : l;
-        int acc = 0, imp = 0;
-        if (t == 0) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int chunks = A.chunks;
+    const uint64_t wm = H.wmask[c];
+    if (wave == 0) {
+        const bool in = lane < n && ((wm >> lane) & 1ull);
+        const uint64_t bal = __ballot(in);
+        if (in) s_nodes[__popcll(bal & ((1ull << lane) - 1ull))] = lane;
+        if (lane == 0) s_cnt = __popcll(bal);
+    }
+    __syncthreads();
+    const int cnt = s_cnt;
+    Acc r[kMergeNodesPerWave];
+#pragma unroll
+    for (int k = 0; k < kMergeNodesPerWave; ++k) {
+        const int q = wave + kMergeWaves * k;
+        acc_init(r[k]);
+        if (q < cnt && lane < chunks) r[k] = load_partial(A.part + ((int64_t)c * n + s_nodes[q]) * chunks + lane);
+    }
+#pragma unroll
+    for (int k = 0; k < kMergeNodesPerWave; ++k) {
+        const int q = wave + kMergeWaves * k;
+        if (q >= cnt) break;
+        const int i = s_nodes[q];
+        const Partial *pp = A.part + ((int64_t)c * n + i) * chunks;
+        for (int cc = lane + 64; cc < chunks; cc += 64) acc_merge(r[k], load_partial(pp + cc));
+        acc_wave_reduce(r[k], lane);
+        if (lane == 0) {
+            s_l[i] = (double)r[k].m + log((double)r[k].s);
+            s_b[i] = (double)r[k].best;
+            s_bm[i] = r[k].bm;
+        }
+    }
+    __syncthreads();
+    if (wave != 0) return;
+
+    const int64_t row = (int64_t)c * n;
+    const bool in = lane < n && ((wm >> lane) & 1ull);
+    const double li = lane < n ? (in ? s_l[lane] : H.node_l[row + lane]) : 0.0;
+    const double mi = lane < n ? (in ? s_b[lane] : H.node_m[row + lane]) : 0.0;
+    const double L = wave_sum_f64(li, lane);
+    const double M = wave_sum_f64(mi, lane);
+    const uint64_t chain = (uint64_t)(H.chain0 + c);
+    const int64_t t = H.t[c];
+    const double nv = H.target ? M : L;
+    int acc = 0, imp = 0;
+    if (lane == 0) {
+        if (t == H.t_first) {            // adopt the initial (or re-scored saved) order
             acc = 1;
-            imp = 1;
             H.score[c] = nv;
-            H.best_score[c] = m;
+            if (H.t_first == 0) {
+                imp = 1;
+                H.best_score[c] = M;
+                if (H.trace) H.trace[(int64_t)c * H.trace_len] = nv;
+            }
         } else {
             const double u = rng_unit_open(rng_draw(H.seed, chain, 3, (uint64_t)t));
             acc = log(u) < nv - H.score[c];
             if (acc) {
                 H.score[c] = nv;
                 H.accepted[c] += 1;
-                if (m > H.best_score[c]) {
-                    H.best_score[c] = m;
+                if (M > H.best_score[c]) {
+                    H.best_score[c] = M;
                     imp = 1;
                 }
             }
             if (H.flags) H.flags[(int64_t)c * H.iterations + (t - H.t_first - 1)] = (uint8_t)acc;
+            const int64_t k = t - H.t_first;
+            if (H.trace && k % H.trace_every == 0) H.trace[(int64_t)c * H.trace_len + k / H.trace_every] = H.score[c];
         }
-        const int64_t k = t - H.t_first;
-        if (H.trace && k % H.trace_every == 0) H.trace[(int64_t)c * H.trace_len + k / H.trace_every] = H.score[c];
-        const int64_t t1 = t + 1;
-        int a = 0, b = 0;
-        const int next = t1 <= H.t_last;
-        if (next) rng_pair(H.seed, chain, n, (uint64_t)t1, a, b);
-        H.t[c] = t1;
-        s_acc = acc;
-        s_imp = imp;
-        s_a = a;
-        s_b2 = b;
-        s_next = next;
     }
-    __syncthreads();
-    const int lane = threadIdx.x;
-    if (lane < 64) {
-        const int64_t row = (int64_t)c * n;
-        int32_t v = 0;
-        if (lane < n) {
-            v = s_acc ? H.prop[row + lane] : H.cur[row + lane];
+    acc = __shfl(acc, 0, 64);
+    imp = __shfl(imp, 0, 64);
+    int32_t v = 0;
+    if (lane < n) {
+        v = acc ? H.prop[row + lane] : H.cur[row + lane];
+        if (acc) {
             H.cur[row + lane] = v;
-            if (s_imp) H.best_graph[row + lane] = H.prop_best[row + lane];
+            H.node_l[row + lane] = li;
+            H.node_m[row + lane] = mi;
+            if (in) H.node_best[row + lane] = s_bm[lane];
         }
-        const int a = s_a, b = s_b2;
-        const int src = (lane == a) ? b : ((lane == b) ? a : lane);
-        const int32_t w = __shfl(v, src, 64);
-        if (s_next && lane < n) H.prop[row + lane] = w;
+    }
+    if (imp && lane < n) {
+        // node_best now holds the accepted order's greedy graph (this lane's entry)
+        H.best_graph[row + lane] = in ? s_bm[lane] : H.node_best[row + lane];
+    }
+    const int64_t t1 = t + 1;
+    const bool next = t1 <= H.t_last;
+    int a = 0, b = 0;
+    if (next) rng_pair(H.seed, chain, n, (uint64_t)t1, a, b);
+    const int src = (lane == a) ? b : ((lane == b) ? a : lane);
+    const int32_t w = __shfl(v, src, 64);
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    uint64_t bits = (next && lane >= lo && lane <= hi && lane < n) ? (1ull << v) : 0ull;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) bits |= (uint64_t)__shfl_xor((unsigned long long)bits, off, 64);
+    if (next && lane < n) H.prop[row + lane] = w;
+    if (lane == 0) {
+        H.t[c] = t1;
+        H.wmask[c] = bits;
     }
 }
 
@@ -198,31 +285,33 @@ extern "C" bnos_status bnos_run_chains(bnos_table h, const bnos_chain_cfg *cfg, 
         return BNOS_E_INVALID;
     }
     if (n < 2) { set_error("chains need n >= 2 (a swap needs two positions)"); return BNOS_E_RANGE; }
-    const bool fresh = cfg->first_iteration == 0;
-    // scoring steps: fresh runs t = 0..iterations, a resume runs t = first+1..first+iterations
-    const int64_t steps = fresh ? cfg->iterations + 1 : cfg->iterations;
-    if (steps == 0) return BNOS_OK;
+    // scoring steps: the adoption of the starting order (fresh: iteration 0; resume: the
+    // saved order, re-scored to rebuild the per-node caches) and one per iteration
+    if (cfg->iterations == 0 && cfg->first_iteration > 0) return BNOS_OK;
+    const int64_t steps = cfg->iterations + 1;
     hipStream_t us = reinterpret_cast<hipStream_t>(stream);
     BNOS_HIP(hipSetDevice(t->device));
     bnos_status s = ensure_workspace(t, C);
     if (s != BNOS_OK) return s;
 
-    // per-call workspace: proposals, their greedy graphs and scores, iteration counters
+    // per-call workspace: per-node caches, proposals, windows, work lists, iteration counters
     char *ws = nullptr;
-    const size_t b_prop = sizeof(int32_t) * (size_t)C * n;
-    const size_t b_pbest = sizeof(uint64_t) * (size_t)C * n;
-    const size_t b_pl = sizeof(double) * (size_t)C;
-    const size_t b_t = sizeof(int64_t) * (size_t)C;
-    hipError_t e = hipMalloc((void **)&ws, b_prop + b_pbest + 2 * b_pl + b_t + 256);
+    const size_t cn = (size_t)C * n;
+    const size_t bytes = cn * (8 + 8 + 8) + (size_t)C * (8 + 8) + cn * 4 + (size_t)n * C * 4 + (size_t)n * 4 + 256;
+    hipError_t e = hipMalloc((void **)&ws, bytes);
     if (e != hipSuccess) {
         set_error(std::string("hipMalloc chain workspace: ") + hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? BNOS_E_NOMEM : BNOS_E_DEVICE;
     }
-    uint64_t *prop_best = reinterpret_cast<uint64_t *>(ws);
-    double *prop_l = reinterpret_cast<double *>(ws + b_pbest);
-    double *prop_m = prop_l + C;
-    int64_t *tcount = reinterpret_cast<int64_t *>(ws + b_pbest + 2 * b_pl);
-    int32_t *prop = reinterpret_cast<int32_t *>(ws + b_pbest + 2 * b_pl + b_t);
+    char *p = ws;
+    double *node_l = reinterpret_cast<double *>(p);       p += cn * 8;
+    double *node_m = reinterpret_cast<double *>(p);       p += cn * 8;
+    uint64_t *node_best = reinterpret_cast<uint64_t *>(p); p += cn * 8;
+    uint64_t *wmask = reinterpret_cast<uint64_t *>(p);    p += (size_t)C * 8;
+    int64_t *tcount = reinterpret_cast<int64_t *>(p);     p += (size_t)C * 8;
+    int32_t *prop = reinterpret_cast<int32_t *>(p);       p += cn * 4;
+    int32_t *wl_list = reinterpret_cast<int32_t *>(p);    p += (size_t)n * C * 4;
+    int32_t *wl_count = reinterpret_cast<int32_t *>(p);
 
     ChainArgs H;
     H.n = n;
@@ -237,15 +326,22 @@ extern "C" bnos_status bnos_run_chains(bnos_table h, const bnos_chain_cfg *cfg, 
     H.score = st->scores;
     H.best_score = st->best_scores;
     H.best_graph = st->best_graphs;
-    H.prop_best = prop_best;
     H.accepted = st->accepted;
     H.t = tcount;
+    H.node_l = node_l;
+    H.node_m = node_m;
+    H.node_best = node_best;
+    H.wmask = wmask;
+    H.wl_count = wl_count;
+    H.wl_list = wl_list;
     H.trace = st->trace;
     H.trace_every = cfg->trace_every;
     H.trace_len = cfg->iterations / cfg->trace_every + 1;
     H.flags = st->accept_flags;
     H.iterations = cfg->iterations;
-    ScoreArgs A = score_args(t, prop, C, prop_l, prop_m, prop_best, nullptr, nullptr);
+    ScoreArgs A = score_args(t, prop, C, nullptr, nullptr, nullptr, nullptr, nullptr);
+    A.wl_count = wl_count;
+    A.wl_list = wl_list;
     const int bt = pick_bt(t, C);
 
     hipStream_t cs = nullptr;
@@ -261,6 +357,8 @@ extern "C" bnos_status bnos_run_chains(bnos_table h, const bnos_chain_cfg *cfg, 
     hipLaunchKernelGGL(k_chain_init, dim3(C), dim3(64), 0, us, H);
     CK(hipGetLastError());
     auto one_step = [&](hipStream_t q) -> bnos_status {
+        hipLaunchKernelGGL(k_worklist, dim3(n), dim3(kListThreads), 0, q, H);
+        BNOS_HIP(hipGetLastError());
         bnos_status r = launch_stream(t, A, q, bt);
         if (r != BNOS_OK) return r;
         hipLaunchKernelGGL(k_chain_step, dim3(C), dim3(kMergeWaves * 64), 0, q, A, H);

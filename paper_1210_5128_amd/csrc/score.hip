@@ -91,6 +91,8 @@ ScoreArgs score_args(const TableT *t, const int32_t *orders, int B, double *lse,
     A.best = best;
     A.node_lse = node_lse;
     A.node_second = node_second;
+    A.wl_count = nullptr;
+    A.wl_list = nullptr;
     return A;
 }
 

@@ -155,6 +155,10 @@ struct ScoreArgs {
     uint64_t *best;
     double *node_lse;
     float *node_second;
+    // Optional work list (chains): node i scores only the wl_count[i] orders listed
+    // in wl_list[i * B ...]; a block's slot j takes the (group*BT + j)-th listed order.
+    const int32_t *wl_count;   // [n] or null (then slot j of group g is order g*BT + j)
+    const int32_t *wl_list;    // [n][B]
 };
 
 // Grid: x = node * chunks + chunk, y = group of BT orders.  Every block
@@ -171,15 +175,24 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int n = A.n;
+    // orders this block folds: slots b0..b0+BT-1 of the plain batch or of node's work list
+    const int count = A.wl_count ? A.wl_count[node] : A.B;
+    if (b0 >= count) return;                     // uniform: nothing listed for this group
+    __shared__ int s_ord[BT];
 
     for (int j = wave; j < BT; j += kScoreThreads / 64) {
         uint64_t np = ~0ull;   // no order in this slot: nothing is consistent
-        if (b0 + j < A.B) {
+        int ob = -1;
+        if (b0 + j < count) {
+            ob = A.wl_count ? A.wl_list[(int64_t)node * A.B + b0 + j] : b0 + j;
             bool valid;
-            uint64_t pred = wave_pred(A.orders + (int64_t)(b0 + j) * n, n, node, lane, valid);
+            uint64_t pred = wave_pred(A.orders + (int64_t)ob * n, n, node, lane, valid);
             np = ~pred;        // invalid order: only the empty set is consistent
         }
-        if (lane == 0) s_npred[j] = np;
+        if (lane == 0) {
+            s_npred[j] = np;
+            s_ord[j] = ob;
+        }
     }
     __syncthreads();
     uint64_t npred[BT];
@@ -227,7 +240,8 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
     __syncthreads();
     if (threadIdx.x < BT) {
         const int j = threadIdx.x;
-        if (b0 + j < A.B) {
+        if (b0 + j < count) {
+            const int ob = s_ord[j];
             Acc r;
             r.m = s_red[0][j].m;
             r.s = s_red[0][j].s;
@@ -250,7 +264,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
             p.best = r.best;
             p.second = r.sec;
             p.bmask = r.bm;
-            A.part[((int64_t)(b0 + j) * n + node) * A.chunks + chunk] = p;
+            A.part[((int64_t)ob * n + node) * A.chunks + chunk] = p;
         }
     }
 }
