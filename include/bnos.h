@@ -206,6 +206,18 @@ bnos_status bnos_run_chains(bnos_table t, const bnos_chain_cfg *cfg, bnos_chain_
                             void *stream);
 
 /*
+ * The same for T datasets of possibly different n at once: every kernel of an
+ * iteration spans all T tables (one grid over all tables' (node, chunk)
+ * blocks, one block per chain of every table).  tables[k] gets
+ * cfg->chains chains whose RNG stream ids are chain_offset + k*chains + c,
+ * and its own state states[k] (sized by tables[k]'s n).  Each chain's
+ * trajectory is the one bnos_run_chains gives it with that chain id.
+ * T is 1..4096; a table may appear once.
+ */
+bnos_status bnos_run_chains_multi(const bnos_table *tables, int32_t T, const bnos_chain_cfg *cfg,
+                                  bnos_chain_state *states, void *stream);
+
+/*
  * Kernel timing for measurement: while enabled, every order-scoring launch
  * of this table is bracketed by HIP events recorded on the launch stream.
  * bnos_table_timing_read waits for the recorded events and returns the sum of

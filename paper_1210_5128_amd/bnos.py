@@ -56,6 +56,7 @@ _SIGS = {
     "bnos_score_orders": (i32, [P, P, i32, P, P, P, P, P, P]),
     "bnos_score_order": (i32, [P, P, P, P, P]),
     "bnos_run_chains": (i32, [P, P, P, P]),
+    "bnos_run_chains_multi": (i32, [P, i32, P, P, P]),
     "bnos_table_timing": (i32, [P, i32]),
     "bnos_table_timing_read": (i32, [P, P, P, P]),
 }
@@ -189,23 +190,8 @@ class Table:
                    trace_every: int = 1, chain_offset: int = 0, sweep_len: int = 0, stream=None):
         """Run MH chains in place on `state` (from new_chain_state); returns when done."""
         chains = int(state["orders"].shape[0])
-        cfg = ChainCfg()
-        cfg.chains = chains
-        cfg.target = target
-        cfg.iterations = iterations
-        cfg.first_iteration = first_iteration
-        cfg.seed = seed
-        cfg.chain_offset = chain_offset
-        cfg.trace_every = max(1, trace_every)
-        cfg.sweep_len = sweep_len
-        st = ChainState()
-        for k in ("orders", "scores", "best_graphs", "best_scores", "accepted", "trace", "accept_flags"):
-            v = state.get(k)
-            setattr(st, k, None if v is None else v.data_ptr())
-        if state.get("trace") is not None and state["trace"].shape[1] < iterations // cfg.trace_every + 1:
-            raise ValueError("trace tensor too small")
-        if state.get("accept_flags") is not None and state["accept_flags"].shape[1] < iterations:
-            raise ValueError("accept_flags tensor too small")
+        cfg = _chain_cfg(chains, iterations, seed, target, first_iteration, trace_every, chain_offset, sweep_len)
+        st = _chain_state(state, iterations, trace_every)
         _check(_lib.bnos_run_chains(self._h, ctypes.byref(cfg), ctypes.byref(st), _stream(stream)))
 
     # -- timing
@@ -217,6 +203,44 @@ class Table:
         ms, cnt, passes = f64(), i64(), i64()
         _check(_lib.bnos_table_timing_read(self._h, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(passes)))
         return ms.value, cnt.value, passes.value
+
+
+def _chain_cfg(chains, iterations, seed, target, first_iteration, trace_every, chain_offset, sweep_len):
+    cfg = ChainCfg()
+    cfg.chains = chains
+    cfg.target = target
+    cfg.iterations = iterations
+    cfg.first_iteration = first_iteration
+    cfg.seed = seed
+    cfg.chain_offset = chain_offset
+    cfg.trace_every = max(1, trace_every)
+    cfg.sweep_len = sweep_len
+    return cfg
+
+
+def _chain_state(state: dict, iterations: int, trace_every: int) -> ChainState:
+    st = ChainState()
+    for k in ("orders", "scores", "best_graphs", "best_scores", "accepted", "trace", "accept_flags"):
+        v = state.get(k)
+        setattr(st, k, None if v is None else v.data_ptr())
+    if state.get("trace") is not None and state["trace"].shape[1] < iterations // max(1, trace_every) + 1:
+        raise ValueError("trace tensor too small")
+    if state.get("accept_flags") is not None and state["accept_flags"].shape[1] < iterations:
+        raise ValueError("accept_flags tensor too small")
+    return st
+
+
+def run_chains_multi(tables, states, iterations: int, seed: int, target: int = 0, first_iteration: int = 0,
+                     trace_every: int = 1, chain_offset: int = 0, sweep_len: int = 0, stream=None):
+    """Advance the chains of several tables in one set of launches (bnos_run_chains_multi)."""
+    T = len(tables)
+    chains = int(states[0]["orders"].shape[0])
+    if any(int(s["orders"].shape[0]) != chains for s in states):
+        raise ValueError("every table needs the same number of chains")
+    cfg = _chain_cfg(chains, iterations, seed, target, first_iteration, trace_every, chain_offset, sweep_len)
+    hs = (P * T)(*[t.handle.value for t in tables])
+    sts = (ChainState * T)(*[_chain_state(s, iterations, trace_every) for s in states])
+    _check(_lib.bnos_run_chains_multi(hs, T, ctypes.byref(cfg), sts, _stream(stream)))
 
 
 def build_score_table(data, arities, K: int, ess: float = 1.0, prior=None, prior_mode: int = 0,

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "bnos_internal.h"
 #include "score_device.h"
@@ -52,11 +53,13 @@ __device__ __forceinline__ void rng_pair(uint64_t seed, uint64_t chain, int n, u
 
 // ------------------------------------------------------------------ kernels
 
-struct ChainArgs {
+// Chains of one table.  Kernels take an array of these (one per table) and
+// find their table from prefix bases over the grid.
+struct ChainView {
     int n, C, target;
     uint64_t seed;
-    int64_t chain0;
-    int64_t t_first, t_last;   // iterations already done before this call; last iteration to run
+    int64_t chain0;            // RNG stream id of this table's chain 0
+    int64_t t_first, t_last;   // iterations done before this call; last iteration to run
     int32_t *cur;              // [C][n] current orders (state)
     int32_t *prop;             // [C][n] orders being scored
     double *score;             // [C] target score of the current order (state)
@@ -82,9 +85,12 @@ __device__ __forceinline__ uint64_t all_nodes(int n) { return n == 64 ? ~0ull : 
 // Block per chain.  Fresh start: the initial order (iteration 0 adopts it).
 // Resume: the saved current order is re-scored first to rebuild the per-node
 // caches (same arithmetic, so the same values), then iteration t_first+1 follows.
-__global__ __launch_bounds__(64) void k_chain_init(ChainArgs H)
+__global__ __launch_bounds__(64) void k_chain_init(const ChainView *__restrict__ views,
+                                                   const int64_t *__restrict__ chain_base, int T)
 {
-    const int c = blockIdx.x;
+    const int k = find_segment(chain_base, T, (int64_t)blockIdx.x);
+    const ChainView &H = views[k];
+    const int c = (int)((int64_t)blockIdx.x - chain_base[k]);
     const int lane = threadIdx.x;
     const int n = H.n;
     const uint64_t chain = (uint64_t)(H.chain0 + c);
@@ -111,14 +117,17 @@ __global__ __launch_bounds__(64) void k_chain_init(ChainArgs H)
     }
 }
 
-// Block per node: the chains whose proposal window contains the node, in chain
-// order (deterministic compaction).
+// Block per (table, node): the chains whose proposal window contains the node,
+// in chain order (deterministic compaction).
 constexpr int kListThreads = 1024;
-__global__ __launch_bounds__(kListThreads) void k_worklist(ChainArgs H)
+__global__ __launch_bounds__(kListThreads) void k_worklist(const ChainView *__restrict__ views,
+                                                           const int64_t *__restrict__ node_base, int T)
 {
     __shared__ int s_wave[kListThreads / 64];
     __shared__ int s_base;
-    const int node = blockIdx.x;
+    const int k = find_segment(node_base, T, (int64_t)blockIdx.x);
+    const ChainView &H = views[k];
+    const int node = (int)((int64_t)blockIdx.x - node_base[k]);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     if (threadIdx.x == 0) s_base = 0;
@@ -148,17 +157,22 @@ __global__ __launch_bounds__(kListThreads) void k_worklist(ChainArgs H)
 // the cached values of the other nodes (per-order sums in node order with a
 // fixed butterfly, as a full rescoring would), take the MH decision, update
 // the caches and the best-graph record, and write the next proposal.
-__global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(ScoreArgs A, ChainArgs H)
+__global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(const TabView *__restrict__ tviews,
+                                                                 const ChainView *__restrict__ views,
+                                                                 const int64_t *__restrict__ chain_base, int T)
 {
     __shared__ double s_l[64], s_b[64];
     __shared__ uint64_t s_bm[64];
     __shared__ int s_nodes[64];
     __shared__ int s_cnt;
-    const int c = blockIdx.x;
+    const int k = find_segment(chain_base, T, (int64_t)blockIdx.x);
+    const ChainView &H = views[k];
+    const TabView &V = tviews[k];
+    const int c = (int)((int64_t)blockIdx.x - chain_base[k]);
     const int n = H.n;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int chunks = A.chunks;
+    const int chunks = V.chunks;
     const uint64_t wm = H.wmask[c];
     if (wave == 0) {
         const bool in = lane < n && ((wm >> lane) & 1ull);
@@ -170,23 +184,23 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(ScoreArgs A, Ch
     const int cnt = s_cnt;
     Acc r[kMergeNodesPerWave];
 #pragma unroll
-    for (int k = 0; k < kMergeNodesPerWave; ++k) {
-        const int q = wave + kMergeWaves * k;
-        acc_init(r[k]);
-        if (q < cnt && lane < chunks) r[k] = load_partial(A.part + ((int64_t)c * n + s_nodes[q]) * chunks + lane);
+    for (int q = 0; q < kMergeNodesPerWave; ++q) {
+        const int w = wave + kMergeWaves * q;
+        acc_init(r[q]);
+        if (w < cnt && lane < chunks) r[q] = load_partial(V.part + ((int64_t)c * n + s_nodes[w]) * chunks + lane);
     }
 #pragma unroll
-    for (int k = 0; k < kMergeNodesPerWave; ++k) {
-        const int q = wave + kMergeWaves * k;
-        if (q >= cnt) break;
-        const int i = s_nodes[q];
-        const Partial *pp = A.part + ((int64_t)c * n + i) * chunks;
-        for (int cc = lane + 64; cc < chunks; cc += 64) acc_merge(r[k], load_partial(pp + cc));
-        acc_wave_reduce(r[k], lane);
+    for (int q = 0; q < kMergeNodesPerWave; ++q) {
+        const int w = wave + kMergeWaves * q;
+        if (w >= cnt) break;
+        const int i = s_nodes[w];
+        const Partial *pp = V.part + ((int64_t)c * n + i) * chunks;
+        for (int cc = lane + 64; cc < chunks; cc += 64) acc_merge(r[q], load_partial(pp + cc));
+        acc_wave_reduce(r[q], lane);
         if (lane == 0) {
-            s_l[i] = (double)r[k].m + log((double)r[k].s);
-            s_b[i] = (double)r[k].best;
-            s_bm[i] = r[k].bm;
+            s_l[i] = (double)r[q].m + log((double)r[q].s);
+            s_b[i] = (double)r[q].best;
+            s_bm[i] = r[q].bm;
         }
     }
     __syncthreads();
@@ -223,8 +237,8 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(ScoreArgs A, Ch
                 }
             }
             if (H.flags) H.flags[(int64_t)c * H.iterations + (t - H.t_first - 1)] = (uint8_t)acc;
-            const int64_t k = t - H.t_first;
-            if (H.trace && k % H.trace_every == 0) H.trace[(int64_t)c * H.trace_len + k / H.trace_every] = H.score[c];
+            const int64_t kk = t - H.t_first;
+            if (H.trace && kk % H.trace_every == 0) H.trace[(int64_t)c * H.trace_len + kk / H.trace_every] = H.score[c];
         }
     }
     acc = __shfl(acc, 0, 64);
@@ -239,10 +253,7 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(ScoreArgs A, Ch
             if (in) H.node_best[row + lane] = s_bm[lane];
         }
     }
-    if (imp && lane < n) {
-        // node_best now holds the accepted order's greedy graph (this lane's entry)
-        H.best_graph[row + lane] = in ? s_bm[lane] : H.node_best[row + lane];
-    }
+    if (imp && lane < n) H.best_graph[row + lane] = in ? s_bm[lane] : H.node_best[row + lane];
     const int64_t t1 = t + 1;
     const bool next = t1 <= H.t_last;
     int a = 0, b = 0;
@@ -264,15 +275,12 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(ScoreArgs A, Ch
 
 using namespace bnos;
 
-extern "C" bnos_status bnos_run_chains(bnos_table h, const bnos_chain_cfg *cfg, bnos_chain_state *st,
-                                       void *stream)
+namespace {
+
+bnos_status validate_cfg(const bnos_chain_cfg *cfg)
 {
-    TableT *t = reinterpret_cast<TableT *>(h);
-    if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
-    if (!cfg || !st) { set_error("NULL argument"); return BNOS_E_INVALID; }
-    const int n = t->n;
-    const int C = cfg->chains;
-    if (C < 1 || C > 65536) { set_error("chains outside [1, 65536]"); return BNOS_E_RANGE; }
+    if (!cfg) { set_error("NULL cfg"); return BNOS_E_INVALID; }
+    if (cfg->chains < 1 || cfg->chains > 65536) { set_error("chains outside [1, 65536]"); return BNOS_E_RANGE; }
     if (cfg->target != 0 && cfg->target != 1) { set_error("target must be 0 or 1"); return BNOS_E_INVALID; }
     if (cfg->iterations < 0 || cfg->first_iteration < 0) { set_error("negative iteration count"); return BNOS_E_RANGE; }
     if (cfg->trace_every < 1) { set_error("trace_every must be >= 1"); return BNOS_E_RANGE; }
@@ -280,69 +288,115 @@ extern "C" bnos_status bnos_run_chains(bnos_table h, const bnos_chain_cfg *cfg, 
     if (cfg->chain_offset < 0) { set_error("chain_offset < 0"); return BNOS_E_RANGE; }
     for (int r = 0; r < 6; ++r)
         if (cfg->reserved[r] != 0) { set_error("cfg.reserved must be zero"); return BNOS_E_INVALID; }
-    if (!st->orders || !st->scores || !st->best_graphs || !st->best_scores || !st->accepted) {
-        set_error("NULL state array");
-        return BNOS_E_INVALID;
+    return BNOS_OK;
+}
+
+}  // namespace
+
+extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, const bnos_chain_cfg *cfg,
+                                             bnos_chain_state *states, void *stream)
+{
+    if (!hs || !states) { set_error("NULL argument"); return BNOS_E_INVALID; }
+    if (T < 1 || T > 4096) { set_error("T outside [1, 4096]"); return BNOS_E_RANGE; }
+    bnos_status s = validate_cfg(cfg);
+    if (s != BNOS_OK) return s;
+    std::vector<TableT *> tabs(T);
+    for (int k = 0; k < T; ++k) {
+        tabs[k] = reinterpret_cast<TableT *>(hs[k]);
+        if (!handle_live(tabs[k])) { set_error("invalid table handle"); return BNOS_E_STATE; }
+        for (int j = 0; j < k; ++j)
+            if (tabs[j] == tabs[k]) { set_error("a table appears twice"); return BNOS_E_INVALID; }
+        if (tabs[k]->device != tabs[0]->device) { set_error("tables on different devices"); return BNOS_E_INVALID; }
+        if (tabs[k]->n < 2) { set_error("chains need n >= 2 (a swap needs two positions)"); return BNOS_E_RANGE; }
+        const bnos_chain_state &st = states[k];
+        if (!st.orders || !st.scores || !st.best_graphs || !st.best_scores || !st.accepted) {
+            set_error("NULL state array");
+            return BNOS_E_INVALID;
+        }
     }
-    if (n < 2) { set_error("chains need n >= 2 (a swap needs two positions)"); return BNOS_E_RANGE; }
     // scoring steps: the adoption of the starting order (fresh: iteration 0; resume: the
     // saved order, re-scored to rebuild the per-node caches) and one per iteration
     if (cfg->iterations == 0 && cfg->first_iteration > 0) return BNOS_OK;
     const int64_t steps = cfg->iterations + 1;
+    const int C = cfg->chains;
     hipStream_t us = reinterpret_cast<hipStream_t>(stream);
-    BNOS_HIP(hipSetDevice(t->device));
-    bnos_status s = ensure_workspace(t, C);
-    if (s != BNOS_OK) return s;
+    BNOS_HIP(hipSetDevice(tabs[0]->device));
+    for (int k = 0; k < T; ++k)
+        if ((s = ensure_workspace(tabs[k], C)) != BNOS_OK) return s;
 
-    // per-call workspace: per-node caches, proposals, windows, work lists, iteration counters
+    // per-call workspace: descriptors + per table: per-node caches, proposals,
+    // windows, work lists, iteration counters
+    size_t bytes = sizeof(TabView) * T + sizeof(ChainView) * T + 3 * sizeof(int64_t) * (T + 1) + 256;
+    std::vector<size_t> off(T);
+    for (int k = 0; k < T; ++k) {
+        const size_t n = tabs[k]->n, cn = (size_t)C * n;
+        off[k] = bytes;
+        bytes += cn * 24 + (size_t)C * 16 + cn * 4 + n * C * 4 + n * 4;
+        bytes = (bytes + 255) & ~(size_t)255;
+    }
     char *ws = nullptr;
-    const size_t cn = (size_t)C * n;
-    const size_t bytes = cn * (8 + 8 + 8) + (size_t)C * (8 + 8) + cn * 4 + (size_t)n * C * 4 + (size_t)n * 4 + 256;
     hipError_t e = hipMalloc((void **)&ws, bytes);
     if (e != hipSuccess) {
         set_error(std::string("hipMalloc chain workspace: ") + hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? BNOS_E_NOMEM : BNOS_E_DEVICE;
     }
-    char *p = ws;
-    double *node_l = reinterpret_cast<double *>(p);       p += cn * 8;
-    double *node_m = reinterpret_cast<double *>(p);       p += cn * 8;
-    uint64_t *node_best = reinterpret_cast<uint64_t *>(p); p += cn * 8;
-    uint64_t *wmask = reinterpret_cast<uint64_t *>(p);    p += (size_t)C * 8;
-    int64_t *tcount = reinterpret_cast<int64_t *>(p);     p += (size_t)C * 8;
-    int32_t *prop = reinterpret_cast<int32_t *>(p);       p += cn * 4;
-    int32_t *wl_list = reinterpret_cast<int32_t *>(p);    p += (size_t)n * C * 4;
-    int32_t *wl_count = reinterpret_cast<int32_t *>(p);
-
-    ChainArgs H;
-    H.n = n;
-    H.C = C;
-    H.target = cfg->target;
-    H.seed = cfg->seed;
-    H.chain0 = cfg->chain_offset;
-    H.t_first = cfg->first_iteration;
-    H.t_last = cfg->first_iteration + cfg->iterations;
-    H.cur = st->orders;
-    H.prop = prop;
-    H.score = st->scores;
-    H.best_score = st->best_scores;
-    H.best_graph = st->best_graphs;
-    H.accepted = st->accepted;
-    H.t = tcount;
-    H.node_l = node_l;
-    H.node_m = node_m;
-    H.node_best = node_best;
-    H.wmask = wmask;
-    H.wl_count = wl_count;
-    H.wl_list = wl_list;
-    H.trace = st->trace;
-    H.trace_every = cfg->trace_every;
-    H.trace_len = cfg->iterations / cfg->trace_every + 1;
-    H.flags = st->accept_flags;
-    H.iterations = cfg->iterations;
-    ScoreArgs A = score_args(t, prop, C, nullptr, nullptr, nullptr, nullptr, nullptr);
-    A.wl_count = wl_count;
-    A.wl_list = wl_list;
-    const int bt = pick_bt(t, C);
+    std::vector<TabView> tv(T);
+    std::vector<ChainView> cv(T);
+    std::vector<int64_t> blk_base(T + 1, 0), chain_base(T + 1, 0), node_base(T + 1, 0);
+    int64_t max_groups_c = C;
+    for (int k = 0; k < T; ++k) {
+        TableT *t = tabs[k];
+        const int n = t->n;
+        const size_t cn = (size_t)C * n;
+        char *p = ws + off[k];
+        ChainView &H = cv[k];
+        H.n = n;
+        H.C = C;
+        H.target = cfg->target;
+        H.seed = cfg->seed;
+        H.chain0 = cfg->chain_offset + (int64_t)k * C;
+        H.t_first = cfg->first_iteration;
+        H.t_last = cfg->first_iteration + cfg->iterations;
+        H.node_l = reinterpret_cast<double *>(p);       p += cn * 8;
+        H.node_m = reinterpret_cast<double *>(p);       p += cn * 8;
+        H.node_best = reinterpret_cast<uint64_t *>(p);  p += cn * 8;
+        H.wmask = reinterpret_cast<uint64_t *>(p);      p += (size_t)C * 8;
+        H.t = reinterpret_cast<int64_t *>(p);           p += (size_t)C * 8;
+        H.prop = reinterpret_cast<int32_t *>(p);        p += cn * 4;
+        H.wl_list = reinterpret_cast<int32_t *>(p);     p += (size_t)n * C * 4;
+        H.wl_count = reinterpret_cast<int32_t *>(p);
+        const bnos_chain_state &st = states[k];
+        H.cur = st.orders;
+        H.score = st.scores;
+        H.best_score = st.best_scores;
+        H.best_graph = st.best_graphs;
+        H.accepted = st.accepted;
+        H.trace = st.trace;
+        H.trace_every = cfg->trace_every;
+        H.trace_len = cfg->iterations / cfg->trace_every + 1;
+        H.flags = st.accept_flags;
+        H.iterations = cfg->iterations;
+        TabView &V = tv[k];
+        V.masks = t->d_masks;
+        V.scores = t->d_scores;
+        V.S_pad = t->S_pad;
+        V.chunks = t->chunks;
+        V.chunk_entries = t->chunk_entries;
+        V.n = n;
+        V.B = C;
+        V.orders = H.prop;
+        V.part = reinterpret_cast<Partial *>(t->d_part);
+        V.wl_count = H.wl_count;
+        V.wl_list = H.wl_list;
+        blk_base[k + 1] = blk_base[k] + (int64_t)n * t->chunks;
+        chain_base[k + 1] = chain_base[k] + C;
+        node_base[k + 1] = node_base[k] + n;
+    }
+    TabView *d_tv = reinterpret_cast<TabView *>(ws);
+    ChainView *d_cv = reinterpret_cast<ChainView *>(ws + sizeof(TabView) * T);
+    int64_t *d_blk = reinterpret_cast<int64_t *>(ws + sizeof(TabView) * T + sizeof(ChainView) * T);
+    int64_t *d_chain = d_blk + (T + 1);
+    int64_t *d_node = d_chain + (T + 1);
 
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
@@ -354,46 +408,55 @@ extern "C" bnos_status bnos_run_chains(bnos_table h, const bnos_chain_cfg *cfg, 
         hipFree(ws);
     };
 #define CK(call) if ((e = (call)) != hipSuccess) { set_error(std::string(#call) + ": " + hipGetErrorString(e)); cleanup(); return BNOS_E_DEVICE; }
-    hipLaunchKernelGGL(k_chain_init, dim3(C), dim3(64), 0, us, H);
+    CK(hipMemcpy(d_tv, tv.data(), sizeof(TabView) * T, hipMemcpyHostToDevice));
+    CK(hipMemcpy(d_cv, cv.data(), sizeof(ChainView) * T, hipMemcpyHostToDevice));
+    CK(hipMemcpy(d_blk, blk_base.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice));
+    CK(hipMemcpy(d_chain, chain_base.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice));
+    CK(hipMemcpy(d_node, node_base.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice));
+    const int bt = pick_bt(tabs[0], C);
+    const unsigned groups = (unsigned)((max_groups_c + bt - 1) / bt);
+    const unsigned total_chains = (unsigned)chain_base[T];
+    hipLaunchKernelGGL(k_chain_init, dim3(total_chains), dim3(64), 0, us, d_cv, d_chain, T);
     CK(hipGetLastError());
-    auto one_step = [&](hipStream_t q) -> bnos_status {
-        hipLaunchKernelGGL(k_worklist, dim3(n), dim3(kListThreads), 0, q, H);
-        BNOS_HIP(hipGetLastError());
-        bnos_status r = launch_stream(t, A, q, bt);
-        if (r != BNOS_OK) return r;
-        hipLaunchKernelGGL(k_chain_step, dim3(C), dim3(kMergeWaves * 64), 0, q, A, H);
-        BNOS_HIP(hipGetLastError());
-        return BNOS_OK;
+    auto one_step = [&](hipStream_t q) -> hipError_t {
+        hipLaunchKernelGGL(k_worklist, dim3((unsigned)node_base[T]), dim3(kListThreads), 0, q, d_cv, d_node, T);
+        dim3 grid((unsigned)blk_base[T], groups);
+        if (bt == 8) hipLaunchKernelGGL(k_score_multi<8>, grid, dim3(kScoreThreads), 0, q, d_tv, d_blk, T);
+        else if (bt == 4) hipLaunchKernelGGL(k_score_multi<4>, grid, dim3(kScoreThreads), 0, q, d_tv, d_blk, T);
+        else if (bt == 2) hipLaunchKernelGGL(k_score_multi<2>, grid, dim3(kScoreThreads), 0, q, d_tv, d_blk, T);
+        else hipLaunchKernelGGL(k_score_multi<1>, grid, dim3(kScoreThreads), 0, q, d_tv, d_blk, T);
+        hipLaunchKernelGGL(k_chain_step, dim3(total_chains), dim3(kMergeWaves * 64), 0, q, d_tv, d_cv, d_chain, T);
+        return hipGetLastError();
     };
     const int64_t sweep = cfg->sweep_len > 0 ? cfg->sweep_len : 32;
     const int64_t graphs = steps / sweep;
     const int64_t rest = steps - graphs * sweep;
     if (graphs > 0) {
-        // Capture one sweep on a private stream (timing events are not captured).
-        const bool timing = t->timing;
-        t->timing = false;
         CK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         CK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        for (int64_t k = 0; k < sweep; ++k) {
-            if ((s = one_step(cs)) != BNOS_OK) {
+        for (int64_t q = 0; q < sweep; ++q) {
+            if ((e = one_step(cs)) != hipSuccess) {
                 hipGraph_t g2 = nullptr;
                 hipStreamEndCapture(cs, &g2);
                 if (g2) hipGraphDestroy(g2);
-                t->timing = timing;
+                set_error(std::string("kernel launch during capture: ") + hipGetErrorString(e));
                 cleanup();
-                return s;
+                return BNOS_E_DEVICE;
             }
         }
         CK(hipStreamEndCapture(cs, &graph));
-        t->timing = timing;
         CK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
         for (int64_t g = 0; g < graphs; ++g) CK(hipGraphLaunch(exec, us));
     }
-    for (int64_t k = 0; k < rest; ++k) {
-        if ((s = one_step(us)) != BNOS_OK) { cleanup(); return s; }
-    }
+    for (int64_t q = 0; q < rest; ++q) CK(one_step(us));
     CK(hipStreamSynchronize(us));
 #undef CK
     cleanup();
     return BNOS_OK;
+}
+
+extern "C" bnos_status bnos_run_chains(bnos_table h, const bnos_chain_cfg *cfg, bnos_chain_state *st,
+                                       void *stream)
+{
+    return bnos_run_chains_multi(&h, 1, cfg, st, stream);
 }

@@ -161,32 +161,43 @@ struct ScoreArgs {
     const int32_t *wl_list;    // [n][B]
 };
 
-// Grid: x = node * chunks + chunk, y = group of BT orders.  Every block
-// streams one chunk of one node's entries once, folds each entry into BT order
-// states and writes one Partial per order.
+// What one streaming block needs to know about its table and its orders.
+struct TabView {
+    const uint64_t *masks;
+    const float *scores;
+    int64_t S_pad;
+    int chunks, chunk_entries, n;
+    int B;                      // orders (chains) of this table; row stride of wl_list
+    const int32_t *orders;      // [B][n]
+    Partial *part;              // [B][n][chunks]
+    const int32_t *wl_count;    // [n] or null
+    const int32_t *wl_list;     // [n][B]
+};
+
+// One block streams chunk `chunk` of node `node`'s entries once and folds each
+// entry into BT order states (group `group` of the batch, or of the node's work
+// list); it writes one Partial per order.
 template <int BT>
-__global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
+__device__ __forceinline__ void score_block(const TabView &V, int node, int chunk, int group)
 {
     __shared__ uint64_t s_npred[BT];
     __shared__ Acc s_red[kScoreThreads / 64][BT];
-    const int node = blockIdx.x / A.chunks;
-    const int chunk = blockIdx.x - node * A.chunks;
-    const int b0 = blockIdx.y * BT;
+    __shared__ int s_ord[BT];
+    const int b0 = group * BT;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int n = A.n;
+    const int n = V.n;
     // orders this block folds: slots b0..b0+BT-1 of the plain batch or of node's work list
-    const int count = A.wl_count ? A.wl_count[node] : A.B;
+    const int count = V.wl_count ? V.wl_count[node] : V.B;
     if (b0 >= count) return;                     // uniform: nothing listed for this group
-    __shared__ int s_ord[BT];
 
     for (int j = wave; j < BT; j += kScoreThreads / 64) {
         uint64_t np = ~0ull;   // no order in this slot: nothing is consistent
         int ob = -1;
         if (b0 + j < count) {
-            ob = A.wl_count ? A.wl_list[(int64_t)node * A.B + b0 + j] : b0 + j;
+            ob = V.wl_count ? V.wl_list[(int64_t)node * V.B + b0 + j] : b0 + j;
             bool valid;
-            uint64_t pred = wave_pred(A.orders + (int64_t)ob * n, n, node, lane, valid);
+            uint64_t pred = wave_pred(V.orders + (int64_t)ob * n, n, node, lane, valid);
             np = ~pred;        // invalid order: only the empty set is consistent
         }
         if (lane == 0) {
@@ -203,10 +214,10 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
         acc_init(a[j]);
     }
 
-    const int64_t row = (int64_t)node * A.S_pad + (int64_t)chunk * A.chunk_entries;
-    const u64x2 *mp = reinterpret_cast<const u64x2 *>(A.masks + row);
-    const f32x4 *sp = reinterpret_cast<const f32x4 *>(A.scores + row);
-    const int steps = A.chunk_entries / kEntriesPerStep;
+    const int64_t row = (int64_t)node * V.S_pad + (int64_t)chunk * V.chunk_entries;
+    const u64x2 *mp = reinterpret_cast<const u64x2 *>(V.masks + row);
+    const f32x4 *sp = reinterpret_cast<const f32x4 *>(V.scores + row);
+    const int steps = V.chunk_entries / kEntriesPerStep;
     // Software pipeline: the loads of step it+1 are in flight while step it is folded.
     int q = threadIdx.x;                                     // this lane's 4-entry group
     u64x2 n01 = __builtin_nontemporal_load(&mp[2 * q]);
@@ -264,9 +275,61 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
             p.best = r.best;
             p.second = r.sec;
             p.bmask = r.bm;
-            A.part[((int64_t)ob * n + node) * A.chunks + chunk] = p;
+            V.part[((int64_t)ob * n + node) * V.chunks + chunk] = p;
         }
     }
+}
+
+__device__ __forceinline__ TabView view_of(const ScoreArgs &A)
+{
+    TabView V;
+    V.masks = A.masks;
+    V.scores = A.scores;
+    V.S_pad = A.S_pad;
+    V.chunks = A.chunks;
+    V.chunk_entries = A.chunk_entries;
+    V.n = A.n;
+    V.B = A.B;
+    V.orders = A.orders;
+    V.part = A.part;
+    V.wl_count = A.wl_count;
+    V.wl_list = A.wl_list;
+    return V;
+}
+
+// Grid: x = node * chunks + chunk, y = group of BT orders.
+template <int BT>
+__global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
+{
+    const int node = blockIdx.x / A.chunks;
+    const int chunk = blockIdx.x - node * A.chunks;
+    score_block<BT>(view_of(A), node, chunk, blockIdx.y);
+}
+
+// Index of the segment holding x, for prefix bases base[0] = 0 < ... < base[T].
+__device__ __forceinline__ int find_segment(const int64_t *__restrict__ base, int T, int64_t x)
+{
+    int lo = 0, hi = T - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Many tables in one grid: x runs over every table's (node, chunk) blocks
+// (table k owns x in [blk_base[k], blk_base[k+1])), y = group of BT orders.
+template <int BT>
+__global__ __launch_bounds__(kScoreThreads) void k_score_multi(const TabView *__restrict__ views,
+                                                              const int64_t *__restrict__ blk_base, int T)
+{
+    const int k = find_segment(blk_base, T, (int64_t)blockIdx.x);
+    const TabView V = views[k];
+    const int local = (int)((int64_t)blockIdx.x - blk_base[k]);
+    const int node = local / V.chunks;
+    const int chunk = local - node * V.chunks;
+    score_block<BT>(V, node, chunk, blockIdx.y);
 }
 
 constexpr int kMergeWaves = 16;

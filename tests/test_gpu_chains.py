@@ -199,3 +199,25 @@ def test_mixed60_chain_properties(bnos):
         assert abs(l0 - g["trace"][c, 0]) <= REL * abs(l0)
         assert g["best_scores"][c] >= m0
     t.free()
+
+
+def test_uneven_datasets_in_one_launch_match_one_at_a_time(bnos):
+    ws = [datagen.uneven_workload(d) for d in range(5)]
+    ws = [datagen.Workload(w.name, w.n, min(w.N, 1500), w.arity_choices, w.dmax, 3, w.data_seed, None)
+          for w in ws]                                     # K=3 keeps the test short
+    tabs = []
+    for w in ws:
+        net, _ = datagen.make(w)
+        tabs.append(bnos.build_score_table(net.data, net.arities, w.K))
+    C, iters, seed = 6, 150, 33
+    states = [t.new_chain_state(C, iters, trace_every=1, flags=True) for t in tabs]
+    bnos.run_chains_multi(tabs, states, iters, seed, chain_offset=11)
+    torch.cuda.synchronize()
+    for k, t in enumerate(tabs):
+        ref = t.new_chain_state(C, iters, trace_every=1, flags=True)
+        t.run_chains(ref, iters, seed, chain_offset=11 + k * C)
+        torch.cuda.synchronize()
+        for key in ("orders", "scores", "best_graphs", "best_scores", "accepted", "trace", "accept_flags"):
+            assert torch.equal(states[k][key], ref[key]), (k, key)
+    for t in tabs:
+        t.free()
