@@ -134,6 +134,42 @@ def bench_chains(bnos, datagen, wname: str, chains: int, iters: int, seed: int =
     return out
 
 
+def bench_uneven(bnos, datagen, n_datasets: int, chains: int, iters: int, seed: int = 202):
+    """Uneven family (n ~ U[20,60], N ~ U[1000,5000], K=4): all datasets' chains in one
+    set of launches vs one dataset at a time (chain-iterations/s)."""
+    import torch
+    tabs, ns = [], []
+    t0 = time.perf_counter()
+    for d in range(n_datasets):
+        w = datagen.uneven_workload(d)
+        net, _ = datagen.make(w)
+        tabs.append(bnos.build_score_table(net.data, net.arities, w.K))
+        ns.append(w.n)
+    build_s = time.perf_counter() - t0
+    table_bytes = sum(t.info()["device_bytes"] for t in tabs)
+    states = [t.new_chain_state(chains, iters, trace_every=max(1, iters)) for t in tabs]
+    bnos.run_chains_multi(tabs, states, 20, seed + 1, trace_every=20)          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bnos.run_chains_multi(tabs, states, iters, seed, trace_every=iters)
+    torch.cuda.synchronize()
+    one = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for k, t in enumerate(tabs):
+        t.run_chains(states[k], iters, seed, trace_every=iters, chain_offset=k * chains)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    total = n_datasets * chains * iters
+    for t in tabs:
+        t.free()
+    print(f"# uneven: one launch {one:.2f} s, one at a time {seq:.2f} s", file=sys.stderr, flush=True)
+    return {"datasets": n_datasets, "n": ns, "chains_per_dataset": chains, "iterations": iters,
+            "tables_device_bytes": table_bytes, "build_s": build_s,
+            "one_launch_s": one, "one_launch_chain_iterations_per_s": total / one,
+            "one_at_a_time_s": seq, "one_at_a_time_chain_iterations_per_s": total / seq,
+            "speedup": seq / one}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +183,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--chains", type=int, default=256, help="batched chains on the mixed40 table (0 = skip)")
     ap.add_argument("--chain-iters", type=int, default=20000)
+    ap.add_argument("--uneven", type=int, default=0, metavar="D",
+                    help="also run the uneven family: D datasets x 64 chains in one launch vs one at a time")
+    ap.add_argument("--uneven-iters", type=int, default=1000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (scale for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -266,6 +305,8 @@ def main():
     }
     if args.chains:
         out["chains"] = bench_chains(bnos, datagen, "mixed40", args.chains, args.chain_iters)
+    if args.uneven:
+        out["uneven"] = bench_uneven(bnos, datagen, args.uneven, 64, args.uneven_iters)
     if not args.no_cpu:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(net, prior, K)

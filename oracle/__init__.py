@@ -71,6 +71,23 @@ def lib():
         L.orc_accept_uniform.argtypes = [u64, u64, u64]
         L.orc_run_chain.restype = None
         L.orc_run_chain.argtypes = [P, i32, i32, u64, u64, i64, i32, i32, P, P, P, P, P, P]
+        L.orc_mlp_num_params.restype = i32
+        L.orc_mlp_num_params.argtypes = []
+        L.orc_table_stats.restype = None
+        L.orc_table_stats.argtypes = [P, i32, i32, i32, P]
+        L.orc_features.restype = None
+        L.orc_features.argtypes = [i32, P, P, P, P, P, P]
+        L.orc_mlp_forward.restype = None
+        L.orc_mlp_forward.argtypes = [P, i32, P, P, P, P]
+        L.orc_pair_logq.restype = f64
+        L.orc_pair_logq.argtypes = [P, i32, i32, i32, f64]
+        L.orc_mlp_loss_grad.restype = f64
+        L.orc_mlp_loss_grad.argtypes = [P, i32, P, i32, i32, f64, P]
+        L.orc_learned_pair.restype = None
+        L.orc_learned_pair.argtypes = [u64, u64, i32, u64, P, P, f64, P, P]
+        L.orc_run_chain_learned.restype = None
+        L.orc_run_chain_learned.argtypes = [P, i32, i32, u64, u64, i64, i32, i32, P, P, P, P, P, f64,
+                                            P, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -236,3 +253,97 @@ def run_chain(table: np.ndarray, K: int, seed: int, chain: int, iters: int, targ
                         _p(trace), _p(acc), _p(bg), ctypes.byref(bs), ctypes.byref(na))
     return dict(order=order, trace=trace, acc=acc[:iters], best_graph=bg, best_score=bs.value,
                 accepted=na.value)
+
+
+# ---------------------------------------------------------------- learned proposal
+
+HIDDEN = 128
+FEATURES = 8
+
+
+def mlp_num_params() -> int:
+    return int(lib().orc_mlp_num_params())
+
+
+def table_stats(table: np.ndarray, K: int, round_f32: bool = True) -> np.ndarray:
+    table = np.ascontiguousarray(table, dtype=np.float64)
+    n = table.shape[0]
+    out = np.zeros((n, 3))
+    lib().orc_table_stats(_p(table), n, K, int(round_f32), _p(out))
+    return out
+
+
+def prior_nats(prior, n: int, prior_mode: int = 0) -> np.ndarray:
+    """Per-edge prior terms in nats, [child][parent], 0 on the diagonal."""
+    out = np.zeros((n, n))
+    if prior is not None:
+        for i in range(n):
+            for m in range(n):
+                if i != m:
+                    out[i, m] = ppf_nats(float(np.float32(prior[i, m])), prior_mode)
+    return out
+
+
+def features(order, node_best, node_second, prior_nats_m, stats) -> np.ndarray:
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    n = order.size
+    nb = np.ascontiguousarray(node_best, dtype=np.float64)
+    ns = np.ascontiguousarray(node_second, dtype=np.float64)
+    pn = None if prior_nats_m is None else np.ascontiguousarray(prior_nats_m, dtype=np.float64)
+    st = np.ascontiguousarray(stats, dtype=np.float64)
+    out = np.zeros((n, FEATURES))
+    lib().orc_features(n, _p(order), _p(nb), _p(ns), None if pn is None else _p(pn), _p(st), _p(out))
+    return out
+
+
+def mlp_forward(prm: np.ndarray, z: np.ndarray) -> np.ndarray:
+    prm = np.ascontiguousarray(prm, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    n = z.shape[0]
+    out = np.zeros(n)
+    lib().orc_mlp_forward(_p(prm), n, _p(z), _p(out), None, None)
+    return out
+
+
+def pair_logq(logits, a: int, b: int, eps: float) -> float:
+    lg = np.ascontiguousarray(logits, dtype=np.float64)
+    return float(lib().orc_pair_logq(_p(lg), lg.size, a, b, eps))
+
+
+def mlp_loss_grad(prm: np.ndarray, z: np.ndarray, a: int, b: int, eps: float):
+    """(loss, gradient) of -ln q({a,b}) for one sample."""
+    prm = np.ascontiguousarray(prm, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    g = np.zeros_like(prm)
+    loss = lib().orc_mlp_loss_grad(_p(prm), z.shape[0], _p(z), a, b, eps, _p(g))
+    return float(loss), g
+
+
+def learned_pair(seed: int, chain: int, step: int, logits, order, eps: float):
+    lg = np.ascontiguousarray(logits, dtype=np.float64)
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    a, b = ctypes.c_int(), ctypes.c_int()
+    lib().orc_learned_pair(seed, chain, order.size, step, _p(lg), _p(order), eps, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def run_chain_learned(table, K, seed, chain, iters, prm, mu, sd, prior_nats_m, stats, eps=0.1, target=0,
+                      round_f32=True):
+    table = np.ascontiguousarray(table, dtype=np.float64)
+    n = table.shape[0]
+    prm = np.ascontiguousarray(prm, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    sd = np.ascontiguousarray(sd, dtype=np.float64)
+    st = np.ascontiguousarray(stats, dtype=np.float64)
+    pn = None if prior_nats_m is None else np.ascontiguousarray(prior_nats_m, dtype=np.float64)
+    order = np.zeros(n, dtype=np.int32)
+    trace = np.zeros(iters + 1)
+    acc = np.zeros(max(iters, 1), dtype=np.uint8)
+    bg = np.zeros(n, dtype=np.uint64)
+    bs = ctypes.c_double()
+    na = ctypes.c_int64()
+    lib().orc_run_chain_learned(_p(table), n, K, seed, chain, iters, target, int(round_f32), _p(prm), _p(mu), _p(sd),
+                                None if pn is None else _p(pn), _p(st), eps, _p(order), _p(trace), _p(acc), _p(bg),
+                                ctypes.byref(bs), ctypes.byref(na))
+    return dict(order=order, trace=trace, acc=acc[:iters], best_graph=bg, best_score=bs.value, accepted=na.value)
+

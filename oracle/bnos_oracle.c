@@ -484,3 +484,272 @@ void orc_run_chain(const double *table, int n, int K, uint64_t seed, uint64_t ch
     free(prop);
     free(g);
 }
+
+/* ------------------------------------------------------------------ */
+/* Learned swap proposal (exact MH correction)                          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * A small network scores every node of the current order; the scores define
+ * a distribution over unordered node pairs, and the two nodes' positions are
+ * swapped.  Because the proposal is not symmetric, the acceptance test uses
+ * the Metropolis-Hastings ratio with q evaluated in both directions:
+ *     accept iff ln u < [score(new) - score(old)] + ln q(pair | new) - ln q(pair | old).
+ *
+ * Per-node features (8), for node i in order o:
+ *   0 position / n; 1 best consistent local score s(i, best_i);
+ *   2 gap best - second best (0 when the empty set is the only candidate);
+ *   3 sum_m prior(i, m) (prior terms in nats, row); 4 sum_j prior(j, i) (column);
+ *   5, 6, 7 max, mean, standard deviation of s(i, .) over all candidate sets.
+ * They enter the network z-scored: z = (f - mu) / sd.
+ * Network: h1 = relu(W1 z + b1), h2 = relu(W2 h1 + b2), l = w3 . h2 + b3, with
+ * W1 128x8, W2 128x128; parameters flattened as W1, b1, W2, b2, w3, b3 (17,793).
+ * Pair distribution, p = softmax(l) over the n nodes, eps mixing weight:
+ *   q({a,b}) = (1 - eps) p_a p_b (1/(1 - p_a) + 1/(1 - p_b)) + eps * 2 / (n (n - 1)),
+ * i.e. with probability eps a uniform pair, else a ~ p then b ~ p without a.
+ */
+#define ORC_H 128
+#define ORC_F 8
+#define ORC_NPARAM (ORC_H * ORC_F + ORC_H + ORC_H * ORC_H + ORC_H + ORC_H + 1)
+
+int orc_mlp_num_params(void) { return ORC_NPARAM; }
+
+/* max, mean, population standard deviation of each node's row (FP32-rounded values if round_f32). */
+void orc_table_stats(const double *table, int n, int K, int round_f32, double *stats /*[n][3]*/)
+{
+    int64_t S = orc_num_sets(n - 1, K);
+    for (int i = 0; i < n; ++i) {
+        double mx = -INFINITY, sum = 0.0, sq = 0.0;
+        for (int64_t r = 0; r < S; ++r) {
+            double v = table[(int64_t)i * S + r];
+            if (round_f32) v = to_f32(v);
+            if (v > mx) mx = v;
+            sum += v;
+        }
+        double mean = sum / (double)S;
+        for (int64_t r = 0; r < S; ++r) {
+            double v = table[(int64_t)i * S + r];
+            if (round_f32) v = to_f32(v);
+            sq += (v - mean) * (v - mean);
+        }
+        stats[i * 3 + 0] = mx;
+        stats[i * 3 + 1] = mean;
+        stats[i * 3 + 2] = sqrt(sq / (double)S);
+    }
+}
+
+/* Raw features of every node (by node id) for an order, from its per-node
+ * best / second-best scores (as orc_score_order returns them). */
+void orc_features(int n, const int32_t *order, const double *node_best, const double *node_second,
+                  const double *prior_nats /*[n][n] or NULL*/, const double *stats, double *f /*[n][8]*/)
+{
+    for (int p = 0; p < n; ++p) f[order[p] * ORC_F + 0] = (double)p / (double)n;
+    for (int i = 0; i < n; ++i) {
+        double *r = f + i * ORC_F;
+        r[1] = node_best[i];
+        r[2] = isinf(node_second[i]) ? 0.0 : node_best[i] - node_second[i];
+        double row = 0.0, col = 0.0;
+        if (prior_nats)
+            for (int m = 0; m < n; ++m) {
+                if (m == i) continue;
+                row += prior_nats[i * n + m];
+                col += prior_nats[m * n + i];
+            }
+        r[3] = row;
+        r[4] = col;
+        r[5] = stats[i * 3 + 0];
+        r[6] = stats[i * 3 + 1];
+        r[7] = stats[i * 3 + 2];
+    }
+}
+
+/* Forward pass for n nodes: z [n][8] (already normalised) -> logits [n].
+ * pre1/pre2 [n][128] (optional) receive the pre-activations. */
+void orc_mlp_forward(const double *prm, int n, const double *z, double *logits, double *pre1, double *pre2)
+{
+    const double *W1 = prm, *b1 = W1 + ORC_H * ORC_F, *W2 = b1 + ORC_H, *b2 = W2 + ORC_H * ORC_H;
+    const double *w3 = b2 + ORC_H, *b3 = w3 + ORC_H;
+    double h1[ORC_H], h2[ORC_H];
+    for (int i = 0; i < n; ++i) {
+        for (int u = 0; u < ORC_H; ++u) {
+            double a = b1[u];
+            for (int k = 0; k < ORC_F; ++k) a += W1[u * ORC_F + k] * z[i * ORC_F + k];
+            if (pre1) pre1[i * ORC_H + u] = a;
+            h1[u] = a > 0.0 ? a : 0.0;
+        }
+        for (int u = 0; u < ORC_H; ++u) {
+            double a = b2[u];
+            for (int k = 0; k < ORC_H; ++k) a += W2[u * ORC_H + k] * h1[k];
+            if (pre2) pre2[i * ORC_H + u] = a;
+            h2[u] = a > 0.0 ? a : 0.0;
+        }
+        double l = b3[0];
+        for (int u = 0; u < ORC_H; ++u) l += w3[u] * h2[u];
+        logits[i] = l;
+    }
+}
+
+static void softmax(const double *l, int n, double *p)
+{
+    double mx = -INFINITY;
+    for (int i = 0; i < n; ++i) if (l[i] > mx) mx = l[i];
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) { p[i] = exp(l[i] - mx); s += p[i]; }
+    for (int i = 0; i < n; ++i) p[i] /= s;
+}
+
+/* ln q({a, b}) for nodes a != b. */
+double orc_pair_logq(const double *logits, int n, int a, int b, double eps)
+{
+    double p[64];
+    softmax(logits, n, p);
+    double Q = p[a] * p[b] * (1.0 / (1.0 - p[a]) + 1.0 / (1.0 - p[b]));
+    return log((1.0 - eps) * Q + eps * 2.0 / ((double)n * (n - 1)));
+}
+
+/*
+ * Loss -ln q({a,b} | z) of one sample and its gradient, added to grad[]
+ * (same layout as prm).  Returns the loss.
+ */
+double orc_mlp_loss_grad(const double *prm, int n, const double *z, int a, int b, double eps, double *grad)
+{
+    const double *W1 = prm, *b1 = W1 + ORC_H * ORC_F, *W2 = b1 + ORC_H, *b2 = W2 + ORC_H * ORC_H;
+    const double *w3 = b2 + ORC_H;
+    (void)b1; (void)b2;
+    double *gW1 = grad, *gb1 = gW1 + ORC_H * ORC_F, *gW2 = gb1 + ORC_H, *gb2 = gW2 + ORC_H * ORC_H;
+    double *gw3 = gb2 + ORC_H, *gb3 = gw3 + ORC_H;
+    double logits[64], p[64], dl[64];
+    double *pre1 = (double *)malloc(sizeof(double) * (size_t)n * ORC_H);
+    double *pre2 = (double *)malloc(sizeof(double) * (size_t)n * ORC_H);
+    orc_mlp_forward(prm, n, z, logits, pre1, pre2);
+    softmax(logits, n, p);
+    double pa = p[a], pb = p[b];
+    double Q = pa * pb * (1.0 / (1.0 - pa) + 1.0 / (1.0 - pb));
+    double U = 2.0 / ((double)n * (n - 1));
+    double q = (1.0 - eps) * Q + eps * U;
+    /* dQ/dp_a = p_b (1/(1-p_a)^2 + 1/(1-p_b)), dQ/dp_b symmetric; through the softmax:
+       dQ/dl_k = [k=a] g_a + [k=b] g_b - p_k (g_a + g_b), g_x = p_x dQ/dp_x. */
+    double ga = pa * pb * (1.0 / ((1.0 - pa) * (1.0 - pa)) + 1.0 / (1.0 - pb));
+    double gb = pb * pa * (1.0 / ((1.0 - pb) * (1.0 - pb)) + 1.0 / (1.0 - pa));
+    for (int k = 0; k < n; ++k) {
+        double dQ = -p[k] * (ga + gb) + (k == a ? ga : 0.0) + (k == b ? gb : 0.0);
+        dl[k] = -(1.0 - eps) * dQ / q;
+    }
+    for (int i = 0; i < n; ++i) {
+        double h1[ORC_H], h2[ORC_H], d2[ORC_H], d1[ORC_H];
+        for (int u = 0; u < ORC_H; ++u) {
+            h1[u] = pre1[i * ORC_H + u] > 0.0 ? pre1[i * ORC_H + u] : 0.0;
+            h2[u] = pre2[i * ORC_H + u] > 0.0 ? pre2[i * ORC_H + u] : 0.0;
+        }
+        gb3[0] += dl[i];
+        for (int u = 0; u < ORC_H; ++u) {
+            gw3[u] += dl[i] * h2[u];
+            d2[u] = pre2[i * ORC_H + u] > 0.0 ? dl[i] * w3[u] : 0.0;
+            gb2[u] += d2[u];
+        }
+        for (int u = 0; u < ORC_H; ++u)
+            for (int k = 0; k < ORC_H; ++k) gW2[u * ORC_H + k] += d2[u] * h1[k];
+        for (int k = 0; k < ORC_H; ++k) {
+            double s = 0.0;
+            for (int u = 0; u < ORC_H; ++u) s += W2[u * ORC_H + k] * d2[u];
+            d1[k] = pre1[i * ORC_H + k] > 0.0 ? s : 0.0;
+            gb1[k] += d1[k];
+        }
+        for (int u = 0; u < ORC_H; ++u)
+            for (int k = 0; k < ORC_F; ++k) gW1[u * ORC_F + k] += d1[u] * z[i * ORC_F + k];
+    }
+    free(pre1);
+    free(pre2);
+    return -log(q);
+}
+
+/* Draw an unordered node pair from q at iteration `step` (purposes 4: mixture
+ * choice, 5: first node, 6: second node, 1/2: uniform positions); returns the
+ * two POSITIONS to swap. */
+void orc_learned_pair(uint64_t seed, uint64_t chain, int n, uint64_t step, const double *logits,
+                      const int32_t *order, double eps, int *pa_out, int *pb_out)
+{
+    double mix = unit_open(orc_draw(seed, chain, 4, step));
+    if (mix < eps) { orc_swap_pair(seed, chain, n, step, pa_out, pb_out); return; }
+    double p[64];
+    softmax(logits, n, p);
+    double u = unit_open(orc_draw(seed, chain, 5, step));
+    int a = n - 1;
+    double c = 0.0;
+    for (int i = 0; i < n; ++i) { c += p[i]; if (u < c) { a = i; break; } }
+    double v = unit_open(orc_draw(seed, chain, 6, step)) * (1.0 - p[a]);
+    int b = (a == n - 1) ? n - 2 : n - 1;
+    c = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (i == a) continue;
+        c += p[i];
+        if (v < c) { b = i; break; }
+    }
+    int pos_a = 0, pos_b = 0;
+    for (int q = 0; q < n; ++q) { if (order[q] == a) pos_a = q; if (order[q] == b) pos_b = q; }
+    *pa_out = pos_a;
+    *pb_out = pos_b;
+}
+
+static void node_of_positions(const int32_t *order, int pa, int pb, int *a, int *b) { *a = order[pa]; *b = order[pb]; }
+
+/*
+ * MH chain with the learned proposal (same conventions as orc_run_chain).
+ * prm: network parameters; mu, sd: feature normalisation; prior_nats: [n][n]
+ * prior terms or NULL; stats: [n][3] table statistics.
+ */
+void orc_run_chain_learned(const double *table, int n, int K, uint64_t seed, uint64_t chain, int64_t iters,
+                           int target, int round_f32, const double *prm, const double *mu, const double *sd,
+                           const double *prior_nats, const double *stats, double eps,
+                           int32_t *order_out, double *trace, uint8_t *acc, uint64_t *best_graph,
+                           double *best_score, int64_t *accepted)
+{
+    int32_t *cur = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *prop = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    uint64_t *g = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    double nl[64], nb[64], ns[64], f[64 * ORC_F], z[64 * ORC_F], lc[64], lp[64];
+    orc_initial_order(seed, chain, n, cur);
+    double l, m;
+    orc_score_order(table, n, K, cur, round_f32, &l, &m, best_graph, nl, nb, ns);
+    double cur_score = target == 0 ? l : m;
+    *best_score = m;
+    orc_features(n, cur, nb, ns, prior_nats, stats, f);
+    for (int k = 0; k < n * ORC_F; ++k) z[k] = (f[k] - mu[k % ORC_F]) / sd[k % ORC_F];
+    orc_mlp_forward(prm, n, z, lc, NULL, NULL);
+    int64_t nacc = 0;
+    if (trace) trace[0] = cur_score;
+    for (int64_t t = 1; t <= iters; ++t) {
+        int pa, pb, a, b;
+        orc_learned_pair(seed, chain, n, (uint64_t)t, lc, cur, eps, &pa, &pb);
+        node_of_positions(cur, pa, pb, &a, &b);
+        memcpy(prop, cur, sizeof(int32_t) * (size_t)n);
+        prop[pa] = cur[pb];
+        prop[pb] = cur[pa];
+        double pl, pm;
+        orc_score_order(table, n, K, prop, round_f32, &pl, &pm, g, nl, nb, ns);
+        orc_features(n, prop, nb, ns, prior_nats, stats, f);
+        for (int k = 0; k < n * ORC_F; ++k) z[k] = (f[k] - mu[k % ORC_F]) / sd[k % ORC_F];
+        orc_mlp_forward(prm, n, z, lp, NULL, NULL);
+        double new_score = target == 0 ? pl : pm;
+        double ratio = new_score - cur_score + orc_pair_logq(lp, n, a, b, eps) - orc_pair_logq(lc, n, a, b, eps);
+        double u = orc_accept_uniform(seed, chain, (uint64_t)t);
+        int ok = log(u) < ratio;
+        if (ok) {
+            memcpy(cur, prop, sizeof(int32_t) * (size_t)n);
+            memcpy(lc, lp, sizeof(double) * (size_t)n);
+            cur_score = new_score;
+            ++nacc;
+            if (pm > *best_score) {
+                *best_score = pm;
+                memcpy(best_graph, g, sizeof(uint64_t) * (size_t)n);
+            }
+        }
+        if (acc) acc[t - 1] = (uint8_t)ok;
+        if (trace) trace[t] = cur_score;
+    }
+    memcpy(order_out, cur, sizeof(int32_t) * (size_t)n);
+    *accepted = nacc;
+    free(cur);
+    free(prop);
+    free(g);
+}

@@ -154,3 +154,21 @@ def make(w: Workload):
     net = random_network(w.n, w.N, w.arity_choices, w.dmax, w.data_seed)
     prior = random_prior(w.n, w.prior_seed) if w.prior_seed is not None else None
     return net, prior
+
+
+MLP_HIDDEN = 128
+MLP_FEATURES = 8
+
+
+def mlp_params(seed: int, scale: float = 1.0) -> np.ndarray:
+    """Random network parameters (He-style normal draws), flat FP64 in the order
+    W1 [128][8], b1 [128], W2 [128][128], b2 [128], w3 [128], b3 [1]."""
+    rng = np.random.default_rng(seed)
+    H, F = MLP_HIDDEN, MLP_FEATURES
+    W1 = rng.standard_normal((H, F)) * np.sqrt(2.0 / F) * scale
+    b1 = rng.standard_normal(H) * 0.1 * scale
+    W2 = rng.standard_normal((H, H)) * np.sqrt(2.0 / H) * scale
+    b2 = rng.standard_normal(H) * 0.1 * scale
+    w3 = rng.standard_normal(H) * np.sqrt(1.0 / H) * scale
+    b3 = np.zeros(1)
+    return np.concatenate([W1.ravel(), b1, W2.ravel(), b2, w3, b3])
