@@ -170,6 +170,67 @@ def bench_uneven(bnos, datagen, n_datasets: int, chains: int, iters: int, seed: 
             "speedup": seq / one}
 
 
+def bench_learned(bnos, datagen, wname: str, chains: int, harvest_iters: int, iters: int, epochs: int,
+                  seed: int = 404):
+    """Learned swap proposal: harvest accepted moves from uniform chains, train the
+    network on the device, then run learned and uniform chains from the same
+    starting orders; ESS/s of the log-sum-exp trace and best-graph score."""
+    import torch
+    from paper_1210_5128_amd import ess as E
+    w = datagen.WORKLOADS[wname]
+    net, prior = datagen.make(w)
+    table = bnos.build_score_table(net.data, net.arities, w.K, ess=w.ess, prior=prior)
+    n = w.n
+    out = {"workload": f"{w.name}: n={n}, K={w.K}, N={w.N}", "chains": chains, "iterations": iters}
+    # 1. harvest
+    cap = max(1, harvest_iters // 2)
+    st = table.new_chain_state(chains, harvest_iters, trace_every=harvest_iters, harvest_cap=cap)
+    t0 = time.perf_counter()
+    table.run_chains(st, harvest_iters, seed + 1, trace_every=harvest_iters)
+    torch.cuda.synchronize()
+    cnt = st["harvest_count"].cpu().numpy()
+    feats = torch.cat([st["harvest_feats"][c, :int(cnt[c])] for c in range(chains)])
+    pairs = torch.cat([st["harvest_pairs"][c, :int(cnt[c])] for c in range(chains)])
+    out["harvest"] = {"moves": int(feats.shape[0]), "seconds": time.perf_counter() - t0}
+    # 2. train
+    m = bnos.Mlp()
+    m.set_params(datagen.mlp_params(seed + 2, scale=0.5).astype(np.float32))
+    m.fit_norm(feats)
+    steps = epochs * ((feats.shape[0] + 1023) // 1024)
+    trace = torch.zeros(max(steps, 1), dtype=torch.float32, device=feats.device)
+    t0 = time.perf_counter()
+    m.train(feats, pairs, epochs=epochs, batch=1024, lr=2e-3, seed=seed + 3, loss_trace=trace)
+    torch.cuda.synchronize()
+    tr = trace.cpu().numpy()
+    out["train"] = {"epochs": epochs, "steps": int(steps), "seconds": time.perf_counter() - t0,
+                    "loss_first": float(tr[:10].mean()), "loss_last": float(tr[-10:].mean()),
+                    "uniform_pair_loss": float(np.log(n * (n - 1) / 2))}
+    # 3. learned vs uniform, same chain ids (same initial orders)
+    for label, mlp in (("uniform", None), ("learned", m)):
+        s2 = table.new_chain_state(chains, iters, trace_every=1)
+        table.run_chains(s2, 20, seed + 9, mlp=mlp)                    # warm-up
+        torch.cuda.synchronize()
+        s2 = table.new_chain_state(chains, iters, trace_every=1)
+        t0 = time.perf_counter()
+        table.run_chains(s2, iters, seed, mlp=mlp)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        trc = s2["trace"].cpu().numpy()
+        e = E.ess(trc)
+        out[label] = {"seconds": dt, "chain_iterations_per_s": chains * iters / dt, "ess": e, "ess_per_s": e / dt,
+                      "accept_rate": float(s2["accepted"].sum().item()) / (chains * iters),
+                      "best_score_max": float(s2["best_scores"].max().item()),
+                      "best_score_mean": float(s2["best_scores"].mean().item()),
+                      "final_score_mean": float(s2["scores"].mean().item()),
+                      "split_rhat": E.split_rhat(trc)}
+        print(f"# {label}: {dt:.2f} s, ESS/s {e / dt:.1f}, accept {out[label]['accept_rate']:.3f}",
+              file=sys.stderr, flush=True)
+    out["ess_per_s_ratio_learned_vs_uniform"] = out["learned"]["ess_per_s"] / max(out["uniform"]["ess_per_s"], 1e-30)
+    m.free()
+    table.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,6 +244,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--chains", type=int, default=256, help="batched chains on the mixed40 table (0 = skip)")
     ap.add_argument("--chain-iters", type=int, default=20000)
+    ap.add_argument("--learned", type=int, default=0, metavar="C",
+                    help="also run the learned-proposal comparison with C chains on the mixed60 table (0 = skip)")
+    ap.add_argument("--learned-iters", type=int, default=2000)
+    ap.add_argument("--learned-workload", default="mixed60")
     ap.add_argument("--uneven", type=int, default=0, metavar="D",
                     help="also run the uneven family: D datasets x 64 chains in one launch vs one at a time")
     ap.add_argument("--uneven-iters", type=int, default=1000)
@@ -227,7 +292,8 @@ def main():
 
     bytes_per_pass = 12 * n * S                           # (u64 mask + f32 score) per entry, one full scan
 
-    def timed(Bq, steps, warmup):
+    def timed(Bq, steps, warmup, skip=True):
+        table.tile_skip(skip)
         pool = max(8, min(64, steps))
         orders = torch.from_numpy(datagen.random_orders(n, pool * Bq, seed=5 + Bq).reshape(pool, Bq, n)).to(dev)
         lse = torch.empty(Bq, dtype=torch.float64, device=dev)
@@ -247,18 +313,33 @@ def main():
         torch.cuda.synchronize()
         total_ms = ev0.elapsed_time(ev1)
         k_ms, k_launches, k_passes = table.timing_read()
+        tiles, tiles_per_pass = table.tiles_read()
         table.timing(False)
         kernel_avg_ms = k_ms / k_launches
         passes_per_launch = k_passes / k_launches
-        gbs = bytes_per_pass * passes_per_launch / (kernel_avg_ms / 1e3) / 1e9
+        # bytes the launch had to read: with tile skipping, the tiles it loaded
+        # (256 entries x 12 B) plus every tile's 8-byte summary; without, the full scan
+        if skip:
+            alg = tiles / k_launches * 256 * 12 + passes_per_launch * tiles_per_pass * 8
+        else:
+            alg = bytes_per_pass * passes_per_launch
+        gbs = alg / (kernel_avg_ms / 1e3) / 1e9
         return dict(total_ms=total_ms, ms_per_step=total_ms / steps, value=Bq * steps / (total_ms / 1e3),
-                    kernel_avg_ms=kernel_avg_ms, passes_per_launch=passes_per_launch, gbs=gbs)
+                    kernel_avg_ms=kernel_avg_ms, passes_per_launch=passes_per_launch, gbs=gbs, alg_bytes=alg,
+                    tile_fraction=tiles / max(1, k_passes * tiles_per_pass),
+                    full_scan_equiv_gbs=bytes_per_pass * passes_per_launch / (kernel_avg_ms / 1e3) / 1e9)
 
     stream = torch.cuda.current_stream()
-    r = timed(B, args.steps, args.warmup)
+    rf = timed(B, args.steps, args.warmup, skip=False)         # full scan of every entry
+    print(f"# full scan: {rf['total_ms']:.3f} ms for {args.steps} steps", file=sys.stderr, flush=True)
+    r = timed(B, args.steps, args.warmup, skip=True)           # with tile summaries (default path)
     print(f"# timed {args.steps} steps: {r['total_ms']:.3f} ms", file=sys.stderr, flush=True)
     ms_per_step, value = r["ms_per_step"], r["value"]
     kernel_avg_ms, passes_per_launch, achieved_gbs = r["kernel_avg_ms"], r["passes_per_launch"], r["gbs"]
+    full_scan = {"order_scores_per_s": rf["value"], "ms_per_step": rf["ms_per_step"],
+                 "kernel_avg_us": rf["kernel_avg_ms"] * 1e3, "algorithmic_bytes_per_launch": rf["alg_bytes"],
+                 "achieved_GBs": rf["gbs"], "frac": rf["gbs"] / HBM_PEAK_GBS,
+                 "traffic": measured_traffic(B) if args.workload == "mixed60" else None}
     batched = None
     if args.batched_check:
         rb = timed(args.batched_check, 20, 3)
@@ -292,11 +373,14 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": measured_traffic(B) if args.workload == "mixed60" else None,
-            "kernel": "k_score",
+            "traffic": None,
+            "kernel": "k_score (tile skipping)",
             "kernel_avg_us": kernel_avg_ms * 1e3,
-            "algorithmic_bytes_per_launch": bytes_per_pass * passes_per_launch,
+            "algorithmic_bytes_per_launch": r["alg_bytes"],
+            "tile_fraction_read": r["tile_fraction"],
+            "full_scan_equivalent_GBs": r["full_scan_equiv_gbs"],
         },
+        "full_scan": full_scan,
         "batched": batched,
         "build_s": build_s,
         "table_device_bytes": info["device_bytes"],
@@ -307,6 +391,9 @@ def main():
         out["chains"] = bench_chains(bnos, datagen, "mixed40", args.chains, args.chain_iters)
     if args.uneven:
         out["uneven"] = bench_uneven(bnos, datagen, args.uneven, 64, args.uneven_iters)
+    if args.learned:
+        out["learned"] = bench_learned(bnos, datagen, args.learned_workload, args.learned, args.learned_iters,
+                                       args.learned_iters, epochs=4)
     if not args.no_cpu:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(net, prior, K)

@@ -109,6 +109,13 @@ bnos_status bnos_table_export(bnos_table t, int32_t node, uint64_t *masks, float
                               int64_t cap);
 
 /*
+ * The per-node static features of the learned proposal, host double [n][5]:
+ * sum of the node's prior terms as child (row), as parent (column), and the
+ * max, mean and population standard deviation of its stored scores.  Sync.
+ */
+bnos_status bnos_table_node_features(bnos_table t, double *out);
+
+/*
  * Contingency counts N_ijk on the device for Q queries (node[q], parent
  * mask[q]), with the same counting kernel the table build uses.
  *   nodes, masks   host arrays [Q]; masks must not contain the query's node
@@ -151,6 +158,58 @@ bnos_status bnos_score_order(bnos_table t, const int32_t *order, double *lse, do
                              uint64_t *best_parents);
 
 /*
+ * Learned swap proposal: a network that scores every node of an order; the
+ * pair of nodes whose positions are swapped is drawn from
+ *   q({a,b}) = (1 - eps) p_a p_b (1/(1 - p_a) + 1/(1 - p_b)) + eps * 2/(n(n-1)),
+ * p = softmax of the node scores, and the MH test uses q in both directions,
+ * so the chains still sample the posterior over orders (Sec. III.C's
+ * acceptance rule with the Metropolis-Hastings proposal ratio).
+ *
+ * Per-node features (8), raw, in this order: position / n; best consistent
+ * local score; best minus second best (0 if the empty set is the only
+ * candidate); sum of the node's prior terms as child (row); as parent
+ * (column); max, mean and standard deviation of the node's local scores.
+ * The network z-scores them with (mu, sd), then computes
+ *   h1 = relu(W1 z + b1), h2 = relu(W2 h1 + b2), logit = w3 . h2 + b3,
+ * W1 128x8, W2 128x128.  Flat parameter layout (17,793 floats):
+ *   W1 [128][8], b1 [128], W2 [128][128], b2 [128], w3 [128], b3 [1].
+ * The device keeps FP32 master weights; W1, W2, w3 and the activations enter
+ * the matrix cores in BF16 (round to nearest even) with FP32 accumulation.
+ */
+typedef struct bnos_mlp_s *bnos_mlp;
+
+/* New network on the current device: all parameters 0, mu = 0, sd = 1. */
+bnos_status bnos_mlp_create(bnos_mlp *out);
+void bnos_mlp_free(bnos_mlp m);
+
+/* Host arrays; params [17793] or NULL (keep), mu/sd [8] or NULL (keep).
+ * Setting parameters resets the optimiser state.  Synchronous. */
+bnos_status bnos_mlp_set_params(bnos_mlp m, const float *params, const float *mu, const float *sd);
+bnos_status bnos_mlp_get_params(bnos_mlp m, float *params, float *mu, float *sd);
+
+/* mu, sd := per-feature mean and population standard deviation of the rows
+ * of feats (DEVICE float [rows][8]); an sd below 1e-6 becomes 1.  Async. */
+bnos_status bnos_mlp_fit_norm(bnos_mlp m, const float *feats, int64_t rows, void *stream);
+
+/* logits (DEVICE float [R][n]) of R samples of n nodes (DEVICE float [R][n][8]
+ * raw features); 2 <= n <= 64.  Async. */
+bnos_status bnos_mlp_forward(bnos_mlp m, const float *feats, int32_t R, int32_t n, float *logits, void *stream);
+
+/* Mean over R samples of -ln q(pair | sample) and its gradient (DEVICE float
+ * [17793], flat layout) w.r.t. the FP32 parameters; pairs DEVICE int32 [R][2]
+ * node ids (a != b); loss DEVICE double [1] or NULL.  Synchronous. */
+bnos_status bnos_mlp_grad(bnos_mlp m, const float *feats, const int32_t *pairs, int32_t R, int32_t n, float eps,
+                          float *grad, double *loss, void *stream);
+
+/* Adam (beta1 0.9, beta2 0.999, 1e-8) on the mean loss over minibatches of
+ * `batch` samples, `epochs` passes over the count samples, each epoch in a
+ * seeded pseudo-random order; loss_trace DEVICE float [steps] or NULL.
+ * Synchronous. */
+bnos_status bnos_mlp_train(bnos_mlp m, const float *feats, const int32_t *pairs, int64_t count, int32_t n,
+                           float eps, int32_t epochs, int32_t batch, float lr, uint64_t seed, float *loss_trace,
+                           void *stream);
+
+/*
  * Metropolis-Hastings over orders (Sec. III.C), many chains at once.
  *
  * Iteration t = 0 adopts each chain's initial order (a uniform permutation:
@@ -183,7 +242,10 @@ typedef struct {
     int32_t trace_every;      /* >= 1; trace entry j is the score after iteration
                                  first_iteration + j*trace_every, j = 0..iterations/trace_every */
     int32_t sweep_len;        /* iterations per captured graph; 0 = 32 */
-    int32_t reserved[6];      /* must be zero */
+    int32_t proposal;         /* 0: uniform swap of two positions; 1: learned (needs mlp) */
+    float eps;                /* learned: weight of the uniform pair in q, (0, 1]; 0 means 0.1 */
+    struct bnos_mlp_s *mlp;   /* learned: the network (see bnos_mlp_*), read during the call */
+    int32_t reserved[4];      /* must be zero */
 } bnos_chain_cfg;
 
 typedef struct {              /* DEVICE pointers; the chain state, read when resuming, written always */
@@ -194,6 +256,14 @@ typedef struct {              /* DEVICE pointers; the chain state, read when res
     int64_t *accepted;        /* [C] accepted moves since iteration 0 */
     double *trace;            /* [C][iterations/trace_every + 1] or NULL */
     uint8_t *accept_flags;    /* [C][iterations] or NULL: move of iteration first_iteration+1+k accepted */
+    /* Harvest of accepted moves (all NULL / 0 = off): chain c stores its k-th
+       accepted move, k < harvest_cap, as the raw features [n][8] of the order
+       before the move (see the learned proposal above) and the swapped node
+       pair; harvest_count[c] counts the stored moves (in/out). */
+    float *harvest_feats;     /* [C][harvest_cap][n][8] */
+    int32_t *harvest_pairs;   /* [C][harvest_cap][2] node ids */
+    int64_t *harvest_count;   /* [C] */
+    int64_t harvest_cap;
 } bnos_chain_state;
 
 /*
@@ -227,6 +297,17 @@ bnos_status bnos_run_chains_multi(const bnos_table *tables, int32_t T, const bno
  * enable, then keeps counting.  Any output pointer may be NULL.
  */
 bnos_status bnos_table_timing(bnos_table t, int32_t enable);
+
+/*
+ * Tile skipping (on by default): the table keeps, for every 256-entry tile,
+ * the AND of its masks; a tile whose AND contains a node outside an order's
+ * predecessor set holds no consistent entry for that order, and a tile no
+ * order of a block needs is not read.  Results are identical with it off.
+ * bnos_table_tiles_read returns the tiles read by scoring launches while
+ * timing was on, and the tiles of one full pass (n * padded entries / 256).
+ */
+bnos_status bnos_table_tile_skip(bnos_table t, int32_t enable);
+bnos_status bnos_table_tiles_read(bnos_table t, int64_t *tiles_loaded, int64_t *tiles_per_pass);
 bnos_status bnos_table_timing_read(bnos_table t, double *total_ms, int64_t *launches,
                                    int64_t *table_passes);
 

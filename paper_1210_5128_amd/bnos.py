@@ -37,12 +37,14 @@ class BuildOpts(ctypes.Structure):
 class ChainCfg(ctypes.Structure):
     _fields_ = [("chains", ctypes.c_int32), ("target", ctypes.c_int32), ("iterations", ctypes.c_int64),
                 ("first_iteration", ctypes.c_int64), ("seed", ctypes.c_uint64), ("chain_offset", ctypes.c_int64),
-                ("trace_every", ctypes.c_int32), ("sweep_len", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("trace_every", ctypes.c_int32), ("sweep_len", ctypes.c_int32), ("proposal", ctypes.c_int32),
+                ("eps", ctypes.c_float), ("mlp", P), ("reserved", ctypes.c_int32 * 4)]
 
 
 class ChainState(ctypes.Structure):
     _fields_ = [("orders", P), ("scores", P), ("best_graphs", P), ("best_scores", P), ("accepted", P),
-                ("trace", P), ("accept_flags", P)]
+                ("trace", P), ("accept_flags", P), ("harvest_feats", P), ("harvest_pairs", P),
+                ("harvest_count", P), ("harvest_cap", ctypes.c_int64)]
 
 
 _SIGS = {
@@ -52,12 +54,23 @@ _SIGS = {
     "bnos_table_free": (None, [P]),
     "bnos_table_info": (i32, [P, P, P, P, P]),
     "bnos_table_export": (i32, [P, i32, P, P, i64]),
+    "bnos_table_node_features": (i32, [P, P]),
     "bnos_counts": (i32, [P, i32, P, P, P, i64]),
     "bnos_score_orders": (i32, [P, P, i32, P, P, P, P, P, P]),
     "bnos_score_order": (i32, [P, P, P, P, P]),
     "bnos_run_chains": (i32, [P, P, P, P]),
     "bnos_run_chains_multi": (i32, [P, i32, P, P, P]),
+    "bnos_mlp_create": (i32, [P]),
+    "bnos_mlp_free": (None, [P]),
+    "bnos_mlp_set_params": (i32, [P, P, P, P]),
+    "bnos_mlp_get_params": (i32, [P, P, P, P]),
+    "bnos_mlp_fit_norm": (i32, [P, P, i64, P]),
+    "bnos_mlp_forward": (i32, [P, P, i32, i32, P, P]),
+    "bnos_mlp_grad": (i32, [P, P, P, i32, i32, ctypes.c_float, P, P, P]),
+    "bnos_mlp_train": (i32, [P, P, P, i64, i32, ctypes.c_float, i32, i32, ctypes.c_float, ctypes.c_uint64, P, P]),
     "bnos_table_timing": (i32, [P, i32]),
+    "bnos_table_tile_skip": (i32, [P, i32]),
+    "bnos_table_tiles_read": (i32, [P, P, P]),
     "bnos_table_timing_read": (i32, [P, P, P, P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -168,8 +181,14 @@ class Table:
         return lse.value, mx.value, best
 
     # -- chains
+    def node_features(self):
+        """Static per-node features [n][5]: prior row sum, column sum, max, mean, sd of the scores."""
+        out = np.zeros((self.n, 5))
+        _check(_lib.bnos_table_node_features(self._h, _ptr(out)))
+        return out
+
     def new_chain_state(self, chains: int, iterations: int, trace_every: int = 1, flags: bool = False,
-                        device=None):
+                        device=None, harvest_cap: int = 0):
         """Device tensors holding the state of `chains` chains (see bnos_chain_state)."""
         import torch
         dev = device or torch.device("cuda")
@@ -184,15 +203,30 @@ class Table:
                    if trace_every > 0 else None),
             accept_flags=torch.zeros((chains, max(iterations, 1)), dtype=torch.uint8, device=dev) if flags else None,
         )
+        if harvest_cap > 0:
+            st["harvest_feats"] = torch.zeros((chains, harvest_cap, n, 8), dtype=torch.float32, device=dev)
+            st["harvest_pairs"] = torch.zeros((chains, harvest_cap, 2), dtype=torch.int32, device=dev)
+            st["harvest_count"] = torch.zeros(chains, dtype=torch.int64, device=dev)
         return st
 
     def run_chains(self, state: dict, iterations: int, seed: int, target: int = 0, first_iteration: int = 0,
-                   trace_every: int = 1, chain_offset: int = 0, sweep_len: int = 0, stream=None):
-        """Run MH chains in place on `state` (from new_chain_state); returns when done."""
+                   trace_every: int = 1, chain_offset: int = 0, sweep_len: int = 0, mlp=None, eps=0.1, stream=None):
+        """Run MH chains in place on `state` (from new_chain_state); returns when done.
+        With `mlp` the swap pair comes from the learned proposal (exact MH correction)."""
         chains = int(state["orders"].shape[0])
-        cfg = _chain_cfg(chains, iterations, seed, target, first_iteration, trace_every, chain_offset, sweep_len)
+        cfg = _chain_cfg(chains, iterations, seed, target, first_iteration, trace_every, chain_offset, sweep_len,
+                         mlp, eps)
         st = _chain_state(state, iterations, trace_every)
         _check(_lib.bnos_run_chains(self._h, ctypes.byref(cfg), ctypes.byref(st), _stream(stream)))
+
+    def tile_skip(self, enable: bool):
+        _check(_lib.bnos_table_tile_skip(self._h, int(enable)))
+
+    def tiles_read(self):
+        """-> (tiles read by timed scoring launches, tiles of one full pass)."""
+        a, b = i64(), i64()
+        _check(_lib.bnos_table_tiles_read(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     # -- timing
     def timing(self, enable: bool):
@@ -205,8 +239,75 @@ class Table:
         return ms.value, cnt.value, passes.value
 
 
-def _chain_cfg(chains, iterations, seed, target, first_iteration, trace_every, chain_offset, sweep_len):
+NPARAM = 17793
+
+
+class Mlp:
+    """The learned swap proposal's network (see bnos_mlp_* in bnos.h)."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(_lib.bnos_mlp_create(ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h:
+            _lib.bnos_mlp_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def set_params(self, params=None, mu=None, sd=None):
+        p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        if p is not None and p.size != NPARAM:
+            raise ValueError("expected 17793 parameters")
+        m = None if mu is None else np.ascontiguousarray(mu, dtype=np.float32)
+        d = None if sd is None else np.ascontiguousarray(sd, dtype=np.float32)
+        _check(_lib.bnos_mlp_set_params(self._h, None if p is None else _ptr(p), None if m is None else _ptr(m),
+                                        None if d is None else _ptr(d)))
+
+    def get_params(self):
+        p = np.zeros(NPARAM, dtype=np.float32)
+        mu = np.zeros(8, dtype=np.float32)
+        sd = np.zeros(8, dtype=np.float32)
+        _check(_lib.bnos_mlp_get_params(self._h, _ptr(p), _ptr(mu), _ptr(sd)))
+        return p, mu, sd
+
+    def fit_norm(self, feats, stream=None):
+        rows = int(feats.numel() // 8)
+        _check(_lib.bnos_mlp_fit_norm(self._h, _dptr(feats), rows, _stream(stream)))
+
+    def forward(self, feats, logits, stream=None):
+        R, n = int(feats.shape[0]), int(feats.shape[1])
+        _check(_lib.bnos_mlp_forward(self._h, _dptr(feats), R, n, _dptr(logits), _stream(stream)))
+
+    def grad(self, feats, pairs, grad, loss=None, eps=0.1, stream=None):
+        R, n = int(feats.shape[0]), int(feats.shape[1])
+        _check(_lib.bnos_mlp_grad(self._h, _dptr(feats), _dptr(pairs), R, n, eps, _dptr(grad), _dptr(loss),
+                                  _stream(stream)))
+
+    def train(self, feats, pairs, epochs, batch, lr, seed, eps=0.1, loss_trace=None, count=None, stream=None):
+        n = int(feats.shape[1])
+        cnt = int(feats.shape[0]) if count is None else int(count)
+        _check(_lib.bnos_mlp_train(self._h, _dptr(feats), _dptr(pairs), cnt, n, eps, epochs, batch, lr, seed,
+                                   _dptr(loss_trace), _stream(stream)))
+
+
+def _chain_cfg(chains, iterations, seed, target, first_iteration, trace_every, chain_offset, sweep_len,
+               mlp=None, eps=0.1):
     cfg = ChainCfg()
+    if mlp is not None:
+        cfg.proposal = 1
+        cfg.mlp = mlp.handle
+        cfg.eps = eps
     cfg.chains = chains
     cfg.target = target
     cfg.iterations = iterations
@@ -220,9 +321,12 @@ def _chain_cfg(chains, iterations, seed, target, first_iteration, trace_every, c
 
 def _chain_state(state: dict, iterations: int, trace_every: int) -> ChainState:
     st = ChainState()
-    for k in ("orders", "scores", "best_graphs", "best_scores", "accepted", "trace", "accept_flags"):
+    for k in ("orders", "scores", "best_graphs", "best_scores", "accepted", "trace", "accept_flags",
+              "harvest_feats", "harvest_pairs", "harvest_count"):
         v = state.get(k)
         setattr(st, k, None if v is None else v.data_ptr())
+    if state.get("harvest_feats") is not None:
+        st.harvest_cap = int(state["harvest_feats"].shape[1])
     if state.get("trace") is not None and state["trace"].shape[1] < iterations // max(1, trace_every) + 1:
         raise ValueError("trace tensor too small")
     if state.get("accept_flags") is not None and state["accept_flags"].shape[1] < iterations:
@@ -231,13 +335,14 @@ def _chain_state(state: dict, iterations: int, trace_every: int) -> ChainState:
 
 
 def run_chains_multi(tables, states, iterations: int, seed: int, target: int = 0, first_iteration: int = 0,
-                     trace_every: int = 1, chain_offset: int = 0, sweep_len: int = 0, stream=None):
+                     trace_every: int = 1, chain_offset: int = 0, sweep_len: int = 0, mlp=None, eps=0.1, stream=None):
     """Advance the chains of several tables in one set of launches (bnos_run_chains_multi)."""
     T = len(tables)
     chains = int(states[0]["orders"].shape[0])
     if any(int(s["orders"].shape[0]) != chains for s in states):
         raise ValueError("every table needs the same number of chains")
-    cfg = _chain_cfg(chains, iterations, seed, target, first_iteration, trace_every, chain_offset, sweep_len)
+    cfg = _chain_cfg(chains, iterations, seed, target, first_iteration, trace_every, chain_offset, sweep_len,
+                     mlp, eps)
     hs = (P * T)(*[t.handle.value for t in tables])
     sts = (ChainState * T)(*[_chain_state(s, iterations, trace_every) for s in states])
     _check(_lib.bnos_run_chains_multi(hs, T, ctypes.byref(cfg), sts, _stream(stream)))

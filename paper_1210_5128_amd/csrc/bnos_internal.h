@@ -46,6 +46,10 @@ struct TableT {
     int64_t *d_nsets = nullptr;     // [64][8] number of masks over `bit` bits with <= k members
     uint64_t *d_masks = nullptr;    // [n][S_pad]
     float *d_scores = nullptr;      // [n][S_pad]
+    double *d_nstat = nullptr;      // [n][5]: prior row sum, prior column sum, max, mean, sd of the row
+    uint64_t *d_tand = nullptr;     // [n * S_pad / 256]: AND of the masks of each 256-entry tile
+    unsigned long long *d_tiles = nullptr;   // tiles read by timed scoring launches
+    bool tile_skip = true;
 
     // order-scoring workspace: per (order, node, chunk) partial reductions
     void *d_part = nullptr;

@@ -45,8 +45,8 @@ void unregister_handle(TableT *t)
 int64_t TableT::device_bytes() const
 {
     return (int64_t)n * S_pad * (int64_t)(sizeof(uint64_t) + sizeof(float)) + (int64_t)n * N_pad +
-           (int64_t)n * (int64_t)(sizeof(int32_t) + n * sizeof(double)) + 64 * 8 * 8 +
-           part_orders * workspace_bytes_per_order();
+           (int64_t)n * (int64_t)(sizeof(int32_t) + n * sizeof(double) + 5 * sizeof(double)) + 64 * 8 * 8 +
+           part_orders * workspace_bytes_per_order() + (int64_t)n * (S_pad / 256) * 8;
 }
 
 // ------------------------------------------------------------------ device helpers
@@ -254,6 +254,77 @@ __global__ __launch_bounds__(WAVES * 64) void k_build(
     }
 }
 
+// Per-node static features of the learned proposal: prior terms summed as
+// child (row) and as parent (column), and max, mean and population standard
+// deviation of the node's stored FP32 scores (FP64 sums, fixed tree).
+__global__ __launch_bounds__(1024) void k_node_stats(const float *__restrict__ scores, int64_t S, int64_t S_pad,
+                                                     const double *__restrict__ prior, int n,
+                                                     double *__restrict__ out)
+{
+    __shared__ double s_a[1024], s_b[1024];
+    const int node = blockIdx.x;
+    const int tid = threadIdx.x;
+    const float *row = scores + (int64_t)node * S_pad;
+    double mx = -INFINITY, sum = 0.0;
+    for (int64_t e = tid; e < S; e += 1024) {
+        const double v = row[e];
+        mx = v > mx ? v : mx;
+        sum += v;
+    }
+    s_a[tid] = mx;
+    s_b[tid] = sum;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if (tid < w) {
+            s_a[tid] = s_a[tid + w] > s_a[tid] ? s_a[tid + w] : s_a[tid];
+            s_b[tid] += s_b[tid + w];
+        }
+        __syncthreads();
+    }
+    const double gmax = s_a[0];
+    const double mean = s_b[0] / (double)S;
+    __syncthreads();
+    double sq = 0.0;
+    for (int64_t e = tid; e < S; e += 1024) {
+        const double d = (double)row[e] - mean;
+        sq += d * d;
+    }
+    s_b[tid] = sq;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if (tid < w) s_b[tid] += s_b[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double rs = 0.0, cs = 0.0;
+        for (int m = 0; m < n; ++m) {
+            if (m == node) continue;
+            rs += prior[(int64_t)node * n + m];
+            cs += prior[(int64_t)m * n + node];
+        }
+        double *o = out + (int64_t)node * 5;
+        o[0] = rs;
+        o[1] = cs;
+        o[2] = gmax;
+        o[3] = mean;
+        o[4] = sqrt(s_b[0] / (double)S);
+    }
+}
+
+// AND of the masks of every 256-entry tile (one wavefront per tile).
+__global__ __launch_bounds__(256) void k_tile_and(const uint64_t *__restrict__ masks, int64_t tiles,
+                                                  uint64_t *__restrict__ tand)
+{
+    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (tile >= tiles) return;                       // uniform per wavefront
+    const uint64_t *p = masks + tile * 256 + lane * 4;
+    uint64_t v = p[0] & p[1] & p[2] & p[3];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v &= (uint64_t)__shfl_xor((unsigned long long)v, off, 64);
+    if (lane == 0) tand[tile] = v;
+}
+
 // Counts for explicit (node, parent mask) queries, with the build's counting code.
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_counts(
@@ -323,6 +394,9 @@ static void free_device(TableT *t)
     hipFree(t->d_nsets);
     hipFree(t->d_masks);
     hipFree(t->d_scores);
+    hipFree(t->d_nstat);
+    hipFree(t->d_tand);
+    hipFree(t->d_tiles);
     hipFree(t->d_part);
     for (auto e : t->ev_start) hipEventDestroy(e);
     for (auto e : t->ev_stop) hipEventDestroy(e);
@@ -449,6 +523,9 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     ALLOC(t->d_nsets, sizeof(int64_t) * 64 * 8);
     ALLOC(t->d_masks, sizeof(uint64_t) * (size_t)n * t->S_pad);
     ALLOC(t->d_scores, sizeof(float) * (size_t)n * t->S_pad);
+    ALLOC(t->d_nstat, sizeof(double) * (size_t)n * 5);
+    ALLOC(t->d_tand, sizeof(uint64_t) * (size_t)n * (t->S_pad / 256));
+    ALLOC(t->d_tiles, sizeof(unsigned long long));
 #undef ALLOC
     int8_t *d_rows = nullptr;
     float *d_prior_in = nullptr;
@@ -480,6 +557,16 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     int cap = cells_cap_for(max_cells);
     if (waves_for_cells(cap) == 4) { CK(launch_build<4>(t, st, cap)); }
     else { CK(launch_build<1>(t, st, cap)); }
+    hipLaunchKernelGGL(k_node_stats, dim3(n), dim3(1024), 0, st, t->d_scores, t->S, t->S_pad, t->d_prior, n,
+                       t->d_nstat);
+    CK(hipGetLastError());
+    {
+        const int64_t tiles = (int64_t)n * (t->S_pad / 256);
+        hipLaunchKernelGGL(k_tile_and, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, t->d_masks, tiles,
+                           t->d_tand);
+        CK(hipGetLastError());
+        CK(hipMemsetAsync(t->d_tiles, 0, sizeof(unsigned long long), st));
+    }
     CK(hipStreamSynchronize(st));
     hipFree(d_rows);
     hipFree(d_prior_in);
@@ -580,5 +667,15 @@ extern "C" bnos_status bnos_counts(bnos_table h, int32_t Q, const int32_t *nodes
     CK(hipMemcpy(counts, d_out, sizeof(uint32_t) * tot, hipMemcpyDeviceToHost));
 #undef CK
     cleanup();
+    return BNOS_OK;
+}
+
+extern "C" bnos_status bnos_table_node_features(bnos_table h, double *out)
+{
+    TableT *t = reinterpret_cast<TableT *>(h);
+    if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
+    if (!out) { set_error("out is NULL"); return BNOS_E_INVALID; }
+    BNOS_HIP(hipSetDevice(t->device));
+    BNOS_HIP(hipMemcpy(out, t->d_nstat, sizeof(double) * 5 * t->n, hipMemcpyDeviceToHost));
     return BNOS_OK;
 }

@@ -11,6 +11,7 @@
 
 #include "bnos_internal.h"
 #include "score_device.h"
+#include "mlp_device.h"
 
 namespace bnos {
 
@@ -78,6 +79,20 @@ struct ChainView {
     int64_t trace_len;
     uint8_t *flags;            // [C][iterations] or null
     int64_t iterations;
+    double *node_sec;          // [C][n] per-node second-best score of the current order
+    const double *nstat;       // [n][5] static node features of the table
+    // learned proposal
+    int proposal;              // 0 uniform, 1 learned
+    double eps;
+    MlpView mlp;
+    float *cur_logit;          // [C][n] network scores of the current order
+    double *lq_fwd;            // [C] ln q(pending pair | current order)
+    int32_t *pend;             // [C][2] node ids of the pending pair
+    // harvest of accepted moves
+    float *hv_feat;            // [C][hv_cap][n][8] or null
+    int32_t *hv_pair;          // [C][hv_cap][2]
+    int64_t *hv_count;         // [C]
+    int64_t hv_cap;
 };
 
 __device__ __forceinline__ uint64_t all_nodes(int n) { return n == 64 ? ~0ull : ((1ull << n) - 1ull); }
@@ -155,30 +170,42 @@ __global__ __launch_bounds__(kListThreads) void k_worklist(const ChainView *__re
 
 // Block per chain: merge the chunk partials of the window nodes, combine with
 // the cached values of the other nodes (per-order sums in node order with a
-// fixed butterfly, as a full rescoring would), take the MH decision, update
-// the caches and the best-graph record, and write the next proposal.
+// fixed butterfly, as a full rescoring would), take the MH decision (with the
+// proposal ratio q(pair|new)/q(pair|old) for the learned proposal), update the
+// caches and the best-graph record, harvest the accepted move, and draw the
+// next proposal.
 __global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(const TabView *__restrict__ tviews,
                                                                  const ChainView *__restrict__ views,
                                                                  const int64_t *__restrict__ chain_base, int T)
 {
-    __shared__ double s_l[64], s_b[64];
+    __shared__ double s_l[64], s_b[64], s_s[64];
     __shared__ uint64_t s_bm[64];
-    __shared__ int s_nodes[64];
+    __shared__ int s_nodes[64], s_posp[64], s_posc[64];
     __shared__ int s_cnt;
+    __shared__ float s_feat[64 * kF];
+    __shared__ MlpLds s_mlp;
     const int k = find_segment(chain_base, T, (int64_t)blockIdx.x);
     const ChainView &H = views[k];
     const TabView &V = tviews[k];
     const int c = (int)((int64_t)blockIdx.x - chain_base[k]);
     const int n = H.n;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
     const int chunks = V.chunks;
+    const int64_t row = (int64_t)c * n;
     const uint64_t wm = H.wmask[c];
+    const bool learned = H.proposal == 1;
+    const bool harvest = H.hv_feat != nullptr;
     if (wave == 0) {
         const bool in = lane < n && ((wm >> lane) & 1ull);
         const uint64_t bal = __ballot(in);
         if (in) s_nodes[__popcll(bal & ((1ull << lane) - 1ull))] = lane;
         if (lane == 0) s_cnt = __popcll(bal);
+        if (lane < n) {
+            s_posp[H.prop[row + lane]] = lane;
+            s_posc[H.cur[row + lane]] = lane;
+        }
     }
     __syncthreads();
     const int cnt = s_cnt;
@@ -200,22 +227,40 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(const TabView *
         if (lane == 0) {
             s_l[i] = (double)r[q].m + log((double)r[q].s);
             s_b[i] = (double)r[q].best;
+            s_s[i] = (double)r[q].sec;
             s_bm[i] = r[q].bm;
         }
     }
     __syncthreads();
+    if (learned) {
+        // features of the proposal order, then its node scores
+        if (tid < n) {
+            const int i = tid;
+            const bool in = (wm >> i) & 1ull;
+            const double best = in ? s_b[i] : H.node_m[row + i];
+            const double sec = in ? s_s[i] : H.node_sec[row + i];
+            float *f = s_feat + i * kF;
+            f[0] = (float)s_posp[i] / (float)n;
+            f[1] = (float)best;
+            f[2] = isinf(sec) ? 0.f : (float)(best - sec);
+#pragma unroll
+            for (int j = 0; j < 5; ++j) f[3 + j] = (float)H.nstat[i * 5 + j];
+        }
+        __syncthreads();
+        mlp_forward_block(H.mlp, s_feat, n, s_mlp, nullptr);
+    }
     if (wave != 0) return;
 
-    const int64_t row = (int64_t)c * n;
     const bool in = lane < n && ((wm >> lane) & 1ull);
     const double li = lane < n ? (in ? s_l[lane] : H.node_l[row + lane]) : 0.0;
     const double mi = lane < n ? (in ? s_b[lane] : H.node_m[row + lane]) : 0.0;
+    const double si = lane < n ? (in ? s_s[lane] : H.node_sec[row + lane]) : 0.0;
     const double L = wave_sum_f64(li, lane);
     const double M = wave_sum_f64(mi, lane);
     const uint64_t chain = (uint64_t)(H.chain0 + c);
     const int64_t t = H.t[c];
     const double nv = H.target ? M : L;
-    int acc = 0, imp = 0;
+    int acc = 0, imp = 0, slot = -1;
     if (lane == 0) {
         if (t == H.t_first) {            // adopt the initial (or re-scored saved) order
             acc = 1;
@@ -226,14 +271,22 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(const TabView *
                 if (H.trace) H.trace[(int64_t)c * H.trace_len] = nv;
             }
         } else {
+            double ratio = nv - H.score[c];
+            if (learned) ratio += pair_logq_dev(s_mlp.logit, n, H.pend[2 * c], H.pend[2 * c + 1], H.eps) - H.lq_fwd[c];
             const double u = rng_unit_open(rng_draw(H.seed, chain, 3, (uint64_t)t));
-            acc = log(u) < nv - H.score[c];
+            acc = log(u) < ratio;
             if (acc) {
                 H.score[c] = nv;
                 H.accepted[c] += 1;
                 if (M > H.best_score[c]) {
                     H.best_score[c] = M;
                     imp = 1;
+                }
+                if (harvest && H.hv_count[c] < H.hv_cap) {
+                    slot = (int)H.hv_count[c];
+                    H.hv_count[c] += 1;
+                    H.hv_pair[((int64_t)c * H.hv_cap + slot) * 2] = H.pend[2 * c];
+                    H.hv_pair[((int64_t)c * H.hv_cap + slot) * 2 + 1] = H.pend[2 * c + 1];
                 }
             }
             if (H.flags) H.flags[(int64_t)c * H.iterations + (t - H.t_first - 1)] = (uint8_t)acc;
@@ -243,6 +296,17 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(const TabView *
     }
     acc = __shfl(acc, 0, 64);
     imp = __shfl(imp, 0, 64);
+    slot = __shfl(slot, 0, 64);
+    if (slot >= 0 && lane < n) {
+        // raw features of the order before the move (current caches)
+        float *f = H.hv_feat + (((int64_t)c * H.hv_cap + slot) * n + lane) * kF;
+        const double best = H.node_m[row + lane], sec = H.node_sec[row + lane];
+        f[0] = (float)s_posc[lane] / (float)n;
+        f[1] = (float)best;
+        f[2] = isinf(sec) ? 0.f : (float)(best - sec);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) f[3 + j] = (float)H.nstat[lane * 5 + j];
+    }
     int32_t v = 0;
     if (lane < n) {
         v = acc ? H.prop[row + lane] : H.cur[row + lane];
@@ -250,14 +314,71 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(const TabView *
             H.cur[row + lane] = v;
             H.node_l[row + lane] = li;
             H.node_m[row + lane] = mi;
+            H.node_sec[row + lane] = si;
             if (in) H.node_best[row + lane] = s_bm[lane];
+            if (learned) H.cur_logit[row + lane] = s_mlp.logit[lane];
         }
     }
     if (imp && lane < n) H.best_graph[row + lane] = in ? s_bm[lane] : H.node_best[row + lane];
     const int64_t t1 = t + 1;
     const bool next = t1 <= H.t_last;
     int a = 0, b = 0;
-    if (next) rng_pair(H.seed, chain, n, (uint64_t)t1, a, b);
+    if (next) {
+        if (!learned) {
+            rng_pair(H.seed, chain, n, (uint64_t)t1, a, b);
+            const int na = __shfl(v, a, 64), nb = __shfl(v, b, 64);
+            if (harvest && lane == 0) {
+                H.pend[2 * c] = na;
+                H.pend[2 * c + 1] = nb;
+            }
+        } else {
+            // q: with probability eps a uniform pair of positions, else node a ~ p,
+            // then node b ~ p without a (inverse CDF in node order, FP64).
+            // The current order's scores: this step's if accepted, else unchanged.
+            const float *lg = acc ? s_mlp.logit : H.cur_logit + row;
+            const int *pos = acc ? s_posp : s_posc;
+            const double mix = rng_unit_open(rng_draw(H.seed, chain, 4, (uint64_t)t1));
+            int na = 0, nb = 0;
+            if (mix < H.eps) {
+                rng_pair(H.seed, chain, n, (uint64_t)t1, a, b);
+                na = __shfl(v, a, 64);
+                nb = __shfl(v, b, 64);
+            } else if (lane == 0) {
+                // p_i = exp(l_i - max) / sum, recomputed in each pass (no per-lane array)
+                double mx = -1e300;
+                for (int i = 0; i < n; ++i) mx = (double)lg[i] > mx ? (double)lg[i] : mx;
+                double sum = 0.0;
+                for (int i = 0; i < n; ++i) sum += exp((double)lg[i] - mx);
+                const double u = rng_unit_open(rng_draw(H.seed, chain, 5, (uint64_t)t1));
+                na = n - 1;
+                double cu = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    cu += exp((double)lg[i] - mx) / sum;
+                    if (u < cu) { na = i; break; }
+                }
+                const double pna = exp((double)lg[na] - mx) / sum;
+                const double w2 = rng_unit_open(rng_draw(H.seed, chain, 6, (uint64_t)t1)) * (1.0 - pna);
+                nb = (na == n - 1) ? n - 2 : n - 1;
+                cu = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    if (i == na) continue;
+                    cu += exp((double)lg[i] - mx) / sum;
+                    if (w2 < cu) { nb = i; break; }
+                }
+                a = pos[na];
+                b = pos[nb];
+            }
+            a = __shfl(a, 0, 64);
+            b = __shfl(b, 0, 64);
+            na = __shfl(na, 0, 64);
+            nb = __shfl(nb, 0, 64);
+            if (lane == 0) {
+                H.pend[2 * c] = na;
+                H.pend[2 * c + 1] = nb;
+                H.lq_fwd[c] = pair_logq_dev(lg, n, na, nb, H.eps);
+            }
+        }
+    }
     const int src = (lane == a) ? b : ((lane == b) ? a : lane);
     const int32_t w = __shfl(v, src, 64);
     const int lo = a < b ? a : b, hi = a < b ? b : a;
@@ -286,8 +407,13 @@ bnos_status validate_cfg(const bnos_chain_cfg *cfg)
     if (cfg->trace_every < 1) { set_error("trace_every must be >= 1"); return BNOS_E_RANGE; }
     if (cfg->sweep_len < 0) { set_error("sweep_len < 0"); return BNOS_E_RANGE; }
     if (cfg->chain_offset < 0) { set_error("chain_offset < 0"); return BNOS_E_RANGE; }
-    for (int r = 0; r < 6; ++r)
+    for (int r = 0; r < 4; ++r)
         if (cfg->reserved[r] != 0) { set_error("cfg.reserved must be zero"); return BNOS_E_INVALID; }
+    if (cfg->proposal != 0 && cfg->proposal != 1) { set_error("proposal must be 0 or 1"); return BNOS_E_INVALID; }
+    if (cfg->proposal == 1) {
+        if (!mlp_handle_live(cfg->mlp)) { set_error("learned proposal needs a live network handle"); return BNOS_E_STATE; }
+        if (!(cfg->eps >= 0.f && cfg->eps <= 1.f)) { set_error("eps outside [0, 1]"); return BNOS_E_RANGE; }
+    }
     return BNOS_OK;
 }
 
@@ -313,6 +439,11 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
             set_error("NULL state array");
             return BNOS_E_INVALID;
         }
+        if (st.harvest_feats && (!st.harvest_pairs || !st.harvest_count || st.harvest_cap < 1)) {
+            set_error("harvest needs feats, pairs, count and cap >= 1");
+            return BNOS_E_INVALID;
+        }
+        if (cfg->proposal == 1 && tabs[k]->n > 64) { set_error("n > 64"); return BNOS_E_RANGE; }
     }
     // scoring steps: the adoption of the starting order (fresh: iteration 0; resume: the
     // saved order, re-scored to rebuild the per-node caches) and one per iteration
@@ -331,7 +462,8 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
     for (int k = 0; k < T; ++k) {
         const size_t n = tabs[k]->n, cn = (size_t)C * n;
         off[k] = bytes;
-        bytes += cn * 24 + (size_t)C * 16 + cn * 4 + n * C * 4 + n * 4;
+        bytes += cn * 24 + (size_t)C * 16 + cn * 4 + n * C * 4 + n * 4 + 256;   // caches, windows, lists
+        bytes += cn * 8 + cn * 4 + (size_t)C * 8 + (size_t)C * 8 + 256;         // second best, logits, q, pair
         bytes = (bytes + 255) & ~(size_t)255;
     }
     char *ws = nullptr;
@@ -364,7 +496,17 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
         H.t = reinterpret_cast<int64_t *>(p);           p += (size_t)C * 8;
         H.prop = reinterpret_cast<int32_t *>(p);        p += cn * 4;
         H.wl_list = reinterpret_cast<int32_t *>(p);     p += (size_t)n * C * 4;
-        H.wl_count = reinterpret_cast<int32_t *>(p);
+        H.wl_count = reinterpret_cast<int32_t *>(p);    p += (size_t)n * 4;
+        p = ws + ((size_t)(p - ws + 255) & ~(size_t)255);
+        H.node_sec = reinterpret_cast<double *>(p);     p += cn * 8;
+        H.lq_fwd = reinterpret_cast<double *>(p);       p += (size_t)C * 8;
+        H.cur_logit = reinterpret_cast<float *>(p);     p += cn * 4;
+        H.pend = reinterpret_cast<int32_t *>(p);
+        H.nstat = t->d_nstat;
+        H.proposal = cfg->proposal;
+        H.eps = cfg->eps > 0.f ? (double)cfg->eps : 0.1;
+        if (cfg->proposal == 1) H.mlp = mlp_view(cfg->mlp);
+        else std::memset(&H.mlp, 0, sizeof(H.mlp));
         const bnos_chain_state &st = states[k];
         H.cur = st.orders;
         H.score = st.scores;
@@ -376,6 +518,10 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
         H.trace_len = cfg->iterations / cfg->trace_every + 1;
         H.flags = st.accept_flags;
         H.iterations = cfg->iterations;
+        H.hv_feat = st.harvest_feats;
+        H.hv_pair = st.harvest_pairs;
+        H.hv_count = st.harvest_count;
+        H.hv_cap = st.harvest_feats ? st.harvest_cap : 0;
         TabView &V = tv[k];
         V.masks = t->d_masks;
         V.scores = t->d_scores;
@@ -388,6 +534,8 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
         V.part = reinterpret_cast<Partial *>(t->d_part);
         V.wl_count = H.wl_count;
         V.wl_list = H.wl_list;
+        V.tand = t->tile_skip ? t->d_tand : nullptr;
+        V.tiles_loaded = nullptr;
         blk_base[k + 1] = blk_base[k] + (int64_t)n * t->chunks;
         chain_base[k + 1] = chain_base[k] + C;
         node_base[k + 1] = node_base[k] + n;

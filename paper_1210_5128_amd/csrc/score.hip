@@ -93,6 +93,8 @@ ScoreArgs score_args(const TableT *t, const int32_t *orders, int B, double *lse,
     A.node_second = node_second;
     A.wl_count = nullptr;
     A.wl_list = nullptr;
+    A.tand = t->tile_skip ? t->d_tand : nullptr;
+    A.tiles_loaded = t->timing ? t->d_tiles : nullptr;
     return A;
 }
 
@@ -197,11 +199,35 @@ extern "C" bnos_status bnos_table_timing(bnos_table h, int32_t enable)
 {
     TableT *t = reinterpret_cast<TableT *>(h);
     if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
+    BNOS_HIP(hipSetDevice(t->device));
+    BNOS_HIP(hipDeviceSynchronize());
     t->timing = enable != 0;
     t->ev_used = 0;
     t->timed_ms = 0.0;
     t->timed_launches = 0;
     t->timed_passes = 0;
+    BNOS_HIP(hipMemset(t->d_tiles, 0, sizeof(unsigned long long)));
+    return BNOS_OK;
+}
+
+extern "C" bnos_status bnos_table_tiles_read(bnos_table h, int64_t *tiles_loaded, int64_t *tiles_per_pass)
+{
+    TableT *t = reinterpret_cast<TableT *>(h);
+    if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
+    BNOS_HIP(hipSetDevice(t->device));
+    BNOS_HIP(hipDeviceSynchronize());
+    unsigned long long v = 0;
+    BNOS_HIP(hipMemcpy(&v, t->d_tiles, sizeof v, hipMemcpyDeviceToHost));
+    if (tiles_loaded) *tiles_loaded = (int64_t)v;
+    if (tiles_per_pass) *tiles_per_pass = (int64_t)t->n * (t->S_pad / 256);
+    return BNOS_OK;
+}
+
+extern "C" bnos_status bnos_table_tile_skip(bnos_table h, int32_t enable)
+{
+    TableT *t = reinterpret_cast<TableT *>(h);
+    if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
+    t->tile_skip = enable != 0;
     return BNOS_OK;
 }
 

@@ -159,6 +159,8 @@ struct ScoreArgs {
     // in wl_list[i * B ...]; a block's slot j takes the (group*BT + j)-th listed order.
     const int32_t *wl_count;   // [n] or null (then slot j of group g is order g*BT + j)
     const int32_t *wl_list;    // [n][B]
+    const uint64_t *tand;      // tile summaries, or null
+    unsigned long long *tiles_loaded;   // counter, or null
 };
 
 // What one streaming block needs to know about its table and its orders.
@@ -172,6 +174,8 @@ struct TabView {
     Partial *part;              // [B][n][chunks]
     const int32_t *wl_count;    // [n] or null
     const int32_t *wl_list;     // [n][B]
+    const uint64_t *tand;       // [n * S_pad / 256] AND of each 256-entry tile's masks, or null (no skipping)
+    unsigned long long *tiles_loaded;   // counter of tiles read, or null
 };
 
 // One block streams chunk `chunk` of node `node`'s entries once and folds each
@@ -218,30 +222,61 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     const u64x2 *mp = reinterpret_cast<const u64x2 *>(V.masks + row);
     const f32x4 *sp = reinterpret_cast<const f32x4 *>(V.scores + row);
     const int steps = V.chunk_entries / kEntriesPerStep;
+    // Tile skipping: at step `it` this wavefront covers one 256-entry tile; if
+    // the AND of the tile's masks holds a node outside an order's predecessor
+    // set, every entry of the tile does, and the order can skip the tile (a
+    // tile no order needs is not loaded at all).  Lane k holds the summary of
+    // this wavefront's tile at step k (steps <= 16).
+    uint64_t tsum = 0;
+    if (V.tand && lane < steps) tsum = V.tand[(row >> 8) + (int64_t)lane * 4 + wave];
+    auto need = [&](int it) -> uint32_t {      // bit j: slot j may find a consistent entry
+        if (!V.tand) return (1u << BT) - 1u;
+        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)tsum, it);
+        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(tsum >> 32), it);
+        const uint64_t sm = ((uint64_t)hi << 32) | lo;
+        uint32_t m = 0;
+#pragma unroll
+        for (int j = 0; j < BT; ++j) m |= ((sm & npred[j]) == 0ull) ? (1u << j) : 0u;
+        return m;
+    };
     // Software pipeline: the loads of step it+1 are in flight while step it is folded.
     int q = threadIdx.x;                                     // this lane's 4-entry group
-    u64x2 n01 = __builtin_nontemporal_load(&mp[2 * q]);
-    u64x2 n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
-    f32x4 nsc = __builtin_nontemporal_load(&sp[q]);
+    uint32_t need_n = need(0);
+    u64x2 n01 = {0ull, 0ull}, n23 = {0ull, 0ull};
+    f32x4 nsc = {0.f, 0.f, 0.f, 0.f};
+    unsigned loaded = 0;
+    if (need_n) {
+        n01 = __builtin_nontemporal_load(&mp[2 * q]);
+        n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
+        nsc = __builtin_nontemporal_load(&sp[q]);
+    }
     for (int it = 0; it < steps; ++it) {
         const u64x2 m01 = n01, m23 = n23;
         const f32x4 sc = nsc;
+        const uint32_t need_c = need_n;
         if (it + 1 < steps) {
             q += kScoreThreads;
-            n01 = __builtin_nontemporal_load(&mp[2 * q]);
-            n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
-            nsc = __builtin_nontemporal_load(&sp[q]);
+            need_n = need(it + 1);
+            if (need_n) {
+                n01 = __builtin_nontemporal_load(&mp[2 * q]);
+                n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
+                nsc = __builtin_nontemporal_load(&sp[q]);
+            }
         }
+        if (need_c == 0u) continue;                          // uniform across the wavefront
+        ++loaded;
         const uint64_t mk[4] = {m01.x, m01.y, m23.x, m23.y};
         const float x[4] = {sc.x, sc.y, sc.z, sc.w};
 #pragma unroll
         for (int j = 0; j < BT; ++j) {
+            if (!((need_c >> j) & 1u)) continue;             // uniform
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if ((mk[k] & npred[j]) == 0ull) acc_push(a[j], x[k], mk[k]);
             }
         }
     }
+    if (V.tiles_loaded && lane == 0) atomicAdd(V.tiles_loaded, (unsigned long long)loaded);
 
 #pragma unroll
     for (int j = 0; j < BT; ++j) {
@@ -294,6 +329,8 @@ __device__ __forceinline__ TabView view_of(const ScoreArgs &A)
     V.part = A.part;
     V.wl_count = A.wl_count;
     V.wl_list = A.wl_list;
+    V.tand = A.tand;
+    V.tiles_loaded = A.tiles_loaded;
     return V;
 }
 

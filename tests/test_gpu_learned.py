@@ -1,0 +1,119 @@
+"""Learned swap proposal on the device: static features vs the oracle, exact
+stationarity of the q-corrected chains, and the harvest of accepted moves."""
+import itertools
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_1210_5128_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bnos():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1210_5128_amd import bnos as b
+    return b
+
+
+@pytest.fixture(scope="module")
+def prior20(bnos):
+    w = datagen.WORKLOADS["prior20"]
+    net, prior = datagen.make(w)
+    t = bnos.build_score_table(net.data, net.arities, w.K, prior=prior)
+    orc = oracle.build_table(net.data, net.arities, w.K, prior=prior)
+    yield w, net, prior, t, orc
+    t.free()
+
+
+def test_static_node_features_match_oracle(bnos, prior20):
+    w, net, prior, t, orc = prior20
+    got = t.node_features()
+    pn = oracle.prior_nats(prior, w.n)
+    np.testing.assert_allclose(got[:, 0], pn.sum(axis=1), rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(got[:, 1], pn.sum(axis=0), rtol=1e-12, atol=1e-9)
+    st = oracle.table_stats(orc, w.K, round_f32=True)
+    np.testing.assert_allclose(got[:, 2:], st, rtol=1e-9)
+
+
+def test_learned_chains_sample_the_exact_posterior(bnos):
+    # the asymmetric network of the oracle's stationarity test: without the
+    # reverse-q factor the visiting frequencies would miss by TV 0.1-0.2
+    n, K = 4, 3
+    arities = [2, 2, 3, 2]
+    rng = np.random.default_rng(12)
+    data = np.stack([rng.integers(0, a, size=8) for a in arities], axis=1).astype(np.int8)
+    t = bnos.build_score_table(data, arities, K)
+    orc = oracle.build_table(data, arities, K)
+    orders = list(itertools.permutations(range(n)))
+    sc = np.array([oracle.score_order(orc, K, o)[0] for o in orders])
+    post = np.exp(sc - sc.max())
+    post /= post.sum()
+    prm = datagen.mlp_params(7, scale=1.0)
+    prm[1:8 * 128:8] *= 6.0
+    mu = np.zeros(8, np.float32)
+    mu[1] = np.float32(np.mean(sc) / n)
+    sd = np.array([0.3, 1.0, 1.0, 1.0, 1.0, 30.0, 30.0, 5.0], np.float32)
+    m = bnos.Mlp()
+    m.set_params(prm.astype(np.float32), mu, sd)
+    C = 32768
+    st = t.new_chain_state(C, 300, trace_every=300)
+    t.run_chains(st, 300, seed=55, mlp=m, eps=0.1, trace_every=300)
+    fin = st["orders"].cpu().numpy()
+    idx = {o: k for k, o in enumerate(orders)}
+    freq = np.zeros(24)
+    for row in fin:
+        freq[idx[tuple(int(v) for v in row)]] += 1
+    freq /= C
+    tv = 0.5 * np.abs(freq - post).sum()
+    assert tv < 0.03, tv
+    acc = st["accepted"].cpu().numpy().sum() / (C * 300)
+    assert 0.05 < acc < 0.99
+    m.free()
+    t.free()
+
+
+def test_harvest_records_the_order_before_each_accepted_move(bnos, prior20):
+    w, net, prior, t, orc = prior20
+    C, iters, cap = 4, 300, 64
+    st = t.new_chain_state(C, iters, trace_every=1, flags=True, harvest_cap=cap)
+    t.run_chains(st, iters, seed=71)
+    feats = st["harvest_feats"].cpu().numpy()
+    pairs = st["harvest_pairs"].cpu().numpy()
+    cnt = st["harvest_count"].cpu().numpy()
+    acc = st["accepted"].cpu().numpy()
+    static = t.node_features()
+    assert np.all(cnt == np.minimum(acc, cap)) and cnt.min() > 3
+    for c in range(C):
+        orders = []
+        for k in range(int(cnt[c])):
+            f = feats[c, k]
+            order = np.argsort(f[:, 0]).astype(np.int32)         # position / n gives the order
+            assert np.allclose(np.sort(f[:, 0]), np.arange(w.n) / w.n)
+            l, mx, best, nl, nb, ns = oracle.score_order(orc, w.K, order)
+            np.testing.assert_allclose(f[:, 1], nb, rtol=1e-6)
+            gap = np.where(np.isinf(ns), 0.0, nb - ns)
+            np.testing.assert_allclose(f[:, 2], gap, rtol=1e-4, atol=1e-2)
+            np.testing.assert_allclose(f[:, 3:], static, rtol=1e-6, atol=1e-5)
+            orders.append(order)
+        for k in range(len(orders) - 1):
+            a, b = (int(x) for x in pairs[c, k])
+            nxt = orders[k].copy()
+            pa, pb = int(np.nonzero(nxt == a)[0][0]), int(np.nonzero(nxt == b)[0][0])
+            nxt[pa], nxt[pb] = nxt[pb], nxt[pa]
+            assert np.array_equal(nxt, orders[k + 1]), (c, k)
+
+
+def test_uniform_chains_unchanged_by_harvest(bnos, prior20):
+    w, net, prior, t, orc = prior20
+    a = t.new_chain_state(3, 200, trace_every=1, flags=True)
+    t.run_chains(a, 200, seed=3)
+    b = t.new_chain_state(3, 200, trace_every=1, flags=True, harvest_cap=16)
+    t.run_chains(b, 200, seed=3)
+    for k in ("orders", "scores", "best_graphs", "best_scores", "accepted", "trace", "accept_flags"):
+        assert torch.equal(a[k], b[k]), k

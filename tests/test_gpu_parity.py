@@ -305,3 +305,32 @@ def test_mixed60_orders_against_direct_oracle(bnos, mixed60):
         assert abs(got["node_lse"][b, node] - l) <= REL * max(1.0, abs(l))
         assert int(got["best"][b, node]) == bm
         assert float(got["node_second"][b, node]) == sec
+
+
+@pytest.mark.parametrize("B", [1, 3, 8, 20])
+def test_tile_skipping_is_bitwise_identical(bnos, mixed60, B):
+    w, net, prior, t = mixed60
+    orders = datagen.random_orders(w.n, B, seed=90 + B)
+    t.tile_skip(False)
+    full = dev_score(t, orders)
+    t.tile_skip(True)
+    t.timing(True)
+    skip = dev_score(t, orders)
+    loaded, per_pass = t.tiles_read()
+    t.timing(False)
+    for k in full:
+        assert np.array_equal(full[k].view(np.uint8), skip[k].view(np.uint8)), k
+    passes = -(-B // (8 if B >= 8 else (4 if B >= 4 else (2 if B >= 2 else 1))))
+    assert 0 < loaded < passes * per_pass
+
+
+def test_tile_skipping_small_tables(bnos, prior20):
+    w, net, prior, t, orc = prior20
+    orders = datagen.random_orders(w.n, 9, seed=3)
+    t.tile_skip(False)
+    full = dev_score(t, orders)
+    t.tile_skip(True)
+    skip = dev_score(t, orders)
+    for k in full:
+        assert np.array_equal(full[k].view(np.uint8), skip[k].view(np.uint8)), k
+    assert check_orders_against_oracle(skip, orc, w.K, orders) == 0
