@@ -313,8 +313,15 @@ def main():
         torch.cuda.synchronize()
         total_ms = ev0.elapsed_time(ev1)
         k_ms, k_launches, k_passes = table.timing_read()
-        tiles, tiles_per_pass = table.tiles_read()
         table.timing(False)
+        tiles, tiles_per_pass = 0, 1
+        if skip:          # tiles the launches read: counted by a separate kernel over the same orders
+            for s in range(steps):
+                tl, tiles_per_pass = table.count_tiles(orders[s % pool])
+                tiles += tl
+                if s + 1 == pool:
+                    tiles = tiles * steps // pool
+                    break
         kernel_avg_ms = k_ms / k_launches
         passes_per_launch = k_passes / k_launches
         # bytes the launch had to read: with tile skipping, the tiles it loaded
@@ -330,6 +337,14 @@ def main():
                     full_scan_equiv_gbs=bytes_per_pass * passes_per_launch / (kernel_avg_ms / 1e3) / 1e9)
 
     stream = torch.cuda.current_stream()
+    # launch shape (chunk length, orders per block) tuned per batch size before timing
+    tuned = {}
+    for Bq in sorted({B, args.batched_check} - {0}):
+        o = torch.from_numpy(datagen.random_orders(n, Bq, seed=900 + Bq)).to(dev)
+        cs, bt, ms = table.autotune(o, reps=20 if Bq < 64 else 3, stream=stream)
+        tuned[str(Bq)] = {"chunk_steps": cs, "orders_per_block": bt, "tune_ms_per_launch": ms}
+        print(f"# autotune B={Bq}: chunk {cs}x1024 entries, {bt} orders/block, {ms * 1e3:.1f} us",
+              file=sys.stderr, flush=True)
     rf = timed(B, args.steps, args.warmup, skip=False)         # full scan of every entry
     print(f"# full scan: {rf['total_ms']:.3f} ms for {args.steps} steps", file=sys.stderr, flush=True)
     r = timed(B, args.steps, args.warmup, skip=True)           # with tile summaries (default path)
@@ -364,7 +379,7 @@ def main():
         "config": {
             "workload": (f"score_orders on the {w.name} table: n={n}, K={K}, N={w.N}, arities U{{2,3,4}}, "
                          f"BDeu ess={w.ess}, pairwise prior on 10% of ordered pairs; {B} random order(s) per step"),
-            "n": n, "K": K, "N": w.N, "batch": B, "entries_per_node": S,
+            "n": n, "K": K, "N": w.N, "batch": B, "entries_per_node": S, "launch_shape": tuned,
             "parallelism": "single GPU",
         },
         "roofline": {

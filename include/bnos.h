@@ -60,7 +60,10 @@ typedef struct {
     int32_t prior_mode;    /* 0: prior entries are weights w in [-1,1], R = (1 + w)/2;
                               1: prior entries are the paper's R in [0,1] (Sec. IV).
                               Either way the added term is ln(10) * 100 * (R - 0.5)^3. */
-    int32_t reserved[7];   /* must be zero */
+    int32_t chunk_steps;   /* scoring blocks stream chunks of chunk_steps * 1024 entries of one node's
+                              row; a power of two <= 16 that divides the row padding (see
+                              bnos_table_info); 0 = automatic */
+    int32_t reserved[6];   /* must be zero */
 } bnos_build_opts;         /* all-zero = defaults */
 
 /*
@@ -99,6 +102,20 @@ void bnos_table_free(bnos_table t);
  */
 bnos_status bnos_table_info(bnos_table t, int32_t *n, int32_t *K, int64_t *entries_per_node,
                             int64_t *device_bytes);
+
+/*
+ * Autotuner: times scoring launches of the B orders (DEVICE int32 [B][n]) for
+ * every chunk length (powers of two dividing the row padding) and every
+ * number of orders per block (1, 2, 4, 8, at most B), `reps` launches each
+ * after one warm-up, and keeps the fastest pair for this table and batch size
+ * (batch sizes are bucketed as 1, 2-3, 4-7, 8-15, 16+).  Outputs (may be
+ * NULL): the chosen chunk steps and orders per block, and its mean time per
+ * launch in ms.  The chunk length changes the order in which partial sums
+ * are combined, so log-sum-exp values move in the last bits; argmax parent
+ * sets are unaffected.  Synchronous on `stream`.
+ */
+bnos_status bnos_table_autotune(bnos_table t, const int32_t *orders, int32_t B, int32_t reps, void *stream,
+                                int32_t *chunk_steps, int32_t *orders_per_block, double *ms_per_launch);
 
 /*
  * Copy node `node`'s entries to host arrays masks[S], scores[S] (S from
@@ -303,11 +320,13 @@ bnos_status bnos_table_timing(bnos_table t, int32_t enable);
  * the AND of its masks; a tile whose AND contains a node outside an order's
  * predecessor set holds no consistent entry for that order, and a tile no
  * order of a block needs is not read.  Results are identical with it off.
- * bnos_table_tiles_read returns the tiles read by scoring launches while
- * timing was on, and the tiles of one full pass (n * padded entries / 256).
+ * bnos_table_count_tiles (measurement) returns how many tiles a scoring
+ * launch of these B orders (DEVICE int32 [B][n]) reads with tile skipping,
+ * and the tiles of one full pass (n * padded entries / 256).  Synchronous.
  */
 bnos_status bnos_table_tile_skip(bnos_table t, int32_t enable);
-bnos_status bnos_table_tiles_read(bnos_table t, int64_t *tiles_loaded, int64_t *tiles_per_pass);
+bnos_status bnos_table_count_tiles(bnos_table t, const int32_t *orders, int32_t B, int64_t *tiles_read,
+                                   int64_t *tiles_per_pass);
 bnos_status bnos_table_timing_read(bnos_table t, double *total_ms, int64_t *launches,
                                    int64_t *table_passes);
 

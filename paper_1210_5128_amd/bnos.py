@@ -30,8 +30,8 @@ i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 
 
 class BuildOpts(ctypes.Structure):
-    _fields_ = [("log_gamma", ctypes.c_double), ("prior_mode", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("log_gamma", ctypes.c_double), ("prior_mode", ctypes.c_int32), ("chunk_steps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class ChainCfg(ctypes.Structure):
@@ -70,7 +70,8 @@ _SIGS = {
     "bnos_mlp_train": (i32, [P, P, P, i64, i32, ctypes.c_float, i32, i32, ctypes.c_float, ctypes.c_uint64, P, P]),
     "bnos_table_timing": (i32, [P, i32]),
     "bnos_table_tile_skip": (i32, [P, i32]),
-    "bnos_table_tiles_read": (i32, [P, P, P]),
+    "bnos_table_count_tiles": (i32, [P, P, i32, P, P]),
+    "bnos_table_autotune": (i32, [P, P, i32, i32, P, P, P, P]),
     "bnos_table_timing_read": (i32, [P, P, P, P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -219,13 +220,21 @@ class Table:
         st = _chain_state(state, iterations, trace_every)
         _check(_lib.bnos_run_chains(self._h, ctypes.byref(cfg), ctypes.byref(st), _stream(stream)))
 
+    def autotune(self, orders, reps: int = 5, stream=None):
+        """Pick chunk length and orders per block for this batch size (bnos_table_autotune)."""
+        cs, bt, ms = i32(), i32(), f64()
+        _check(_lib.bnos_table_autotune(self._h, _dptr(orders), int(orders.shape[0]), reps, _stream(stream),
+                                        ctypes.byref(cs), ctypes.byref(bt), ctypes.byref(ms)))
+        return cs.value, bt.value, ms.value
+
     def tile_skip(self, enable: bool):
         _check(_lib.bnos_table_tile_skip(self._h, int(enable)))
 
-    def tiles_read(self):
-        """-> (tiles read by timed scoring launches, tiles of one full pass)."""
+    def count_tiles(self, orders):
+        """-> (tiles a scoring launch of these device orders reads with skipping, tiles per full pass)."""
         a, b = i64(), i64()
-        _check(_lib.bnos_table_tiles_read(self._h, ctypes.byref(a), ctypes.byref(b)))
+        _check(_lib.bnos_table_count_tiles(self._h, _dptr(orders), int(orders.shape[0]), ctypes.byref(a),
+                                           ctypes.byref(b)))
         return a.value, b.value
 
     # -- timing
@@ -349,7 +358,7 @@ def run_chains_multi(tables, states, iterations: int, seed: int, target: int = 0
 
 
 def build_score_table(data, arities, K: int, ess: float = 1.0, prior=None, prior_mode: int = 0,
-                      log_gamma: float = 0.0, stream=None) -> Table:
+                      log_gamma: float = 0.0, chunk_steps: int = 0, stream=None) -> Table:
     """Build the local-score table (host inputs; see bnos_build_score_table)."""
     data = np.ascontiguousarray(data, dtype=np.int8)
     if data.ndim != 2:
@@ -360,6 +369,7 @@ def build_score_table(data, arities, K: int, ess: float = 1.0, prior=None, prior
     opts = BuildOpts()
     opts.log_gamma = log_gamma
     opts.prior_mode = prior_mode
+    opts.chunk_steps = chunk_steps
     h = ctypes.c_void_p()
     st = ctypes.c_void_p(0) if stream is None else _stream(stream)
     _check(_lib.bnos_build_score_table(_ptr(data) if N else None, N, n, _ptr(ar), K, ess,

@@ -36,6 +36,7 @@ struct TableT {
     int64_t S = 0, S_pad = 0;       // entries per node before / after padding
     int chunk_entries = 0;          // entries per scoring block
     int chunks = 0;                 // scoring blocks per node = S_pad / chunk_entries
+    int pad_steps = 1;              // rows are padded to a multiple of pad_steps * 1024 entries
     int max_cells = 0;
     double ess = 1.0, log_gamma = 0.0;
     int device = 0;
@@ -48,12 +49,11 @@ struct TableT {
     float *d_scores = nullptr;      // [n][S_pad]
     double *d_nstat = nullptr;      // [n][5]: prior row sum, prior column sum, max, mean, sd of the row
     uint64_t *d_tand = nullptr;     // [n * S_pad / 256]: AND of the masks of each 256-entry tile
-    unsigned long long *d_tiles = nullptr;   // tiles read by timed scoring launches
     bool tile_skip = true;
 
     // order-scoring workspace: per (order, node, chunk) partial reductions
     void *d_part = nullptr;
-    int64_t part_orders = 0;        // capacity in orders
+    int64_t part_bytes = 0;         // capacity in bytes
 
     // kernel timing
     bool timing = false;
@@ -64,13 +64,22 @@ struct TableT {
     std::vector<int64_t> ev_passes;     // table passes of each recorded launch
     int64_t timed_passes = 0;
 
-    // orders per scoring block picked by the autotuner per batch bucket (0 = default rule)
-    int tuned_bt[5] = {0, 0, 0, 0, 0};
+    // autotuned per batch-size bucket (1, 2-3, 4-7, 8-15, 16+); 0 = default
+    int tuned_bt[5] = {0, 0, 0, 0, 0};   // orders per scoring block
+    int tuned_cs[5] = {0, 0, 0, 0, 0};   // chunk length in 1024-entry steps
 
     int64_t device_bytes() const;
-    int64_t workspace_bytes_per_order() const
+    static int bucket(int B) { return B >= 16 ? 4 : (B >= 8 ? 3 : (B >= 4 ? 2 : (B >= 2 ? 1 : 0))); }
+    // chunk length (entries) and chunks per node used for a launch of B orders
+    int chunk_entries_for(int B) const
     {
-        return (int64_t)n * chunks * (int64_t)sizeof(Partial);
+        const int cs = tuned_cs[bucket(B)];
+        return cs > 0 ? cs * 1024 : chunk_entries;
+    }
+    int chunks_for(int B) const { return (int)(S_pad / chunk_entries_for(B)); }
+    int64_t workspace_bytes_for(int B) const
+    {
+        return (int64_t)B * n * chunks_for(B) * (int64_t)sizeof(Partial);
     }
 };
 

@@ -46,7 +46,7 @@ int64_t TableT::device_bytes() const
 {
     return (int64_t)n * S_pad * (int64_t)(sizeof(uint64_t) + sizeof(float)) + (int64_t)n * N_pad +
            (int64_t)n * (int64_t)(sizeof(int32_t) + n * sizeof(double) + 5 * sizeof(double)) + 64 * 8 * 8 +
-           part_orders * workspace_bytes_per_order() + (int64_t)n * (S_pad / 256) * 8;
+           part_bytes + (int64_t)n * (S_pad / 256) * 8;
 }
 
 // ------------------------------------------------------------------ device helpers
@@ -396,7 +396,6 @@ static void free_device(TableT *t)
     hipFree(t->d_scores);
     hipFree(t->d_nstat);
     hipFree(t->d_tand);
-    hipFree(t->d_tiles);
     hipFree(t->d_part);
     for (auto e : t->ev_start) hipEventDestroy(e);
     for (auto e : t->ev_stop) hipEventDestroy(e);
@@ -425,7 +424,7 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     bnos_build_opts o;
     std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
-    for (int r = 0; r < 7; ++r)
+    for (int r = 0; r < 6; ++r)
         if (o.reserved[r] != 0) { set_error("opts.reserved must be zero"); return BNOS_E_INVALID; }
     if (o.prior_mode != 0 && o.prior_mode != 1) { set_error("prior_mode must be 0 or 1"); return BNOS_E_INVALID; }
     if (!std::isfinite(o.log_gamma)) { set_error("log_gamma must be finite"); return BNOS_E_INVALID; }
@@ -472,33 +471,47 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     if (t->N_pad == 0) t->N_pad = 256;
     t->S = sets_upto(n - 1, K);
     {
-        // Chunk length (in 1024-entry steps) for the scoring grid: the one that
-        // best fills whole rounds of resident blocks (8 blocks of 256 threads
-        // per compute unit) for a single-order pass; ties go to longer chunks.
-        int cus = 256;
-        int dev = 0;
-        if (hipGetDevice(&dev) == hipSuccess) {
-            int v = 0;
-            if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-                cus = v;
-        }
-        const int64_t slots = (int64_t)cus * 8;
+        // Rows are padded to a multiple of P * 1024 entries, P the smallest power
+        // of two >= the row's 1024-entry steps, at most 16; chunk lengths are the
+        // powers of two dividing P.
         const int64_t node_steps = (t->S + kEntriesPerStep - 1) / kEntriesPerStep;
-        int best_st = 1;
-        double best_eff = -1.0;
-        for (int st = 1; st <= kMaxStepsPerChunk && st <= node_steps; ++st) {
-            int64_t chunks = (node_steps + st - 1) / st;
-            int64_t blocks = (int64_t)n * chunks;
-            int64_t rounds = (blocks + slots - 1) / slots;
-            double eff = (double)(n * node_steps) / (double)(rounds * slots * st);
-            if (eff >= best_eff - 1e-12) {
-                best_eff = eff;
-                best_st = st;
+        int P = 1;
+        while (P < kMaxStepsPerChunk && P < node_steps) P <<= 1;
+        t->pad_steps = P;
+        t->S_pad = ((node_steps + P - 1) / P) * P * kEntriesPerStep;
+        int st = o.chunk_steps;
+        if (st != 0) {
+            if (st < 1 || st > P || (P % st) != 0 || (st & (st - 1)) != 0) {
+                set_error("chunk_steps must be a power of two dividing the row padding (<= 16)");
+                delete t;
+                return BNOS_E_RANGE;
+            }
+        } else {
+            // automatic: the length that best fills whole rounds of resident blocks
+            // (8 blocks of 256 threads per compute unit) for a single-order pass
+            int cus = 256;
+            int dev = 0;
+            if (hipGetDevice(&dev) == hipSuccess) {
+                int v = 0;
+                if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+                    cus = v;
+            }
+            const int64_t slots = (int64_t)cus * 8;
+            const int64_t steps_pad = t->S_pad / kEntriesPerStep;
+            double best_eff = -1.0;
+            st = 1;
+            for (int c = 1; c <= P; c <<= 1) {
+                const int64_t blocks = (int64_t)n * (steps_pad / c);
+                const int64_t rounds = (blocks + slots - 1) / slots;
+                const double eff = (double)(n * node_steps) / (double)(rounds * slots * c);
+                if (eff >= best_eff - 1e-12) {
+                    best_eff = eff;
+                    st = c;
+                }
             }
         }
-        t->chunk_entries = best_st * kEntriesPerStep;
-        t->chunks = (int)((node_steps + best_st - 1) / best_st);
-        t->S_pad = (int64_t)t->chunks * t->chunk_entries;
+        t->chunk_entries = st * kEntriesPerStep;
+        t->chunks = (int)(t->S_pad / t->chunk_entries);
     }
     t->max_cells = max_cells;
     t->ess = ess;
@@ -525,7 +538,6 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     ALLOC(t->d_scores, sizeof(float) * (size_t)n * t->S_pad);
     ALLOC(t->d_nstat, sizeof(double) * (size_t)n * 5);
     ALLOC(t->d_tand, sizeof(uint64_t) * (size_t)n * (t->S_pad / 256));
-    ALLOC(t->d_tiles, sizeof(unsigned long long));
 #undef ALLOC
     int8_t *d_rows = nullptr;
     float *d_prior_in = nullptr;
@@ -565,7 +577,6 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
         hipLaunchKernelGGL(k_tile_and, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, t->d_masks, tiles,
                            t->d_tand);
         CK(hipGetLastError());
-        CK(hipMemsetAsync(t->d_tiles, 0, sizeof(unsigned long long), st));
     }
     CK(hipStreamSynchronize(st));
     hipFree(d_rows);

@@ -223,7 +223,13 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(const TabView *
         const int i = s_nodes[w];
         const Partial *pp = V.part + ((int64_t)c * n + i) * chunks;
         for (int cc = lane + 64; cc < chunks; cc += 64) acc_merge(r[q], load_partial(pp + cc));
-        acc_wave_reduce(r[q], lane);
+    }
+    acc_wave_reduce_n<kMergeNodesPerWave>(r, lane);
+#pragma unroll
+    for (int q = 0; q < kMergeNodesPerWave; ++q) {
+        const int w = wave + kMergeWaves * q;
+        if (w >= cnt) break;
+        const int i = s_nodes[w];
         if (lane == 0) {
             s_l[i] = (double)r[q].m + log((double)r[q].s);
             s_b[i] = (double)r[q].best;
@@ -526,8 +532,8 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
         V.masks = t->d_masks;
         V.scores = t->d_scores;
         V.S_pad = t->S_pad;
-        V.chunks = t->chunks;
-        V.chunk_entries = t->chunk_entries;
+        V.chunks = t->chunks_for(C);
+        V.chunk_entries = t->chunk_entries_for(C);
         V.n = n;
         V.B = C;
         V.orders = H.prop;
@@ -535,8 +541,7 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
         V.wl_count = H.wl_count;
         V.wl_list = H.wl_list;
         V.tand = t->tile_skip ? t->d_tand : nullptr;
-        V.tiles_loaded = nullptr;
-        blk_base[k + 1] = blk_base[k] + (int64_t)n * t->chunks;
+        blk_base[k + 1] = blk_base[k] + (int64_t)n * V.chunks;
         chain_base[k + 1] = chain_base[k] + C;
         node_base[k + 1] = node_base[k] + n;
     }

@@ -33,31 +33,30 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_merge(ScoreArgs A)
 int pick_bt(const TableT *t, int B)
 {
     int bt = B >= 8 ? 8 : (B >= 4 ? 4 : (B >= 2 ? 2 : 1));
-    if (t->tuned_bt[0] > 0) {
-        // autotuned choice for the batch-size bucket (1, 2-3, 4-7, 8-15, 16+)
-        int k = B >= 16 ? 4 : (B >= 8 ? 3 : (B >= 4 ? 2 : (B >= 2 ? 1 : 0)));
-        if (t->tuned_bt[k] > 0 && t->tuned_bt[k] <= B) bt = t->tuned_bt[k];
-    }
+    // autotuned choice for the batch-size bucket, if any
+    const int k = TableT::bucket(B);
+    if (t->tuned_bt[k] > 0 && t->tuned_bt[k] <= B) bt = t->tuned_bt[k];
     return bt;
 }
 
 // Scoring workspace for up to `B` orders: the chunk partials.
 bnos_status ensure_workspace(TableT *t, int B)
 {
-    if (t->part_orders >= B) return BNOS_OK;
+    const int64_t need = t->workspace_bytes_for(B);
+    if (t->part_bytes >= need) return BNOS_OK;
     // A launch still in flight may use the old buffer.
     BNOS_HIP(hipDeviceSynchronize());
     BNOS_HIP(hipFree(t->d_part));
     t->d_part = nullptr;
-    t->part_orders = 0;
-    int64_t want = B < 64 ? 64 : B;
-    hipError_t e = hipMalloc(&t->d_part, (size_t)want * t->workspace_bytes_per_order());
+    t->part_bytes = 0;
+    const int64_t want = need > t->workspace_bytes_for(64) ? need : t->workspace_bytes_for(64);
+    hipError_t e = hipMalloc(&t->d_part, (size_t)want);
     if (e != hipSuccess) {
         set_error(std::string("hipMalloc scoring workspace: ") + hipGetErrorString(e));
         t->d_part = nullptr;
         return e == hipErrorOutOfMemory ? BNOS_E_NOMEM : BNOS_E_DEVICE;
     }
-    t->part_orders = want;
+    t->part_bytes = want;
     return BNOS_OK;
 }
 
@@ -80,8 +79,8 @@ ScoreArgs score_args(const TableT *t, const int32_t *orders, int B, double *lse,
     A.masks = t->d_masks;
     A.scores = t->d_scores;
     A.S_pad = t->S_pad;
-    A.chunks = t->chunks;
-    A.chunk_entries = t->chunk_entries;
+    A.chunks = t->chunks_for(B);
+    A.chunk_entries = t->chunk_entries_for(B);
     A.orders = orders;
     A.B = B;
     A.n = t->n;
@@ -94,7 +93,6 @@ ScoreArgs score_args(const TableT *t, const int32_t *orders, int B, double *lse,
     A.wl_count = nullptr;
     A.wl_list = nullptr;
     A.tand = t->tile_skip ? t->d_tand : nullptr;
-    A.tiles_loaded = t->timing ? t->d_tiles : nullptr;
     return A;
 }
 
@@ -114,7 +112,7 @@ bnos_status launch_stream(TableT *t, const ScoreArgs &A, hipStream_t st, int bt)
     if (t->timing) {
         if ((s = record_event(t, true, st)) != BNOS_OK) return s;
     }
-    const int nbx = t->n * t->chunks;
+    const int nbx = t->n * A.chunks;
     if (bt == 8) launch_bt<8>(A, nbx, st);
     else if (bt == 4) launch_bt<4>(A, nbx, st);
     else if (bt == 2) launch_bt<2>(A, nbx, st);
@@ -199,26 +197,48 @@ extern "C" bnos_status bnos_table_timing(bnos_table h, int32_t enable)
 {
     TableT *t = reinterpret_cast<TableT *>(h);
     if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
-    BNOS_HIP(hipSetDevice(t->device));
-    BNOS_HIP(hipDeviceSynchronize());
     t->timing = enable != 0;
     t->ev_used = 0;
     t->timed_ms = 0.0;
     t->timed_launches = 0;
     t->timed_passes = 0;
-    BNOS_HIP(hipMemset(t->d_tiles, 0, sizeof(unsigned long long)));
     return BNOS_OK;
 }
 
-extern "C" bnos_status bnos_table_tiles_read(bnos_table h, int64_t *tiles_loaded, int64_t *tiles_per_pass)
+template <int BT>
+static void launch_count(const ScoreArgs &A, int nbx, unsigned *counts)
+{
+    dim3 grid((unsigned)nbx, (unsigned)((A.B + BT - 1) / BT));
+    hipLaunchKernelGGL(k_count_tiles<BT>, grid, dim3(kScoreThreads), 0, 0, A, counts);
+}
+
+extern "C" bnos_status bnos_table_count_tiles(bnos_table h, const int32_t *orders, int32_t B, int64_t *tiles_read,
+                                              int64_t *tiles_per_pass)
 {
     TableT *t = reinterpret_cast<TableT *>(h);
     if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
+    if (!orders) { set_error("NULL argument"); return BNOS_E_INVALID; }
+    if (B < 1 || B > (1 << 20)) { set_error("B outside [1, 2^20]"); return BNOS_E_RANGE; }
     BNOS_HIP(hipSetDevice(t->device));
-    BNOS_HIP(hipDeviceSynchronize());
-    unsigned long long v = 0;
-    BNOS_HIP(hipMemcpy(&v, t->d_tiles, sizeof v, hipMemcpyDeviceToHost));
-    if (tiles_loaded) *tiles_loaded = (int64_t)v;
+    ScoreArgs A = score_args(t, orders, B, nullptr, nullptr, nullptr, nullptr, nullptr);
+    A.tand = t->d_tand;
+    const int bt = pick_bt(t, B);
+    const int nbx = t->n * A.chunks;
+    const int64_t blocks = (int64_t)nbx * ((B + bt - 1) / bt);
+    unsigned *d = nullptr;
+    BNOS_HIP(hipMalloc((void **)&d, sizeof(unsigned) * blocks));
+    if (bt == 8) launch_count<8>(A, nbx, d);
+    else if (bt == 4) launch_count<4>(A, nbx, d);
+    else if (bt == 2) launch_count<2>(A, nbx, d);
+    else launch_count<1>(A, nbx, d);
+    std::vector<unsigned> hc((size_t)blocks);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(hc.data(), d, sizeof(unsigned) * blocks, hipMemcpyDeviceToHost);
+    hipFree(d);
+    if (e != hipSuccess) { set_error(std::string("count tiles: ") + hipGetErrorString(e)); return BNOS_E_DEVICE; }
+    int64_t tot = 0;
+    for (unsigned v : hc) tot += v;
+    if (tiles_read) *tiles_read = tot;
     if (tiles_per_pass) *tiles_per_pass = (int64_t)t->n * (t->S_pad / 256);
     return BNOS_OK;
 }
@@ -248,5 +268,71 @@ extern "C" bnos_status bnos_table_timing_read(bnos_table h, double *total_ms, in
     if (total_ms) *total_ms = t->timed_ms;
     if (launches) *launches = t->timed_launches;
     if (table_passes) *table_passes = t->timed_passes;
+    return BNOS_OK;
+}
+
+extern "C" bnos_status bnos_table_autotune(bnos_table h, const int32_t *orders, int32_t B, int32_t reps, void *stream,
+                                           int32_t *chunk_steps, int32_t *orders_per_block, double *ms_per_launch)
+{
+    TableT *t = reinterpret_cast<TableT *>(h);
+    if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
+    if (!orders) { set_error("NULL argument"); return BNOS_E_INVALID; }
+    if (B < 1 || B > (1 << 20) || reps < 1 || reps > 1000) { set_error("B or reps out of range"); return BNOS_E_RANGE; }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    BNOS_HIP(hipSetDevice(t->device));
+    BNOS_HIP(hipDeviceSynchronize());
+    const int bk = TableT::bucket(B);
+    const int old_cs = t->tuned_cs[bk], old_bt = t->tuned_bt[bk];
+    const bool old_timing = t->timing;
+    t->timing = false;
+    double *d_out = nullptr;
+    uint64_t *d_best = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc((void **)&d_out, sizeof(double) * 2 * (size_t)B);
+    if (e == hipSuccess) e = hipMalloc((void **)&d_best, sizeof(uint64_t) * (size_t)B * t->n);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    double best_ms = 1e300;
+    int best_cs = t->chunk_entries / kEntriesPerStep, best_bt = pick_bt(t, B);
+    bnos_status s = BNOS_OK;
+    for (int cs = 1; cs <= t->pad_steps && e == hipSuccess && s == BNOS_OK; cs <<= 1) {
+        t->tuned_cs[bk] = cs;
+        if ((s = ensure_workspace(t, B)) != BNOS_OK) break;
+        for (int bt = 1; bt <= 8 && bt <= B && s == BNOS_OK; bt <<= 1) {
+            ScoreArgs A = score_args(t, orders, B, d_out, d_out + B, d_best, nullptr, nullptr);
+            for (int r = 0; r <= reps && s == BNOS_OK; ++r) {
+                if (r == 1) e = hipEventRecord(e0, st);
+                if ((s = launch_stream(t, A, st, bt)) != BNOS_OK) break;
+                hipLaunchKernelGGL(k_merge, dim3(B), dim3(kMergeWaves * 64), 0, st, A);
+            }
+            if (s != BNOS_OK) break;
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms / reps < best_ms) {
+                best_ms = ms / reps;
+                best_cs = cs;
+                best_bt = bt;
+            }
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipFree(d_out);
+    hipFree(d_best);
+    t->timing = old_timing;
+    if (s != BNOS_OK || e != hipSuccess) {
+        t->tuned_cs[bk] = old_cs;
+        t->tuned_bt[bk] = old_bt;
+        if (s == BNOS_OK) { set_error(std::string("autotune: ") + hipGetErrorString(e)); s = BNOS_E_DEVICE; }
+        return s;
+    }
+    t->tuned_cs[bk] = best_cs;
+    t->tuned_bt[bk] = best_bt;
+    if ((s = ensure_workspace(t, B)) != BNOS_OK) return s;
+    if (chunk_steps) *chunk_steps = best_cs;
+    if (orders_per_block) *orders_per_block = best_bt;
+    if (ms_per_launch) *ms_per_launch = best_ms;
     return BNOS_OK;
 }

@@ -101,6 +101,36 @@ __device__ __forceinline__ void acc_wave_reduce(Acc &a, int lane)
     }
 }
 
+// Butterfly merge of R independent states at once (their shuffles and merges
+// interleave, hiding the cross-lane latency); same pairing rule as above.
+template <int R>
+__device__ __forceinline__ void acc_wave_reduce_n(Acc (&a)[R], int lane)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        Acc o[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) o[r] = acc_shfl_xor(a[r], off);
+        const bool upper = (lane & off) != 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            Acc lo, hi;
+            lo.m = upper ? o[r].m : a[r].m;
+            hi.m = upper ? a[r].m : o[r].m;
+            lo.s = upper ? o[r].s : a[r].s;
+            hi.s = upper ? a[r].s : o[r].s;
+            lo.best = upper ? o[r].best : a[r].best;
+            hi.best = upper ? a[r].best : o[r].best;
+            lo.sec = upper ? o[r].sec : a[r].sec;
+            hi.sec = upper ? a[r].sec : o[r].sec;
+            lo.bm = upper ? o[r].bm : a[r].bm;
+            hi.bm = upper ? a[r].bm : o[r].bm;
+            acc_merge(lo, hi);
+            a[r] = lo;
+        }
+    }
+}
+
 __device__ __forceinline__ double wave_sum_f64(double v, int lane)
 {
     // fixed butterfly: the lower lane's value is the left operand
@@ -160,7 +190,6 @@ struct ScoreArgs {
     const int32_t *wl_count;   // [n] or null (then slot j of group g is order g*BT + j)
     const int32_t *wl_list;    // [n][B]
     const uint64_t *tand;      // tile summaries, or null
-    unsigned long long *tiles_loaded;   // counter, or null
 };
 
 // What one streaming block needs to know about its table and its orders.
@@ -175,7 +204,6 @@ struct TabView {
     const int32_t *wl_count;    // [n] or null
     const int32_t *wl_list;     // [n][B]
     const uint64_t *tand;       // [n * S_pad / 256] AND of each 256-entry tile's masks, or null (no skipping)
-    unsigned long long *tiles_loaded;   // counter of tiles read, or null
 };
 
 // One block streams chunk `chunk` of node `node`'s entries once and folds each
@@ -194,6 +222,11 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     // orders this block folds: slots b0..b0+BT-1 of the plain batch or of node's work list
     const int count = V.wl_count ? V.wl_count[node] : V.B;
     if (b0 >= count) return;                     // uniform: nothing listed for this group
+    const int64_t row = (int64_t)node * V.S_pad + (int64_t)chunk * V.chunk_entries;
+    const int steps = V.chunk_entries / kEntriesPerStep;    // each wavefront owns tiles wave + 4*i, i < steps
+    // this wavefront's tile summaries, requested before the predecessor masks so the latencies overlap
+    uint64_t tsum = 0;
+    if (V.tand && lane < steps) tsum = V.tand[(row >> 8) + (int64_t)lane * 4 + wave];
 
     for (int j = wave; j < BT; j += kScoreThreads / 64) {
         uint64_t np = ~0ull;   // no order in this slot: nothing is consistent
@@ -218,65 +251,73 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         acc_init(a[j]);
     }
 
-    const int64_t row = (int64_t)node * V.S_pad + (int64_t)chunk * V.chunk_entries;
     const u64x2 *mp = reinterpret_cast<const u64x2 *>(V.masks + row);
     const f32x4 *sp = reinterpret_cast<const f32x4 *>(V.scores + row);
-    const int steps = V.chunk_entries / kEntriesPerStep;
-    // Tile skipping: at step `it` this wavefront covers one 256-entry tile; if
-    // the AND of the tile's masks holds a node outside an order's predecessor
-    // set, every entry of the tile does, and the order can skip the tile (a
-    // tile no order needs is not loaded at all).  Lane k holds the summary of
-    // this wavefront's tile at step k (steps <= 16).
-    uint64_t tsum = 0;
-    if (V.tand && lane < steps) tsum = V.tand[(row >> 8) + (int64_t)lane * 4 + wave];
-    auto need = [&](int it) -> uint32_t {      // bit j: slot j may find a consistent entry
-        if (!V.tand) return (1u << BT) - 1u;
-        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)tsum, it);
-        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(tsum >> 32), it);
-        const uint64_t sm = ((uint64_t)hi << 32) | lo;
+    // Tile skipping: if the AND of a tile's masks holds a node outside an
+    // order's predecessor set, every entry of the tile does, and the order
+    // skips the tile; tiles no order of the block needs are not read.  Each
+    // wavefront compacts its needed tiles (kept in tile order, so the fold
+    // order of the entries that matter is the same as without skipping) so
+    // that every iteration loads one tile.
+    __shared__ int s_tile[kScoreThreads / 64][kMaxStepsPerChunk];
+    __shared__ uint32_t s_tneed[kScoreThreads / 64][kMaxStepsPerChunk];
+    __shared__ int s_ntile[kScoreThreads / 64];
+    {
         uint32_t m = 0;
+        if (lane < steps) {
+            if (V.tand) {
 #pragma unroll
-        for (int j = 0; j < BT; ++j) m |= ((sm & npred[j]) == 0ull) ? (1u << j) : 0u;
-        return m;
-    };
-    // Software pipeline: the loads of step it+1 are in flight while step it is folded.
-    int q = threadIdx.x;                                     // this lane's 4-entry group
-    uint32_t need_n = need(0);
+                for (int j = 0; j < BT; ++j) m |= ((tsum & npred[j]) == 0ull) ? (1u << j) : 0u;
+            } else {
+                m = (1u << BT) - 1u;
+            }
+        }
+        const uint64_t bal = __ballot(m != 0u);
+        if (m != 0u) {
+            const int pos = __popcll(bal & ((1ull << lane) - 1ull));
+            s_tile[wave][pos] = lane * 4 + wave;
+            s_tneed[wave][pos] = m;
+        }
+        if (lane == 0) s_ntile[wave] = __popcll(bal);
+    }
+    __syncthreads();
+    const int nt = s_ntile[wave];
+    // Software pipeline over this wavefront's needed tiles: the loads of the
+    // next tile are in flight while the current one is folded.
+    int k = 0;
     u64x2 n01 = {0ull, 0ull}, n23 = {0ull, 0ull};
     f32x4 nsc = {0.f, 0.f, 0.f, 0.f};
-    unsigned loaded = 0;
-    if (need_n) {
+    uint32_t need_n = 0;
+    if (k < nt) {
+        const int q = s_tile[wave][k] * 64 + lane;           // this lane's 4-entry group
+        need_n = s_tneed[wave][k];
         n01 = __builtin_nontemporal_load(&mp[2 * q]);
         n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
         nsc = __builtin_nontemporal_load(&sp[q]);
     }
-    for (int it = 0; it < steps; ++it) {
+    for (; k < nt; ++k) {
         const u64x2 m01 = n01, m23 = n23;
         const f32x4 sc = nsc;
         const uint32_t need_c = need_n;
-        if (it + 1 < steps) {
-            q += kScoreThreads;
-            need_n = need(it + 1);
-            if (need_n) {
-                n01 = __builtin_nontemporal_load(&mp[2 * q]);
-                n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
-                nsc = __builtin_nontemporal_load(&sp[q]);
-            }
+        const int kn = k + 1;
+        if (kn < nt) {
+            const int q = s_tile[wave][kn] * 64 + lane;
+            need_n = s_tneed[wave][kn];
+            n01 = __builtin_nontemporal_load(&mp[2 * q]);
+            n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
+            nsc = __builtin_nontemporal_load(&sp[q]);
         }
-        if (need_c == 0u) continue;                          // uniform across the wavefront
-        ++loaded;
         const uint64_t mk[4] = {m01.x, m01.y, m23.x, m23.y};
         const float x[4] = {sc.x, sc.y, sc.z, sc.w};
 #pragma unroll
         for (int j = 0; j < BT; ++j) {
             if (!((need_c >> j) & 1u)) continue;             // uniform
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if ((mk[k] & npred[j]) == 0ull) acc_push(a[j], x[k], mk[k]);
+            for (int e = 0; e < 4; ++e) {
+                if ((mk[e] & npred[j]) == 0ull) acc_push(a[j], x[e], mk[e]);
             }
         }
     }
-    if (V.tiles_loaded && lane == 0) atomicAdd(V.tiles_loaded, (unsigned long long)loaded);
 
 #pragma unroll
     for (int j = 0; j < BT; ++j) {
@@ -330,8 +371,51 @@ __device__ __forceinline__ TabView view_of(const ScoreArgs &A)
     V.wl_count = A.wl_count;
     V.wl_list = A.wl_list;
     V.tand = A.tand;
-    V.tiles_loaded = A.tiles_loaded;
     return V;
+}
+
+// Measurement only: how many 256-entry tiles k_score<BT> reads for these
+// orders with tile skipping (same grid, same tests, no data loads).  One
+// count per block, written to counts[blockIdx.y * gridDim.x + blockIdx.x].
+template <int BT>
+__global__ __launch_bounds__(kScoreThreads) void k_count_tiles(ScoreArgs A, unsigned *__restrict__ counts)
+{
+    __shared__ uint64_t s_np[BT];
+    __shared__ unsigned s_c[kScoreThreads / 64];
+    const int node = blockIdx.x / A.chunks;
+    const int chunk = blockIdx.x - node * A.chunks;
+    const int b0 = blockIdx.y * BT;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int n = A.n;
+    const int count = A.B;
+    for (int j = wave; j < BT; j += kScoreThreads / 64) {
+        uint64_t np = ~0ull;
+        if (b0 + j < count) {
+            bool valid;
+            np = ~wave_pred(A.orders + (int64_t)(b0 + j) * n, n, node, lane, valid);
+        }
+        if (lane == 0) s_np[j] = np;
+    }
+    __syncthreads();
+    const int64_t row = (int64_t)node * A.S_pad + (int64_t)chunk * A.chunk_entries;
+    const int steps = A.chunk_entries / kEntriesPerStep;
+    unsigned c = 0;
+    if (b0 < count) {
+        for (int it = 0; it < steps; ++it) {
+            const uint64_t sm = A.tand[(row >> 8) + (int64_t)it * 4 + wave];
+            bool any = false;
+            for (int j = 0; j < BT; ++j) any |= (sm & s_np[j]) == 0ull;
+            c += any ? 1u : 0u;
+        }
+    }
+    if (lane == 0) s_c[wave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned tot = 0;
+        for (int w = 0; w < kScoreThreads / 64; ++w) tot += s_c[w];
+        counts[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+    }
 }
 
 // Grid: x = node * chunks + chunk, y = group of BT orders.
@@ -411,7 +495,12 @@ __device__ __forceinline__ void merge_block(const ScoreArgs &A, int b, double *s
         if (i >= n) break;
         const Partial *pp = A.part + ((int64_t)b * n + i) * chunks;
         for (int c = lane + 64; c < chunks; c += 64) acc_merge(r[k], load_partial(pp + c));
-        acc_wave_reduce(r[k], lane);
+    }
+    acc_wave_reduce_n<kMergeNodesPerWave>(r, lane);   // nodes beyond n reduce identity states
+#pragma unroll
+    for (int k = 0; k < kMergeNodesPerWave; ++k) {
+        const int i = wave + kMergeWaves * k;
+        if (i >= n) break;
         if (lane == 0) {
             const double li = (double)r[k].m + log((double)r[k].s);
             const int64_t o = (int64_t)b * n + i;

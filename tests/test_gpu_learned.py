@@ -1,6 +1,7 @@
 """Learned swap proposal on the device: static features vs the oracle, exact
 stationarity of the q-corrected chains, and the harvest of accepted moves."""
 import itertools
+import math
 
 import numpy as np
 import pytest
@@ -117,3 +118,87 @@ def test_uniform_chains_unchanged_by_harvest(bnos, prior20):
     t.run_chains(b, 200, seed=3)
     for k in ("orders", "scores", "best_graphs", "best_scores", "accepted", "trace", "accept_flags"):
         assert torch.equal(a[k], b[k]), k
+
+
+def dyadic_position_network(seed):
+    """Parameters whose forward pass is exact in BF16/FP32 and FP64 alike when
+    the only nonzero first-layer column is the position feature p/n with n = 8:
+    all weights are small dyadic rationals, so both sides get identical logits."""
+    rng = np.random.default_rng(seed)
+    H = 128
+    W1 = np.zeros((H, 8))
+    W1[:, 0] = rng.choice([-1.0, -0.5, 0.5, 1.0], size=H)
+    b1 = rng.integers(-2, 3, size=H) / 4.0
+    W2 = rng.choice([-0.25, 0.0, 0.0, 0.25], size=(H, H))
+    b2 = rng.integers(-2, 3, size=H) / 8.0
+    w3 = rng.choice([-0.5, 0.0, 0.5], size=H)
+    prm = np.concatenate([W1.ravel(), b1, W2.ravel(), b2, w3, [0.0]])
+    assert np.array_equal(prm.astype(np.float32).astype(np.float64), prm)
+    return prm
+
+
+def oracle_learned_step(orc, K, seed, chain, t, res, prm, stats, eps, target):
+    """The oracle's (ln u, log MH ratio) at iteration t of its own learned chain `res`."""
+    n = orc.shape[0]
+    zeros, ones = np.zeros(8), np.ones(8)
+
+    def logits_of(order):
+        l, m, best, nl, nb, ns = oracle.score_order(orc, K, order, round_f32=True)
+        return oracle.mlp_forward(prm, (oracle.features(order, nb, ns, None, stats) - zeros) / ones), l, m
+
+    cur = list(oracle.initial_order(seed, chain, n))
+    for s in range(1, t + 1):
+        lc, _, _ = logits_of(cur)
+        pa, pb = oracle.learned_pair(seed, chain, s, lc, cur, eps)
+        prop = list(cur)
+        prop[pa], prop[pb] = prop[pb], prop[pa]
+        if s < t:
+            if res["acc"][s - 1]:
+                cur = prop
+            continue
+        lp, l, m = logits_of(prop)
+        a, b = cur[pa], cur[pb]
+        new = l if target == 0 else m
+        ratio = new - res["trace"][t - 1] + oracle.pair_logq(lp, a, b, eps) - oracle.pair_logq(lc, a, b, eps)
+        return math.log(oracle.accept_uniform(seed, chain, t)), ratio
+
+
+@pytest.mark.parametrize("target", [0, 1])
+def test_learned_chains_match_oracle_in_lockstep(bnos, target):
+    # same proposals (the logits agree exactly, the pair sampler is FP64 on
+    # both sides) and the same decisions except within TAU of the threshold
+    TAU, REL = 1e-3, 1e-5
+    w = datagen.WORKLOADS["tiny8"]
+    net, _ = datagen.make(w)
+    t = bnos.build_score_table(net.data, net.arities, w.K)
+    orc = oracle.build_table(net.data, net.arities, w.K)
+    stats = oracle.table_stats(orc, w.K, round_f32=True)
+    prm = dyadic_position_network(31 + target)
+    m = bnos.Mlp()
+    m.set_params(prm.astype(np.float32), np.zeros(8, np.float32), np.ones(8, np.float32))
+    C, iters, seed, eps = 10, 400, 77 + target, 0.25
+    st = t.new_chain_state(C, iters, trace_every=1, flags=True)
+    t.run_chains(st, iters, seed=seed, target=target, mlp=m, eps=eps, trace_every=1)
+    g = {k: (v.cpu().numpy() if v is not None else None) for k, v in st.items()}
+    full = 0
+    for c in range(C):
+        res = oracle.run_chain_learned(orc, w.K, seed, c, iters, prm, np.zeros(8), np.ones(8), None, stats,
+                                       eps=eps, target=target)
+        flags = g["accept_flags"][c, :iters].astype(bool)
+        mism = np.nonzero(flags != res["acc"].astype(bool))[0]
+        if len(mism):
+            k = int(mism[0]) + 1
+            lu, ratio = oracle_learned_step(orc, w.K, seed, c, k, res, prm, stats, eps, target)
+            assert abs(lu - ratio) <= TAU, (c, k, lu, ratio)
+            np.testing.assert_allclose(g["trace"][c, :k], res["trace"][:k], rtol=REL)
+            continue
+        full += 1
+        np.testing.assert_allclose(g["trace"][c, :iters + 1], res["trace"], rtol=REL, atol=1e-6)
+        assert list(g["orders"][c]) == list(res["order"]), c
+        assert [int(x) for x in g["best_graphs"][c].view(np.uint64)] == [int(x) for x in res["best_graph"]], c
+        assert int(g["accepted"][c]) == res["accepted"]
+    assert full >= C - 1
+    acc = g["accepted"].sum() / (C * iters)
+    assert 0.02 < acc < 0.98
+    m.free()
+    t.free()

@@ -314,10 +314,8 @@ def test_tile_skipping_is_bitwise_identical(bnos, mixed60, B):
     t.tile_skip(False)
     full = dev_score(t, orders)
     t.tile_skip(True)
-    t.timing(True)
     skip = dev_score(t, orders)
-    loaded, per_pass = t.tiles_read()
-    t.timing(False)
+    loaded, per_pass = t.count_tiles(torch.from_numpy(orders).cuda())
     for k in full:
         assert np.array_equal(full[k].view(np.uint8), skip[k].view(np.uint8)), k
     passes = -(-B // (8 if B >= 8 else (4 if B >= 4 else (2 if B >= 2 else 1))))
@@ -334,3 +332,39 @@ def test_tile_skipping_small_tables(bnos, prior20):
     for k in full:
         assert np.array_equal(full[k].view(np.uint8), skip[k].view(np.uint8)), k
     assert check_orders_against_oracle(skip, orc, w.K, orders) == 0
+
+
+@pytest.mark.parametrize("chunk_steps", [1, 2, 4, 16])
+def test_chunk_length_option_matches_oracle(bnos, prior20, chunk_steps):
+    # every chunk length (and the row padding it implies) gives the oracle's result
+    w, net, prior, t0, orc = prior20
+    t = bnos.build_score_table(net.data, net.arities, w.K, prior=prior, chunk_steps=chunk_steps)
+    try:
+        orders = datagen.random_orders(w.n, 11, seed=40 + chunk_steps)
+        got = dev_score(t, orders)
+        assert check_orders_against_oracle(got, orc, w.K, orders) == 0
+        ref = dev_score(t0, orders)
+        assert np.array_equal(got["best"], ref["best"])
+        assert np.array_equal(got["node_second"].view(np.uint32), ref["node_second"].view(np.uint32))
+    finally:
+        t.free()
+
+
+def test_autotune_is_per_batch_bucket(bnos, mixed60):
+    w, net, prior, t = mixed60
+    o1 = torch.from_numpy(datagen.random_orders(w.n, 1, seed=70)).cuda()
+    o20 = torch.from_numpy(datagen.random_orders(w.n, 20, seed=71)).cuda()
+    before = dev_score(t, o20.cpu().numpy())
+    cs1, bt1, ms1 = t.autotune(o1, reps=2)
+    assert cs1 in (1, 2, 4, 8, 16) and bt1 == 1 and ms1 > 0
+    single = dev_score(t, o1.cpu().numpy())
+    cs20, bt20, ms20 = t.autotune(o20, reps=2)
+    assert cs20 in (1, 2, 4, 8, 16) and bt20 in (1, 2, 4, 8) and ms20 > 0
+    # tuning the 16+ bucket leaves the single-order launch as it was
+    again = dev_score(t, o1.cpu().numpy())
+    for k in single:
+        assert np.array_equal(single[k].view(np.uint8), again[k].view(np.uint8)), k
+    after = dev_score(t, o20.cpu().numpy())
+    assert np.array_equal(after["best"], before["best"])
+    np.testing.assert_allclose(after["lse"], before["lse"], rtol=1e-12)
+    np.testing.assert_allclose(after["node_lse"], before["node_lse"], rtol=1e-12)
