@@ -89,18 +89,24 @@ def cpu_baseline(net, prior, K: int, sample_nodes=(7, 41), seed: int = 3):
     }
 
 
-def measured_traffic(batch: int):
-    """HBM bytes per k_score launch from the committed rocprofv3 counter runs, or None
-    when the kernel source changed since they were taken (or the batch differs)."""
+def measured_traffic(batch: int, mode: str):
+    """HBM bytes per k_score launch ("full" scan or tile "skip") from the committed
+    rocprofv3 counter runs, or None when the scoring sources changed since they
+    were taken or no run matches the batch size."""
     import hashlib
     try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        recs = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+        h = hashlib.sha256()
+        for f in recs["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
     except (OSError, ValueError, KeyError):
         return None
-    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256") or rec.get("batch") != batch:
+    if h.hexdigest() != recs.get("sources_sha256"):
         return None
-    return float(rec["bytes_per_launch"])
+    for rec in recs.get("runs", []):
+        if rec.get("batch") == batch and rec.get("mode") == mode:
+            return float(rec["bytes_per_launch"])
+    return None
 
 
 def bench_chains(bnos, datagen, wname: str, chains: int, iters: int, seed: int = 102):
@@ -170,11 +176,13 @@ def bench_uneven(bnos, datagen, n_datasets: int, chains: int, iters: int, seed: 
             "speedup": seq / one}
 
 
-def bench_learned(bnos, datagen, wname: str, chains: int, harvest_iters: int, iters: int, epochs: int,
+def bench_learned(bnos, datagen, wname: str, chains: int, moves: int, iters: int, epochs: int,
                   seed: int = 404):
-    """Learned swap proposal: harvest accepted moves from uniform chains, train the
-    network on the device, then run learned and uniform chains from the same
-    starting orders; ESS/s of the log-sum-exp trace and best-graph score."""
+    """Learned swap proposal: harvest `moves` accepted moves from uniform chains
+    (which also serves as burn-in), train the network on the device, then resume
+    every chain from its harvested state twice, with the uniform and with the
+    learned proposal, on the same random-number streams; plus one uniform chain
+    alone.  ESS/s of the log-sum-exp trace, acceptance, best-graph score."""
     import torch
     from paper_1210_5128_amd import ess as E
     w = datagen.WORKLOADS[wname]
@@ -182,50 +190,73 @@ def bench_learned(bnos, datagen, wname: str, chains: int, harvest_iters: int, it
     table = bnos.build_score_table(net.data, net.arities, w.K, ess=w.ess, prior=prior)
     n = w.n
     out = {"workload": f"{w.name}: n={n}, K={w.K}, N={w.N}", "chains": chains, "iterations": iters}
-    # 1. harvest
-    cap = max(1, harvest_iters // 2)
-    st = table.new_chain_state(chains, harvest_iters, trace_every=harvest_iters, harvest_cap=cap)
+    # 1. harvest (uniform proposal, fresh start); the chains run until every one
+    # has filled its share of the harvest
+    cap = -(-moves // chains)
+    st = table.new_chain_state(chains, 1, trace_every=0, harvest_cap=cap)
     t0 = time.perf_counter()
-    table.run_chains(st, harvest_iters, seed + 1, trace_every=harvest_iters)
-    torch.cuda.synchronize()
+    done, block = 0, 2000
+    while True:
+        table.run_chains(st, block, seed + 1, first_iteration=done, trace_every=0)
+        done += block
+        torch.cuda.synchronize()
+        if int(st["harvest_count"].min().item()) >= cap or done >= 400000:
+            break
     cnt = st["harvest_count"].cpu().numpy()
-    feats = torch.cat([st["harvest_feats"][c, :int(cnt[c])] for c in range(chains)])
-    pairs = torch.cat([st["harvest_pairs"][c, :int(cnt[c])] for c in range(chains)])
-    out["harvest"] = {"moves": int(feats.shape[0]), "seconds": time.perf_counter() - t0}
+    feats = torch.cat([st["harvest_feats"][c, :int(min(cnt[c], cap))] for c in range(chains)])
+    pairs = torch.cat([st["harvest_pairs"][c, :int(min(cnt[c], cap))] for c in range(chains)])
+    del st["harvest_feats"], st["harvest_pairs"]
+    out["harvest"] = {"moves": int(feats.shape[0]), "iterations_per_chain": done,
+                      "accept_rate": float(st["accepted"].sum().item()) / (chains * done),
+                      "seconds": time.perf_counter() - t0}
+    print(f"# harvest: {feats.shape[0]} moves in {done} iterations per chain, "
+          f"{out['harvest']['seconds']:.1f} s", file=sys.stderr, flush=True)
     # 2. train
     m = bnos.Mlp()
     m.set_params(datagen.mlp_params(seed + 2, scale=0.5).astype(np.float32))
     m.fit_norm(feats)
-    steps = epochs * ((feats.shape[0] + 1023) // 1024)
+    batch = 1024
+    steps = epochs * ((feats.shape[0] + batch - 1) // batch)
     trace = torch.zeros(max(steps, 1), dtype=torch.float32, device=feats.device)
     t0 = time.perf_counter()
-    m.train(feats, pairs, epochs=epochs, batch=1024, lr=2e-3, seed=seed + 3, loss_trace=trace)
+    m.train(feats, pairs, epochs=epochs, batch=batch, lr=2e-3, seed=seed + 3, loss_trace=trace)
     torch.cuda.synchronize()
     tr = trace.cpu().numpy()
-    out["train"] = {"epochs": epochs, "steps": int(steps), "seconds": time.perf_counter() - t0,
+    out["train"] = {"samples": int(feats.shape[0]), "epochs": epochs, "batch": batch, "steps": int(steps),
+                    "seconds": time.perf_counter() - t0,
                     "loss_first": float(tr[:10].mean()), "loss_last": float(tr[-10:].mean()),
                     "uniform_pair_loss": float(np.log(n * (n - 1) / 2))}
-    # 3. learned vs uniform, same chain ids (same initial orders)
-    for label, mlp in (("uniform", None), ("learned", m)):
-        s2 = table.new_chain_state(chains, iters, trace_every=1)
-        table.run_chains(s2, 20, seed + 9, mlp=mlp)                    # warm-up
-        torch.cuda.synchronize()
-        s2 = table.new_chain_state(chains, iters, trace_every=1)
+    print(f"# train: {steps} steps in {out['train']['seconds']:.1f} s, loss {out['train']['loss_first']:.3f} -> "
+          f"{out['train']['loss_last']:.3f} (uniform {out['train']['uniform_pair_loss']:.3f})",
+          file=sys.stderr, flush=True)
+    del feats, pairs
+    # 3. resume every chain from its harvested state: uniform vs learned, and one uniform chain alone
+    base = {k: v for k, v in st.items() if k in ("orders", "scores", "best_graphs", "best_scores", "accepted")}
+    for label, mlp, C in (("uniform", None, chains), ("learned", m, chains), ("single_uniform", None, 1)):
+        s2 = {k: v[:C].clone() for k, v in base.items()}
+        s2["trace"] = torch.zeros((C, iters + 1), dtype=torch.float64, device=base["scores"].device)
+        s2["accept_flags"] = None
+        a0 = s2["accepted"].clone()
         t0 = time.perf_counter()
-        table.run_chains(s2, iters, seed, mlp=mlp)
+        table.run_chains(s2, iters, seed + 5, first_iteration=done, mlp=mlp)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         trc = s2["trace"].cpu().numpy()
         e = E.ess(trc)
-        out[label] = {"seconds": dt, "chain_iterations_per_s": chains * iters / dt, "ess": e, "ess_per_s": e / dt,
-                      "accept_rate": float(s2["accepted"].sum().item()) / (chains * iters),
+        out[label] = {"chains": C, "seconds": dt, "chain_iterations_per_s": C * iters / dt,
+                      "ess": e, "ess_per_s": e / dt, "ess_per_1k_chain_iterations": 1e3 * e / (C * iters),
+                      "accept_rate": float((s2["accepted"] - a0).sum().item()) / (C * iters),
                       "best_score_max": float(s2["best_scores"].max().item()),
                       "best_score_mean": float(s2["best_scores"].mean().item()),
-                      "final_score_mean": float(s2["scores"].mean().item()),
-                      "split_rhat": E.split_rhat(trc)}
-        print(f"# {label}: {dt:.2f} s, ESS/s {e / dt:.1f}, accept {out[label]['accept_rate']:.3f}",
+                      "score_mean": float(trc.mean()),
+                      "split_rhat": E.split_rhat(trc) if C > 1 else None}
+        print(f"# {label}: {dt:.2f} s, ESS {e:.0f}, ESS/s {e / dt:.1f}, accept {out[label]['accept_rate']:.3f}",
               file=sys.stderr, flush=True)
     out["ess_per_s_ratio_learned_vs_uniform"] = out["learned"]["ess_per_s"] / max(out["uniform"]["ess_per_s"], 1e-30)
+    out["ess_per_s_ratio_learned_vs_single_uniform"] = (out["learned"]["ess_per_s"] /
+                                                        max(out["single_uniform"]["ess_per_s"], 1e-30))
+    out["ess_per_iteration_ratio_learned_vs_uniform"] = (out["learned"]["ess_per_1k_chain_iterations"] /
+                                                         max(out["uniform"]["ess_per_1k_chain_iterations"], 1e-30))
     m.free()
     table.free()
     return out
@@ -242,11 +273,18 @@ def main():
                     help="also time steps of this many orders (0 = skip); reported under 'batched'")
     ap.add_argument("--workload", default="mixed60")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--chunk-steps", type=int, default=0,
+                    help="fix the scoring chunk length (x1024 entries) instead of autotuning it")
+    ap.add_argument("--passes", choices=("both", "skip", "full"), default="both",
+                    help="which scoring passes to time: tile skipping (the headline), full scan, or both; "
+                         "one alone keeps a profiler's per-kernel figures unmixed")
     ap.add_argument("--chains", type=int, default=256, help="batched chains on the mixed40 table (0 = skip)")
     ap.add_argument("--chain-iters", type=int, default=20000)
     ap.add_argument("--learned", type=int, default=0, metavar="C",
                     help="also run the learned-proposal comparison with C chains on the mixed60 table (0 = skip)")
-    ap.add_argument("--learned-iters", type=int, default=2000)
+    ap.add_argument("--learned-iters", type=int, default=2000, help="iterations of each compared run")
+    ap.add_argument("--learned-moves", type=int, default=1000000, help="accepted moves harvested for training")
+    ap.add_argument("--learned-epochs", type=int, default=4)
     ap.add_argument("--learned-workload", default="mixed60")
     ap.add_argument("--uneven", type=int, default=0, metavar="D",
                     help="also run the uneven family: D datasets x 64 chains in one launch vs one at a time")
@@ -284,7 +322,7 @@ def main():
     n, K, B = w.n, w.K, args.batch
     print(f"# building table: {w}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    table = bnos.build_score_table(net.data, net.arities, K, ess=w.ess, prior=prior)
+    table = bnos.build_score_table(net.data, net.arities, K, ess=w.ess, prior=prior, chunk_steps=args.chunk_steps)
     build_s = time.perf_counter() - t0
     info = table.info()
     S = info["entries_per_node"]
@@ -339,22 +377,30 @@ def main():
     stream = torch.cuda.current_stream()
     # launch shape (chunk length, orders per block) tuned per batch size before timing
     tuned = {}
-    for Bq in sorted({B, args.batched_check} - {0}):
+    for Bq in ([] if args.chunk_steps else sorted({B, args.batched_check} - {0})):
         o = torch.from_numpy(datagen.random_orders(n, Bq, seed=900 + Bq)).to(dev)
         cs, bt, ms = table.autotune(o, reps=20 if Bq < 64 else 3, stream=stream)
         tuned[str(Bq)] = {"chunk_steps": cs, "orders_per_block": bt, "tune_ms_per_launch": ms}
         print(f"# autotune B={Bq}: chunk {cs}x1024 entries, {bt} orders/block, {ms * 1e3:.1f} us",
               file=sys.stderr, flush=True)
-    rf = timed(B, args.steps, args.warmup, skip=False)         # full scan of every entry
-    print(f"# full scan: {rf['total_ms']:.3f} ms for {args.steps} steps", file=sys.stderr, flush=True)
-    r = timed(B, args.steps, args.warmup, skip=True)           # with tile summaries (default path)
+    if args.chunk_steps:
+        tuned = {"fixed_chunk_steps": args.chunk_steps}
+    rf = r = None
+    if args.passes != "skip":
+        rf = timed(B, args.steps, args.warmup, skip=False)     # full scan of every entry
+        print(f"# full scan: {rf['total_ms']:.3f} ms for {args.steps} steps", file=sys.stderr, flush=True)
+    if args.passes != "full":
+        r = timed(B, args.steps, args.warmup, skip=True)       # with tile summaries (default path)
+    else:
+        r = rf
     print(f"# timed {args.steps} steps: {r['total_ms']:.3f} ms", file=sys.stderr, flush=True)
     ms_per_step, value = r["ms_per_step"], r["value"]
     kernel_avg_ms, passes_per_launch, achieved_gbs = r["kernel_avg_ms"], r["passes_per_launch"], r["gbs"]
-    full_scan = {"order_scores_per_s": rf["value"], "ms_per_step": rf["ms_per_step"],
-                 "kernel_avg_us": rf["kernel_avg_ms"] * 1e3, "algorithmic_bytes_per_launch": rf["alg_bytes"],
-                 "achieved_GBs": rf["gbs"], "frac": rf["gbs"] / HBM_PEAK_GBS,
-                 "traffic": measured_traffic(B) if args.workload == "mixed60" else None}
+    full_scan = None if rf is None else {
+        "order_scores_per_s": rf["value"], "ms_per_step": rf["ms_per_step"],
+        "kernel_avg_us": rf["kernel_avg_ms"] * 1e3, "algorithmic_bytes_per_launch": rf["alg_bytes"],
+        "achieved_GBs": rf["gbs"], "frac": rf["gbs"] / HBM_PEAK_GBS,
+        "traffic": measured_traffic(B, "full") if args.workload == "mixed60" else None}
     batched = None
     if args.batched_check:
         rb = timed(args.batched_check, 20, 3)
@@ -388,11 +434,12 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel": "k_score (tile skipping)",
+            "traffic": (measured_traffic(B, "full" if args.passes == "full" else "skip")
+                        if args.workload == "mixed60" else None),
+            "kernel": "k_score (full scan)" if args.passes == "full" else "k_score (tile skipping)",
             "kernel_avg_us": kernel_avg_ms * 1e3,
             "algorithmic_bytes_per_launch": r["alg_bytes"],
-            "tile_fraction_read": r["tile_fraction"],
+            "tile_fraction_read": r["tile_fraction"] if args.passes != "full" else 1.0,
             "full_scan_equivalent_GBs": r["full_scan_equiv_gbs"],
         },
         "full_scan": full_scan,
@@ -407,8 +454,8 @@ def main():
     if args.uneven:
         out["uneven"] = bench_uneven(bnos, datagen, args.uneven, 64, args.uneven_iters)
     if args.learned:
-        out["learned"] = bench_learned(bnos, datagen, args.learned_workload, args.learned, args.learned_iters,
-                                       args.learned_iters, epochs=4)
+        out["learned"] = bench_learned(bnos, datagen, args.learned_workload, args.learned, args.learned_moves,
+                                       args.learned_iters, epochs=args.learned_epochs)
     if not args.no_cpu:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(net, prior, K)

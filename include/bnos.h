@@ -61,8 +61,8 @@ typedef struct {
                               1: prior entries are the paper's R in [0,1] (Sec. IV).
                               Either way the added term is ln(10) * 100 * (R - 0.5)^3. */
     int32_t chunk_steps;   /* scoring blocks stream chunks of chunk_steps * 1024 entries of one node's
-                              row; a power of two <= 16 that divides the row padding (see
-                              bnos_table_info); 0 = automatic */
+                              row; a power of two <= 16 (rows are then padded to a multiple of at
+                              least that many steps), or 0 = automatic */
     int32_t reserved[6];   /* must be zero */
 } bnos_build_opts;         /* all-zero = defaults */
 
@@ -306,12 +306,14 @@ bnos_status bnos_run_chains_multi(const bnos_table *tables, int32_t T, const bno
 
 /*
  * Kernel timing for measurement: while enabled, every order-scoring launch
- * of this table is bracketed by HIP events recorded on the launch stream.
- * bnos_table_timing_read waits for the recorded events and returns the sum of
- * the scoring kernels' durations (ms), the number of launches and the number
- * of full passes over the table those launches made (a launch scoring B
- * orders streams the table once per group of up to 4 orders) since the last
- * enable, then keeps counting.  Any output pointer may be NULL.
+ * of this table (bnos_score_orders / bnos_score_order) carries a pair of HIP
+ * events that take the streaming kernel's own start and end on the launch
+ * stream (hipExtLaunchKernel).  bnos_table_timing_read waits for them and
+ * returns the sum of the streaming kernels' durations (ms), the number of
+ * launches and the number of passes over the table those launches made (a
+ * launch scoring B orders streams the table once per group of orders per
+ * block) since the last enable, then keeps counting.  Any output pointer may
+ * be NULL.
  */
 bnos_status bnos_table_timing(bnos_table t, int32_t enable);
 

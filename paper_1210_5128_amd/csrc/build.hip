@@ -472,21 +472,20 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     t->S = sets_upto(n - 1, K);
     {
         // Rows are padded to a multiple of P * 1024 entries, P the smallest power
-        // of two >= the row's 1024-entry steps, at most 16; chunk lengths are the
-        // powers of two dividing P.
+        // of two >= the row's 1024-entry steps (and >= a requested chunk
+        // length), at most 16; chunk lengths are the powers of two dividing P.
         const int64_t node_steps = (t->S + kEntriesPerStep - 1) / kEntriesPerStep;
+        int st = o.chunk_steps;
+        if (st != 0 && (st < 1 || st > kMaxStepsPerChunk || (st & (st - 1)) != 0)) {
+            set_error("chunk_steps must be 0 or a power of two <= 16");
+            delete t;
+            return BNOS_E_RANGE;
+        }
         int P = 1;
-        while (P < kMaxStepsPerChunk && P < node_steps) P <<= 1;
+        while (P < kMaxStepsPerChunk && (P < node_steps || P < st)) P <<= 1;
         t->pad_steps = P;
         t->S_pad = ((node_steps + P - 1) / P) * P * kEntriesPerStep;
-        int st = o.chunk_steps;
-        if (st != 0) {
-            if (st < 1 || st > P || (P % st) != 0 || (st & (st - 1)) != 0) {
-                set_error("chunk_steps must be a power of two dividing the row padding (<= 16)");
-                delete t;
-                return BNOS_E_RANGE;
-            }
-        } else {
+        if (st == 0) {
             // automatic: the length that best fills whole rounds of resident blocks
             // (8 blocks of 256 threads per compute unit) for a single-order pass
             int cus = 256;

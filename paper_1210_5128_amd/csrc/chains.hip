@@ -225,16 +225,26 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(const TabView *
         for (int cc = lane + 64; cc < chunks; cc += 64) acc_merge(r[q], load_partial(pp + cc));
     }
     acc_wave_reduce_n<kMergeNodesPerWave>(r, lane);
+    {
+        // all lanes hold the wave's node states; lane q finishes window node wave + 16q
+        float fm = r[0].m, fs = r[0].s, fb = r[0].best, fsec = r[0].sec;
+        uint64_t fbm = r[0].bm;
 #pragma unroll
-    for (int q = 0; q < kMergeNodesPerWave; ++q) {
-        const int w = wave + kMergeWaves * q;
-        if (w >= cnt) break;
-        const int i = s_nodes[w];
-        if (lane == 0) {
-            s_l[i] = (double)r[q].m + log((double)r[q].s);
-            s_b[i] = (double)r[q].best;
-            s_s[i] = (double)r[q].sec;
-            s_bm[i] = r[q].bm;
+        for (int q = 1; q < kMergeNodesPerWave; ++q) {
+            const bool mine = lane == q;
+            fm = mine ? r[q].m : fm;
+            fs = mine ? r[q].s : fs;
+            fb = mine ? r[q].best : fb;
+            fsec = mine ? r[q].sec : fsec;
+            fbm = mine ? r[q].bm : fbm;
+        }
+        const int w = wave + kMergeWaves * lane;
+        if (lane < kMergeNodesPerWave && w < cnt) {
+            const int i = s_nodes[w];
+            s_l[i] = (double)fm + log((double)fs);
+            s_b[i] = (double)fb;
+            s_s[i] = (double)fsec;
+            s_bm[i] = fbm;
         }
     }
     __syncthreads();

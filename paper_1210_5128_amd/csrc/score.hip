@@ -1,6 +1,7 @@
 // Order scoring: for every node, stream its (mask, score) entries, keep those
 // whose parent set lies inside the node's predecessor set, and reduce them by
 // log-sum-exp and by argmax (Sec. III.B, Alg. 1 and Eq. (6)).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -60,15 +61,18 @@ bnos_status ensure_workspace(TableT *t, int B)
     return BNOS_OK;
 }
 
-static bnos_status record_event(TableT *t, bool start, hipStream_t st)
+// The next pair of timing events (created on first use).
+static bnos_status next_events(TableT *t, hipEvent_t &e0, hipEvent_t &e1)
 {
-    std::vector<hipEvent_t> &pool = start ? t->ev_start : t->ev_stop;
-    if (pool.size() <= t->ev_used) {
-        hipEvent_t e;
-        BNOS_HIP(hipEventCreate(&e));
-        pool.push_back(e);
+    for (std::vector<hipEvent_t> *pool : {&t->ev_start, &t->ev_stop}) {
+        if (pool->size() <= t->ev_used) {
+            hipEvent_t e;
+            BNOS_HIP(hipEventCreate(&e));
+            pool->push_back(e);
+        }
     }
-    BNOS_HIP(hipEventRecord(pool[t->ev_used], st));
+    e0 = t->ev_start[t->ev_used];
+    e1 = t->ev_stop[t->ev_used];
     return BNOS_OK;
 }
 
@@ -96,11 +100,14 @@ ScoreArgs score_args(const TableT *t, const int32_t *orders, int B, double *lse,
     return A;
 }
 
+// With events, they take the kernel's own start and end (hipExtLaunchKernel),
+// without the gap an event record on either side of the launch would add.
 template <int BT>
-static void launch_bt(const ScoreArgs &A, int nblocks_x, hipStream_t st)
+static void launch_bt(const ScoreArgs &A, int nblocks_x, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
     dim3 grid((unsigned)nblocks_x, (unsigned)((A.B + BT - 1) / BT));
-    hipLaunchKernelGGL(k_score<BT>, grid, dim3(kScoreThreads), 0, st, A);
+    if (e0) hipExtLaunchKernelGGL(k_score<BT>, grid, dim3(kScoreThreads), 0, st, e0, e1, 0, A);
+    else hipLaunchKernelGGL(k_score<BT>, grid, dim3(kScoreThreads), 0, st, A);
 }
 
 // The streaming pass (k_score) with the table's block shape; timed when enabled.
@@ -109,17 +116,17 @@ bnos_status launch_stream(TableT *t, const ScoreArgs &A, hipStream_t st, int bt)
 {
     bnos_status s;
     if (bt <= 0) bt = pick_bt(t, A.B);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     if (t->timing) {
-        if ((s = record_event(t, true, st)) != BNOS_OK) return s;
+        if ((s = next_events(t, e0, e1)) != BNOS_OK) return s;
     }
     const int nbx = t->n * A.chunks;
-    if (bt == 8) launch_bt<8>(A, nbx, st);
-    else if (bt == 4) launch_bt<4>(A, nbx, st);
-    else if (bt == 2) launch_bt<2>(A, nbx, st);
-    else launch_bt<1>(A, nbx, st);
+    if (bt == 8) launch_bt<8>(A, nbx, st, e0, e1);
+    else if (bt == 4) launch_bt<4>(A, nbx, st, e0, e1);
+    else if (bt == 2) launch_bt<2>(A, nbx, st, e0, e1);
+    else launch_bt<1>(A, nbx, st, e0, e1);
     BNOS_HIP(hipGetLastError());
     if (t->timing) {
-        if ((s = record_event(t, false, st)) != BNOS_OK) return s;
         if (t->ev_passes.size() <= t->ev_used) t->ev_passes.resize(t->ev_used + 1);
         t->ev_passes[t->ev_used] = (A.B + bt - 1) / bt;
         t->ev_used++;

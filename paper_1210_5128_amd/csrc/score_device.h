@@ -470,8 +470,8 @@ __device__ __forceinline__ Acc load_partial(const Partial *p)
 // Merge of one order's chunk partials, run by a whole block of kMergeWaves
 // wavefronts.  Wave w merges nodes w, w+16, w+32, w+48 (lanes over chunks,
 // every node's first partial loaded before any merging so the loads overlap,
-// then a fixed butterfly); lane 0 forms LSE_i = m + ln s in FP64 and writes the
-// node outputs.  Wave 0 then sums the per-node terms in FP64 with a fixed
+// then a fixed butterfly); lanes 0-3 form LSE_i = m + ln s in FP64 for the
+// four nodes at once and write the node outputs.  Wave 0 then sums the per-node terms in FP64 with a fixed
 // butterfly; the sums are valid in lane 0 of wave 0.
 __device__ __forceinline__ void merge_block(const ScoreArgs &A, int b, double *s_l, double *s_b,
                                             bool &valid, double &lse_out, double &max_out)
@@ -497,19 +497,27 @@ __device__ __forceinline__ void merge_block(const ScoreArgs &A, int b, double *s
         for (int c = lane + 64; c < chunks; c += 64) acc_merge(r[k], load_partial(pp + c));
     }
     acc_wave_reduce_n<kMergeNodesPerWave>(r, lane);   // nodes beyond n reduce identity states
+    // every lane now holds all of the wave's node states; lane k finishes node wave + 16k
+    float fm = r[0].m, fs = r[0].s, fb = r[0].best, fsec = r[0].sec;
+    uint64_t fbm = r[0].bm;
 #pragma unroll
-    for (int k = 0; k < kMergeNodesPerWave; ++k) {
-        const int i = wave + kMergeWaves * k;
-        if (i >= n) break;
-        if (lane == 0) {
-            const double li = (double)r[k].m + log((double)r[k].s);
-            const int64_t o = (int64_t)b * n + i;
-            s_l[i] = li;
-            s_b[i] = (double)r[k].best;
-            A.best[o] = valid ? r[k].bm : 0ull;
-            if (A.node_lse) A.node_lse[o] = valid ? li : NAN;
-            if (A.node_second) A.node_second[o] = valid ? r[k].sec : NAN;
-        }
+    for (int k = 1; k < kMergeNodesPerWave; ++k) {
+        const bool mine = lane == k;
+        fm = mine ? r[k].m : fm;
+        fs = mine ? r[k].s : fs;
+        fb = mine ? r[k].best : fb;
+        fsec = mine ? r[k].sec : fsec;
+        fbm = mine ? r[k].bm : fbm;
+    }
+    const int fi = wave + kMergeWaves * lane;
+    if (lane < kMergeNodesPerWave && fi < n) {
+        const double li = (double)fm + log((double)fs);
+        const int64_t o = (int64_t)b * n + fi;
+        s_l[fi] = li;
+        s_b[fi] = (double)fb;
+        A.best[o] = valid ? fbm : 0ull;
+        if (A.node_lse) A.node_lse[o] = valid ? li : NAN;
+        if (A.node_second) A.node_second[o] = valid ? fsec : NAN;
     }
     __syncthreads();
     lse_out = 0.0;

@@ -366,5 +366,8 @@ def test_autotune_is_per_batch_bucket(bnos, mixed60):
         assert np.array_equal(single[k].view(np.uint8), again[k].view(np.uint8)), k
     after = dev_score(t, o20.cpu().numpy())
     assert np.array_equal(after["best"], before["best"])
-    np.testing.assert_allclose(after["lse"], before["lse"], rtol=1e-12)
-    np.testing.assert_allclose(after["node_lse"], before["node_lse"], rtol=1e-12)
+    assert np.array_equal(after["node_second"].view(np.uint32), before["node_second"].view(np.uint32))
+    # another chunk length adds the FP32 partial sums in another order: ln s of
+    # each node moves by a few 1e-7, the per-order sum of 60 nodes by ~1e-6
+    np.testing.assert_allclose(after["node_lse"], before["node_lse"], rtol=0, atol=2e-6)
+    np.testing.assert_allclose(after["lse"], before["lse"], rtol=0, atol=2e-5)
