@@ -262,7 +262,9 @@ typedef struct {
     int32_t proposal;         /* 0: uniform swap of two positions; 1: learned (needs mlp) */
     float eps;                /* learned: weight of the uniform pair in q, (0, 1]; 0 means 0.1 */
     struct bnos_mlp_s *mlp;   /* learned: the network (see bnos_mlp_*), read during the call */
-    int32_t reserved[4];      /* must be zero */
+    int32_t topk;             /* 0..64: keep each chain's topk best distinct graphs (Sec. III.C keeps a
+                                 number of best graphs); 0 = off */
+    int32_t reserved[3];      /* must be zero */
 } bnos_chain_cfg;
 
 typedef struct {              /* DEVICE pointers; the chain state, read when resuming, written always */
@@ -281,6 +283,16 @@ typedef struct {              /* DEVICE pointers; the chain state, read when res
     int32_t *harvest_pairs;   /* [C][harvest_cap][2] node ids */
     int64_t *harvest_count;   /* [C] */
     int64_t harvest_cap;
+    /* Record of the best distinct graphs (cfg.topk > 0): the greedy graph of
+       the initial order and of every accepted order is offered; records are
+       kept in decreasing order of max score (Eq. (6)), a graph already recorded
+       is not added again, among equal scores the earlier record stays ahead,
+       and when the record is full a graph enters only with a score strictly
+       above the last, which drops out.  A fresh start empties the record; a
+       resumed call continues the one in the state.  Entry 0 is best_graphs. */
+    uint64_t *top_graphs;     /* [C][topk][n] */
+    double *top_scores;       /* [C][topk] */
+    int32_t *top_count;       /* [C] records held (in/out) */
 } bnos_chain_state;
 
 /*

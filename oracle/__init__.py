@@ -70,7 +70,7 @@ def lib():
         L.orc_accept_uniform.restype = f64
         L.orc_accept_uniform.argtypes = [u64, u64, u64]
         L.orc_run_chain.restype = None
-        L.orc_run_chain.argtypes = [P, i32, i32, u64, u64, i64, i32, i32, P, P, P, P, P, P]
+        L.orc_run_chain.argtypes = [P, i32, i32, u64, u64, i64, i32, i32, P, P, P, P, P, P, i32, P, P, P]
         L.orc_mlp_num_params.restype = i32
         L.orc_mlp_num_params.argtypes = []
         L.orc_table_stats.restype = None
@@ -87,7 +87,7 @@ def lib():
         L.orc_learned_pair.argtypes = [u64, u64, i32, u64, P, P, f64, P, P]
         L.orc_run_chain_learned.restype = None
         L.orc_run_chain_learned.argtypes = [P, i32, i32, u64, u64, i64, i32, i32, P, P, P, P, P, f64,
-                                            P, P, P, P, P, P]
+                                            P, P, P, P, P, P, i32, P, P, P]
         _lib = L
     return _lib
 
@@ -238,9 +238,14 @@ def accept_uniform(seed: int, chain: int, step: int) -> float:
     return float(lib().orc_accept_uniform(seed, chain, step))
 
 
+def _topk_buffers(n: int, topk: int):
+    return (np.zeros((max(topk, 1), n), dtype=np.uint64), np.zeros(max(topk, 1)), ctypes.c_int32())
+
+
 def run_chain(table: np.ndarray, K: int, seed: int, chain: int, iters: int, target: int = 0,
-              round_f32: bool = True):
-    """Returns dict(order, trace[iters+1], acc[iters], best_graph[n], best_score, accepted)."""
+              round_f32: bool = True, topk: int = 0):
+    """Returns dict(order, trace[iters+1], acc[iters], best_graph[n], best_score, accepted,
+    top_graphs[count][n], top_scores[count]) (the last two empty unless topk > 0)."""
     table = np.ascontiguousarray(table, dtype=np.float64)
     n = table.shape[0]
     order = np.zeros(n, dtype=np.int32)
@@ -249,10 +254,12 @@ def run_chain(table: np.ndarray, K: int, seed: int, chain: int, iters: int, targ
     bg = np.zeros(n, dtype=np.uint64)
     bs = ctypes.c_double()
     na = ctypes.c_int64()
+    tg, ts, tc = _topk_buffers(n, topk)
     lib().orc_run_chain(_p(table), n, K, seed, chain, iters, target, int(round_f32), _p(order),
-                        _p(trace), _p(acc), _p(bg), ctypes.byref(bs), ctypes.byref(na))
+                        _p(trace), _p(acc), _p(bg), ctypes.byref(bs), ctypes.byref(na),
+                        topk, _p(tg), _p(ts), ctypes.byref(tc))
     return dict(order=order, trace=trace, acc=acc[:iters], best_graph=bg, best_score=bs.value,
-                accepted=na.value)
+                accepted=na.value, top_graphs=tg[:tc.value], top_scores=ts[:tc.value])
 
 
 # ---------------------------------------------------------------- learned proposal
@@ -328,7 +335,7 @@ def learned_pair(seed: int, chain: int, step: int, logits, order, eps: float):
 
 
 def run_chain_learned(table, K, seed, chain, iters, prm, mu, sd, prior_nats_m, stats, eps=0.1, target=0,
-                      round_f32=True):
+                      round_f32=True, topk: int = 0):
     table = np.ascontiguousarray(table, dtype=np.float64)
     n = table.shape[0]
     prm = np.ascontiguousarray(prm, dtype=np.float64)
@@ -342,8 +349,10 @@ def run_chain_learned(table, K, seed, chain, iters, prm, mu, sd, prior_nats_m, s
     bg = np.zeros(n, dtype=np.uint64)
     bs = ctypes.c_double()
     na = ctypes.c_int64()
+    tg, ts, tc = _topk_buffers(n, topk)
     lib().orc_run_chain_learned(_p(table), n, K, seed, chain, iters, target, int(round_f32), _p(prm), _p(mu), _p(sd),
                                 None if pn is None else _p(pn), _p(st), eps, _p(order), _p(trace), _p(acc), _p(bg),
-                                ctypes.byref(bs), ctypes.byref(na))
-    return dict(order=order, trace=trace, acc=acc[:iters], best_graph=bg, best_score=bs.value, accepted=na.value)
+                                ctypes.byref(bs), ctypes.byref(na), topk, _p(tg), _p(ts), ctypes.byref(tc))
+    return dict(order=order, trace=trace, acc=acc[:iters], best_graph=bg, best_score=bs.value, accepted=na.value,
+                top_graphs=tg[:tc.value], top_scores=ts[:tc.value])
 

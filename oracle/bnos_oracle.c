@@ -430,6 +430,32 @@ double orc_accept_uniform(uint64_t seed, uint64_t chain, uint64_t step)
 /* ------------------------------------------------------------------ */
 
 /*
+ * Record of the k best distinct graphs seen by a chain (Sec. III.C keeps a
+ * number of best graphs): offered the greedy graph of the initial order and of
+ * every accepted order.  Kept in decreasing order of score; a graph equal to a
+ * recorded one is not added again; among equal scores the earlier record stays
+ * ahead; when full, a new graph enters only with a score strictly above the
+ * last one, which then drops out.  graphs [k][n], scores [k].
+ */
+void orc_topk_offer(int n, int k, uint64_t *graphs, double *scores, int32_t *count, const uint64_t *g, double s)
+{
+    int cnt = *count;
+    for (int r = 0; r < cnt; ++r)
+        if (memcmp(graphs + (size_t)r * n, g, sizeof(uint64_t) * (size_t)n) == 0) return;
+    int pos = 0;
+    while (pos < cnt && scores[pos] >= s) ++pos;
+    if (pos >= k) return;
+    int last = cnt < k ? cnt : k - 1;
+    for (int r = last; r > pos; --r) {
+        memcpy(graphs + (size_t)r * n, graphs + (size_t)(r - 1) * n, sizeof(uint64_t) * (size_t)n);
+        scores[r] = scores[r - 1];
+    }
+    memcpy(graphs + (size_t)pos * n, g, sizeof(uint64_t) * (size_t)n);
+    scores[pos] = s;
+    if (cnt < k) *count = cnt + 1;
+}
+
+/*
  * One chain of `iters` iterations on a rank-indexed table.
  *   target 0: the order score is the log-sum-exp score; 1: the max score of
  *   Eq. (6).  An iteration (t = 1..iters) proposes a swap of two distinct
@@ -439,12 +465,14 @@ double orc_accept_uniform(uint64_t seed, uint64_t chain, uint64_t step)
  *   larger.
  * Outputs: final order (order_out[n]); trace[t] = target score of the current
  * order after iteration t (trace[0] = initial); acc[t-1] = 1 if accepted;
- * best graph (parent mask per node id) and its score; accepted count.
+ * best graph (parent mask per node id) and its score; accepted count; with
+ * topk > 0 the record of the topk best distinct graphs (orc_topk_offer).
  */
 void orc_run_chain(const double *table, int n, int K, uint64_t seed, uint64_t chain,
                    int64_t iters, int target, int round_f32,
                    int32_t *order_out, double *trace, uint8_t *acc,
-                   uint64_t *best_graph, double *best_score, int64_t *accepted)
+                   uint64_t *best_graph, double *best_score, int64_t *accepted,
+                   int topk, uint64_t *top_graphs, double *top_scores, int32_t *top_count)
 {
     int32_t *cur = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     int32_t *prop = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
@@ -454,6 +482,10 @@ void orc_run_chain(const double *table, int n, int K, uint64_t seed, uint64_t ch
     orc_score_order(table, n, K, cur, round_f32, &l, &m, best_graph, NULL, NULL, NULL);
     double cur_score = target == 0 ? l : m;
     *best_score = m;
+    if (topk > 0) {
+        *top_count = 0;
+        orc_topk_offer(n, topk, top_graphs, top_scores, top_count, best_graph, m);
+    }
     int64_t nacc = 0;
     if (trace) trace[0] = cur_score;
     for (int64_t t = 1; t <= iters; ++t) {
@@ -474,6 +506,7 @@ void orc_run_chain(const double *table, int n, int K, uint64_t seed, uint64_t ch
                 *best_score = pm;
                 memcpy(best_graph, g, sizeof(uint64_t) * (size_t)n);
             }
+            if (topk > 0) orc_topk_offer(n, topk, top_graphs, top_scores, top_count, g, pm);
         }
         if (acc) acc[t - 1] = (uint8_t)ok;
         if (trace) trace[t] = cur_score;
@@ -702,7 +735,8 @@ void orc_run_chain_learned(const double *table, int n, int K, uint64_t seed, uin
                            int target, int round_f32, const double *prm, const double *mu, const double *sd,
                            const double *prior_nats, const double *stats, double eps,
                            int32_t *order_out, double *trace, uint8_t *acc, uint64_t *best_graph,
-                           double *best_score, int64_t *accepted)
+                           double *best_score, int64_t *accepted,
+                           int topk, uint64_t *top_graphs, double *top_scores, int32_t *top_count)
 {
     int32_t *cur = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     int32_t *prop = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
@@ -713,6 +747,10 @@ void orc_run_chain_learned(const double *table, int n, int K, uint64_t seed, uin
     orc_score_order(table, n, K, cur, round_f32, &l, &m, best_graph, nl, nb, ns);
     double cur_score = target == 0 ? l : m;
     *best_score = m;
+    if (topk > 0) {
+        *top_count = 0;
+        orc_topk_offer(n, topk, top_graphs, top_scores, top_count, best_graph, m);
+    }
     orc_features(n, cur, nb, ns, prior_nats, stats, f);
     for (int k = 0; k < n * ORC_F; ++k) z[k] = (f[k] - mu[k % ORC_F]) / sd[k % ORC_F];
     orc_mlp_forward(prm, n, z, lc, NULL, NULL);
@@ -743,6 +781,7 @@ void orc_run_chain_learned(const double *table, int n, int K, uint64_t seed, uin
                 *best_score = pm;
                 memcpy(best_graph, g, sizeof(uint64_t) * (size_t)n);
             }
+            if (topk > 0) orc_topk_offer(n, topk, top_graphs, top_scores, top_count, g, pm);
         }
         if (acc) acc[t - 1] = (uint8_t)ok;
         if (trace) trace[t] = cur_score;

@@ -38,13 +38,14 @@ class ChainCfg(ctypes.Structure):
     _fields_ = [("chains", ctypes.c_int32), ("target", ctypes.c_int32), ("iterations", ctypes.c_int64),
                 ("first_iteration", ctypes.c_int64), ("seed", ctypes.c_uint64), ("chain_offset", ctypes.c_int64),
                 ("trace_every", ctypes.c_int32), ("sweep_len", ctypes.c_int32), ("proposal", ctypes.c_int32),
-                ("eps", ctypes.c_float), ("mlp", P), ("reserved", ctypes.c_int32 * 4)]
+                ("eps", ctypes.c_float), ("mlp", P), ("topk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class ChainState(ctypes.Structure):
     _fields_ = [("orders", P), ("scores", P), ("best_graphs", P), ("best_scores", P), ("accepted", P),
                 ("trace", P), ("accept_flags", P), ("harvest_feats", P), ("harvest_pairs", P),
-                ("harvest_count", P), ("harvest_cap", ctypes.c_int64)]
+                ("harvest_count", P), ("harvest_cap", ctypes.c_int64), ("top_graphs", P), ("top_scores", P),
+                ("top_count", P)]
 
 
 _SIGS = {
@@ -189,7 +190,7 @@ class Table:
         return out
 
     def new_chain_state(self, chains: int, iterations: int, trace_every: int = 1, flags: bool = False,
-                        device=None, harvest_cap: int = 0):
+                        device=None, harvest_cap: int = 0, topk: int = 0):
         """Device tensors holding the state of `chains` chains (see bnos_chain_state)."""
         import torch
         dev = device or torch.device("cuda")
@@ -208,6 +209,10 @@ class Table:
             st["harvest_feats"] = torch.zeros((chains, harvest_cap, n, 8), dtype=torch.float32, device=dev)
             st["harvest_pairs"] = torch.zeros((chains, harvest_cap, 2), dtype=torch.int32, device=dev)
             st["harvest_count"] = torch.zeros(chains, dtype=torch.int64, device=dev)
+        if topk > 0:
+            st["top_graphs"] = torch.zeros((chains, topk, n), dtype=torch.int64, device=dev)
+            st["top_scores"] = torch.zeros((chains, topk), dtype=torch.float64, device=dev)
+            st["top_count"] = torch.zeros(chains, dtype=torch.int32, device=dev)
         return st
 
     def run_chains(self, state: dict, iterations: int, seed: int, target: int = 0, first_iteration: int = 0,
@@ -217,6 +222,7 @@ class Table:
         chains = int(state["orders"].shape[0])
         cfg = _chain_cfg(chains, iterations, seed, target, first_iteration, trace_every, chain_offset, sweep_len,
                          mlp, eps)
+        cfg.topk = _state_topk([state])
         st = _chain_state(state, iterations, trace_every)
         _check(_lib.bnos_run_chains(self._h, ctypes.byref(cfg), ctypes.byref(st), _stream(stream)))
 
@@ -328,10 +334,18 @@ def _chain_cfg(chains, iterations, seed, target, first_iteration, trace_every, c
     return cfg
 
 
+def _state_topk(states) -> int:
+    """Records per chain of the best-graph record the states carry (0 = none)."""
+    ks = {int(s["top_graphs"].shape[1]) if s.get("top_graphs") is not None else 0 for s in states}
+    if len(ks) != 1:
+        raise ValueError("every state needs the same best-graph record size")
+    return ks.pop()
+
+
 def _chain_state(state: dict, iterations: int, trace_every: int) -> ChainState:
     st = ChainState()
     for k in ("orders", "scores", "best_graphs", "best_scores", "accepted", "trace", "accept_flags",
-              "harvest_feats", "harvest_pairs", "harvest_count"):
+              "harvest_feats", "harvest_pairs", "harvest_count", "top_graphs", "top_scores", "top_count"):
         v = state.get(k)
         setattr(st, k, None if v is None else v.data_ptr())
     if state.get("harvest_feats") is not None:
@@ -352,6 +366,7 @@ def run_chains_multi(tables, states, iterations: int, seed: int, target: int = 0
         raise ValueError("every table needs the same number of chains")
     cfg = _chain_cfg(chains, iterations, seed, target, first_iteration, trace_every, chain_offset, sweep_len,
                      mlp, eps)
+    cfg.topk = _state_topk(states)
     hs = (P * T)(*[t.handle.value for t in tables])
     sts = (ChainState * T)(*[_chain_state(s, iterations, trace_every) for s in states])
     _check(_lib.bnos_run_chains_multi(hs, T, ctypes.byref(cfg), sts, _stream(stream)))

@@ -93,6 +93,11 @@ struct ChainView {
     int32_t *hv_pair;          // [C][hv_cap][2]
     int64_t *hv_count;         // [C]
     int64_t hv_cap;
+    // record of the best distinct graphs
+    int topk;                  // 0 = off
+    uint64_t *top_graph;       // [C][topk][n]
+    double *top_score;         // [C][topk]
+    int32_t *top_count;        // [C]
 };
 
 __device__ __forceinline__ uint64_t all_nodes(int n) { return n == 64 ? ~0ull : ((1ull << n) - 1ull); }
@@ -121,6 +126,7 @@ __global__ __launch_bounds__(64) void k_chain_init(const ChainView *__restrict__
             }
             for (int p = 0; p < n; ++p) H.prop[(int64_t)c * n + p] = ord[p];
             H.accepted[c] = 0;
+            if (H.topk > 0) H.top_count[c] = 0;
         }
     } else {
         if (lane < n) H.prop[(int64_t)c * n + lane] = H.cur[(int64_t)c * n + lane];
@@ -166,6 +172,41 @@ __global__ __launch_bounds__(kListThreads) void k_worklist(const ChainView *__re
         __syncthreads();
     }
     if (threadIdx.x == 0) H.wl_count[node] = s_base;
+}
+
+// Offer graph g (lane i holds node i's parent mask) with max score M to chain
+// c's record of best distinct graphs (wave 0, all lanes).  Records are sorted
+// by decreasing score; the new graph goes after every record scoring >= M.  An
+// identical graph has the identical score (the same FP32 entries summed in the
+// same order), so only records of equal score are compared for duplicates.
+__device__ __forceinline__ void topk_offer(const ChainView &H, int c, int n, int lane, double M, uint64_t g)
+{
+    const int K = H.topk;
+    uint64_t *G = H.top_graph + (int64_t)c * K * n;
+    double *Sc = H.top_score + (int64_t)c * K;
+    const int cnt = H.top_count[c];
+    const double mine = lane < cnt ? Sc[lane] : 0.0;
+    const int pos = __popcll(__ballot(lane < cnt && mine >= M));
+    if (pos >= K) return;
+    uint64_t eq = __ballot(lane < cnt && mine == M);
+    bool dup = false;
+    while (eq) {
+        const int r = __builtin_ctzll(eq);
+        eq &= eq - 1;
+        const uint64_t x = lane < n ? G[(int64_t)r * n + lane] : 0ull;
+        dup = dup || (__ballot(lane < n && x != g) == 0ull);
+    }
+    if (dup) return;
+    const int last = cnt < K ? cnt : K - 1;
+    if (lane < n) {
+        for (int r = last; r > pos; --r) G[(int64_t)r * n + lane] = G[(int64_t)(r - 1) * n + lane];
+        G[(int64_t)pos * n + lane] = g;
+    }
+    const bool shift = lane > pos && lane <= last;
+    const double prev = shift ? Sc[lane - 1] : 0.0;
+    if (shift) Sc[lane] = prev;
+    if (lane == pos) Sc[pos] = M;
+    if (lane == 0 && cnt < K) H.top_count[c] = cnt + 1;
 }
 
 // Block per chain: merge the chunk partials of the window nodes, combine with
@@ -336,6 +377,8 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(const TabView *
         }
     }
     if (imp && lane < n) H.best_graph[row + lane] = in ? s_bm[lane] : H.node_best[row + lane];
+    if (H.topk > 0 && acc && !(t == H.t_first && H.t_first > 0))
+        topk_offer(H, c, n, lane, M, lane < n ? (in ? s_bm[lane] : H.node_best[row + lane]) : 0ull);
     const int64_t t1 = t + 1;
     const bool next = t1 <= H.t_last;
     int a = 0, b = 0;
@@ -423,9 +466,10 @@ bnos_status validate_cfg(const bnos_chain_cfg *cfg)
     if (cfg->trace_every < 1) { set_error("trace_every must be >= 1"); return BNOS_E_RANGE; }
     if (cfg->sweep_len < 0) { set_error("sweep_len < 0"); return BNOS_E_RANGE; }
     if (cfg->chain_offset < 0) { set_error("chain_offset < 0"); return BNOS_E_RANGE; }
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 3; ++r)
         if (cfg->reserved[r] != 0) { set_error("cfg.reserved must be zero"); return BNOS_E_INVALID; }
     if (cfg->proposal != 0 && cfg->proposal != 1) { set_error("proposal must be 0 or 1"); return BNOS_E_INVALID; }
+    if (cfg->topk < 0 || cfg->topk > 64) { set_error("topk outside [0, 64]"); return BNOS_E_RANGE; }
     if (cfg->proposal == 1) {
         if (!mlp_handle_live(cfg->mlp)) { set_error("learned proposal needs a live network handle"); return BNOS_E_STATE; }
         if (!(cfg->eps >= 0.f && cfg->eps <= 1.f)) { set_error("eps outside [0, 1]"); return BNOS_E_RANGE; }
@@ -460,6 +504,10 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
             return BNOS_E_INVALID;
         }
         if (cfg->proposal == 1 && tabs[k]->n > 64) { set_error("n > 64"); return BNOS_E_RANGE; }
+        if (cfg->topk > 0 && (!st.top_graphs || !st.top_scores || !st.top_count)) {
+            set_error("topk > 0 needs top_graphs, top_scores and top_count");
+            return BNOS_E_INVALID;
+        }
     }
     // scoring steps: the adoption of the starting order (fresh: iteration 0; resume: the
     // saved order, re-scored to rebuild the per-node caches) and one per iteration
@@ -538,6 +586,10 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
         H.hv_pair = st.harvest_pairs;
         H.hv_count = st.harvest_count;
         H.hv_cap = st.harvest_feats ? st.harvest_cap : 0;
+        H.topk = cfg->topk;
+        H.top_graph = st.top_graphs;
+        H.top_score = st.top_scores;
+        H.top_count = st.top_count;
         TabView &V = tv[k];
         V.masks = t->d_masks;
         V.scores = t->d_scores;

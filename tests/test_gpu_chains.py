@@ -29,8 +29,8 @@ def bnos():
     return b
 
 
-def gpu_chains(table, chains, iters, seed, target=0, sweep_len=0, chain_offset=0):
-    st = table.new_chain_state(chains, iters, trace_every=1, flags=True)
+def gpu_chains(table, chains, iters, seed, target=0, sweep_len=0, chain_offset=0, topk=0):
+    st = table.new_chain_state(chains, iters, trace_every=1, flags=True, topk=topk)
     table.run_chains(st, iters, seed, target=target, sweep_len=sweep_len, chain_offset=chain_offset)
     torch.cuda.synchronize()
     return {k: (v.cpu().numpy() if v is not None else None) for k, v in st.items()}
@@ -52,12 +52,35 @@ def oracle_replay_delta(orc, K, seed, chain, t, res, target):
     return math.log(oracle.accept_uniform(seed, chain, t)), new - res["trace"][t - 1]
 
 
-def compare_chains(g, orc, K, seed, iters, target, chain_offset=0):
+def compare_topk(gg, gs, gc, og, os_, full_record):
+    """GPU best-graph record vs the oracle's: equal scores (REL) position by
+    position; equal graphs, except that records whose scores are near-tied (the
+    two sides sum FP32 scores that differ in the last bits) may swap places
+    within their tie group, and a tie group at the cut of a full record may
+    hold different members."""
+    cnt = int(gc)
+    assert cnt == len(os_)
+    np.testing.assert_allclose(gs[:cnt], os_, rtol=REL)
+    tol = 1e-4 + REL * np.abs(os_)
+    r = 0
+    while r < cnt:
+        e = r
+        while e + 1 < cnt and abs(os_[e + 1] - os_[e]) <= tol[e]:
+            e += 1
+        at_cut = full_record and e == cnt - 1
+        if not at_cut:
+            a = sorted(tuple(int(x) for x in gg[q].view(np.uint64)) for q in range(r, e + 1))
+            b = sorted(tuple(int(x) for x in og[q]) for q in range(r, e + 1))
+            assert a == b, (r, e)
+        r = e + 1
+
+
+def compare_chains(g, orc, K, seed, iters, target, chain_offset=0, topk=0):
     full = 0
     C = g["orders"].shape[0]
     for c in range(C):
         chain = chain_offset + c
-        res = oracle.run_chain(orc, K, seed, chain, iters, target=target, round_f32=True)
+        res = oracle.run_chain(orc, K, seed, chain, iters, target=target, round_f32=True, topk=topk)
         flags = g["accept_flags"][c, :iters].astype(bool)
         mism = np.nonzero(flags != res["acc"].astype(bool))[0]
         if len(mism):
@@ -73,6 +96,11 @@ def compare_chains(g, orc, K, seed, iters, target, chain_offset=0):
         assert abs(g["best_scores"][c] - res["best_score"]) <= REL * max(1.0, abs(res["best_score"]))
         assert int(g["accepted"][c]) == res["accepted"]
         assert abs(g["scores"][c] - res["trace"][-1]) <= REL * max(1.0, abs(res["trace"][-1]))
+        if topk:
+            compare_topk(g["top_graphs"][c], g["top_scores"][c], g["top_count"][c], res["top_graphs"],
+                         res["top_scores"], int(g["top_count"][c]) == topk)
+            assert [int(x) for x in g["top_graphs"][c, 0].view(np.uint64)] == \
+                [int(x) for x in g["best_graphs"][c].view(np.uint64)]
     return full
 
 
@@ -110,6 +138,35 @@ def test_chains_match_oracle_prior20_max_target(bnos, prior20):
     g = gpu_chains(t, C, iters, seed=101, target=1, chain_offset=7)
     full = compare_chains(g, orc, w.K, 101, iters, 1, chain_offset=7)
     assert full >= C - 1
+
+
+@pytest.mark.parametrize("wname,topk,target", [("tiny8", 6, 0), ("prior20", 10, 1), ("prior20", 64, 0)])
+def test_best_graph_record_matches_oracle(bnos, wname, topk, target, request):
+    w, t, orc = request.getfixturevalue(wname)
+    iters, C = (1500, 8) if wname == "tiny8" else (400, 5)
+    g = gpu_chains(t, C, iters, seed=130 + topk, target=target, topk=topk)
+    full = compare_chains(g, orc, w.K, 130 + topk, iters, target, topk=topk)
+    assert full >= C - 1
+    assert g["top_count"].max() >= min(topk, 5)
+    # records are distinct and sorted
+    for c in range(C):
+        k = int(g["top_count"][c])
+        sc = g["top_scores"][c, :k]
+        assert np.all(np.diff(sc) <= 0)
+        assert len({tuple(r) for r in g["top_graphs"][c, :k].tolist()}) == k
+
+
+def test_best_graph_record_resumes(bnos, tiny8):
+    w, t, orc = tiny8
+    C, topk = 6, 5
+    ref = gpu_chains(t, C, 300, seed=9, topk=topk)
+    st = t.new_chain_state(C, 100, trace_every=1, topk=topk)
+    t.run_chains(st, 100, 9)
+    st["trace"] = torch.zeros((C, 201), dtype=torch.float64, device="cuda")
+    t.run_chains(st, 200, 9, first_iteration=100)
+    torch.cuda.synchronize()
+    for k in ("top_graphs", "top_scores", "top_count", "best_graphs"):
+        assert np.array_equal(st[k].cpu().numpy(), ref[k]), k
 
 
 def test_chains_prior20_lse(bnos, prior20):
@@ -177,6 +234,9 @@ def test_chain_validation(bnos, tiny8):
     assert e.value.status == bnos.E_INVALID
     with pytest.raises(bnos.BnosError) as e:
         t.run_chains(st, -1, 1)
+    assert e.value.status == bnos.E_RANGE
+    with pytest.raises(bnos.BnosError) as e:
+        t.run_chains(t.new_chain_state(2, 10, topk=65), 10, 1)
     assert e.value.status == bnos.E_RANGE
 
 

@@ -419,3 +419,44 @@ def test_row_and_node_scoring_agree_with_full_table():
         d = oracle.score_node_direct(data, arities, K, v, pred)
         assert d == (l, b, bm, s)
         pred |= 1 << v
+
+
+@pytest.mark.parametrize("topk,target", [(4, 0), (8, 1), (1, 0)])
+def test_topk_record_equals_brute_force_over_visited_orders(topk, target):
+    # the record = the topk best distinct exhaustive-best DAGs of the orders the
+    # chain visited (initial order and every accepted one), earlier first on ties;
+    # a weak prior breaks the exact ties of Markov-equivalent graphs
+    n, K = 5, 2
+    net = datagen.random_network(n, 60, (2, 3), 3, 3)
+    prior = np.random.default_rng(78).uniform(-0.2, 0.2, size=(n, n)).astype(np.float32)
+    table = oracle.build_table(net.data, net.arities, K, prior=prior)
+    dags = brute.enumerate_dags(n, K)
+    local = {}
+    for i in range(n):
+        for m in set(int(v) for v in dags[:, i]):
+            local[(i, m)] = oracle.local_score(net.data, net.arities, i, m, prior=prior)
+    gs = np.array([sum(local[(i, int(row[i]))] for i in range(n)) for row in dags])
+    seed, chain, iters = 31, 2, 400
+    res = oracle.run_chain(table, K, seed, chain, iters, target=target, round_f32=False, topk=topk)
+    cur = list(oracle.initial_order(seed, chain, n))
+    visited = [tuple(cur)]
+    for t in range(1, iters + 1):
+        if res["acc"][t - 1]:
+            a, b = oracle.swap_pair(seed, chain, n, t)
+            cur[a], cur[b] = cur[b], cur[a]
+            visited.append(tuple(cur))
+    seen = {}
+    for k, order in enumerate(visited):
+        ok = brute.consistent_with(dags, order)
+        j = int(np.argmax(np.where(ok, gs, -np.inf)))
+        g = tuple(int(v) for v in dags[j])
+        if g not in seen:
+            seen[g] = (float(gs[j]), k)
+    assert len(seen) > 8                      # the record overflows: eviction is exercised
+    want = sorted(seen.items(), key=lambda kv: (-kv[1][0], kv[1][1]))[:topk]
+    got_g = [tuple(int(v) for v in row) for row in res["top_graphs"]]
+    assert got_g == [g for g, _ in want]
+    np.testing.assert_allclose(res["top_scores"], [s for _, (s, _) in want], rtol=1e-12)
+    # the first record is the best-graph record
+    assert got_g[0] == tuple(int(v) for v in res["best_graph"])
+    assert res["top_scores"][0] == res["best_score"]
