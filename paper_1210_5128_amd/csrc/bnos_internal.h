@@ -70,11 +70,16 @@ struct TableT {
 
     int64_t device_bytes() const;
     static int bucket(int B) { return B >= 16 ? 4 : (B >= 8 ? 3 : (B >= 4 ? 2 : (B >= 2 ? 1 : 0))); }
-    // chunk length (entries) and chunks per node used for a launch of B orders
+    // Chunk length (entries) and chunks per node used for a launch of B orders:
+    // the autotuned length of B's bucket; else for 8+ orders the longest chunk
+    // (a block's fixed cost -- tile summaries, predecessor masks, the per-order
+    // reductions -- is then spread over the most entries, and the orders
+    // already fill the grid); else the length chosen at build time.
     int chunk_entries_for(int B) const
     {
         const int cs = tuned_cs[bucket(B)];
-        return cs > 0 ? cs * 1024 : chunk_entries;
+        if (cs > 0) return cs * 1024;
+        return B >= 8 ? pad_steps * 1024 : chunk_entries;
     }
     int chunks_for(int B) const { return (int)(S_pad / chunk_entries_for(B)); }
     int64_t workspace_bytes_for(int B) const
