@@ -280,11 +280,11 @@ def main():
                          "one alone keeps a profiler's per-kernel figures unmixed")
     ap.add_argument("--chains", type=int, default=256, help="batched chains on the mixed40 table (0 = skip)")
     ap.add_argument("--chain-iters", type=int, default=20000)
-    ap.add_argument("--learned", type=int, default=0, metavar="C",
-                    help="also run the learned-proposal comparison with C chains on the mixed60 table (0 = skip)")
-    ap.add_argument("--learned-iters", type=int, default=2000, help="iterations of each compared run")
+    ap.add_argument("--learned", type=int, default=256, metavar="C",
+                    help="learned-proposal comparison with C chains on the mixed60 table (0 = skip)")
+    ap.add_argument("--learned-iters", type=int, default=4000, help="iterations of each compared run")
     ap.add_argument("--learned-moves", type=int, default=1000000, help="accepted moves harvested for training")
-    ap.add_argument("--learned-epochs", type=int, default=4)
+    ap.add_argument("--learned-epochs", type=int, default=16)
     ap.add_argument("--learned-workload", default="mixed60")
     ap.add_argument("--uneven", type=int, default=0, metavar="D",
                     help="also run the uneven family: D datasets x 64 chains in one launch vs one at a time")

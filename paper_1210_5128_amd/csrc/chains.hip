@@ -215,7 +215,9 @@ __device__ __forceinline__ void topk_offer(const ChainView &H, int c, int n, int
 // proposal ratio q(pair|new)/q(pair|old) for the learned proposal), update the
 // caches and the best-graph record, harvest the accepted move, and draw the
 // next proposal.
-__global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(const TabView *__restrict__ tviews,
+constexpr int kStepWaves = 16;
+
+__global__ __launch_bounds__(kStepWaves * 64) void k_chain_step(const TabView *__restrict__ tviews,
                                                                  const ChainView *__restrict__ views,
                                                                  const int64_t *__restrict__ chain_base, int T)
 {
@@ -225,6 +227,7 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(const TabView *
     __shared__ int s_cnt;
     __shared__ float s_feat[64 * kF];
     __shared__ MlpLds s_mlp;
+    __shared__ MergeLds s_merge;
     const int k = find_segment(chain_base, T, (int64_t)blockIdx.x);
     const ChainView &H = views[k];
     const TabView &V = tviews[k];
@@ -250,42 +253,16 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_chain_step(const TabView *
     }
     __syncthreads();
     const int cnt = s_cnt;
-    Acc r[kMergeNodesPerWave];
-#pragma unroll
-    for (int q = 0; q < kMergeNodesPerWave; ++q) {
-        const int w = wave + kMergeWaves * q;
-        acc_init(r[q]);
-        if (w < cnt && lane < chunks) r[q] = load_partial(V.part + ((int64_t)c * n + s_nodes[w]) * chunks + lane);
-    }
-#pragma unroll
-    for (int q = 0; q < kMergeNodesPerWave; ++q) {
-        const int w = wave + kMergeWaves * q;
-        if (w >= cnt) break;
-        const int i = s_nodes[w];
-        const Partial *pp = V.part + ((int64_t)c * n + i) * chunks;
-        for (int cc = lane + 64; cc < chunks; cc += 64) acc_merge(r[q], load_partial(pp + cc));
-    }
-    acc_wave_reduce_n<kMergeNodesPerWave>(r, lane);
     {
-        // all lanes hold the wave's node states; lane q finishes window node wave + 16q
-        float fm = r[0].m, fs = r[0].s, fb = r[0].best, fsec = r[0].sec;
-        uint64_t fbm = r[0].bm;
-#pragma unroll
-        for (int q = 1; q < kMergeNodesPerWave; ++q) {
-            const bool mine = lane == q;
-            fm = mine ? r[q].m : fm;
-            fs = mine ? r[q].s : fs;
-            fb = mine ? r[q].best : fb;
-            fsec = mine ? r[q].sec : fsec;
-            fbm = mine ? r[q].bm : fbm;
-        }
-        const int w = wave + kMergeWaves * lane;
-        if (lane < kMergeNodesPerWave && w < cnt) {
-            const int i = s_nodes[w];
-            s_l[i] = (double)fm + log((double)fs);
-            s_b[i] = (double)fb;
-            s_s[i] = (double)fsec;
-            s_bm[i] = fbm;
+        // lane j of the merging waves takes window node s_nodes[j]
+        const Acc r = merge_nodes(V.part + (int64_t)c * chunks * n, n, chunks, lane < cnt ? s_nodes[lane] : -1,
+                                  s_merge);
+        if (wave == 0 && lane < cnt) {
+            const int i = s_nodes[lane];
+            s_l[i] = (double)r.m + log((double)r.s);
+            s_b[i] = (double)r.best;
+            s_s[i] = (double)r.sec;
+            s_bm[i] = r.bm;
         }
     }
     __syncthreads();
@@ -640,7 +617,7 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
         else if (bt == 4) hipLaunchKernelGGL(k_score_multi<4>, grid, dim3(kScoreThreads), 0, q, d_tv, d_blk, T);
         else if (bt == 2) hipLaunchKernelGGL(k_score_multi<2>, grid, dim3(kScoreThreads), 0, q, d_tv, d_blk, T);
         else hipLaunchKernelGGL(k_score_multi<1>, grid, dim3(kScoreThreads), 0, q, d_tv, d_blk, T);
-        hipLaunchKernelGGL(k_chain_step, dim3(total_chains), dim3(kMergeWaves * 64), 0, q, d_tv, d_cv, d_chain, T);
+        hipLaunchKernelGGL(k_chain_step, dim3(total_chains), dim3(kStepWaves * 64), 0, q, d_tv, d_cv, d_chain, T);
         return hipGetLastError();
     };
     const int64_t sweep = cfg->sweep_len > 0 ? cfg->sweep_len : 32;

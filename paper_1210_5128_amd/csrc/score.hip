@@ -17,11 +17,11 @@ namespace bnos {
 // One block per order: merge its chunk partials and write the per-order sums.
 __global__ __launch_bounds__(kMergeWaves * 64) void k_merge(ScoreArgs A)
 {
-    __shared__ double s_l[64], s_b[64];
+    __shared__ MergeLds L;
     const int b = blockIdx.x;
     bool valid;
     double l, m;
-    merge_block(A, b, s_l, s_b, valid, l, m);
+    merge_block(A, b, L, valid, l, m);
     if (threadIdx.x == 0) {
         A.lse[b] = valid ? l : NAN;
         A.maxs[b] = valid ? m : NAN;

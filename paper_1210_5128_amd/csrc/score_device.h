@@ -101,36 +101,6 @@ __device__ __forceinline__ void acc_wave_reduce(Acc &a, int lane)
     }
 }
 
-// Butterfly merge of R independent states at once (their shuffles and merges
-// interleave, hiding the cross-lane latency); same pairing rule as above.
-template <int R>
-__device__ __forceinline__ void acc_wave_reduce_n(Acc (&a)[R], int lane)
-{
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        Acc o[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) o[r] = acc_shfl_xor(a[r], off);
-        const bool upper = (lane & off) != 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            Acc lo, hi;
-            lo.m = upper ? o[r].m : a[r].m;
-            hi.m = upper ? a[r].m : o[r].m;
-            lo.s = upper ? o[r].s : a[r].s;
-            hi.s = upper ? a[r].s : o[r].s;
-            lo.best = upper ? o[r].best : a[r].best;
-            hi.best = upper ? a[r].best : o[r].best;
-            lo.sec = upper ? o[r].sec : a[r].sec;
-            hi.sec = upper ? a[r].sec : o[r].sec;
-            lo.bm = upper ? o[r].bm : a[r].bm;
-            hi.bm = upper ? a[r].bm : o[r].bm;
-            acc_merge(lo, hi);
-            a[r] = lo;
-        }
-    }
-}
-
 __device__ __forceinline__ double wave_sum_f64(double v, int lane)
 {
     // fixed butterfly: the lower lane's value is the left operand
@@ -180,7 +150,7 @@ struct ScoreArgs {
     int chunks, chunk_entries;
     const int32_t *orders;
     int B, n;
-    Partial *part;          // [B][n][chunks]
+    Partial *part;          // [B][chunks][n]
     double *lse, *maxs;
     uint64_t *best;
     double *node_lse;
@@ -200,7 +170,7 @@ struct TabView {
     int chunks, chunk_entries, n;
     int B;                      // orders (chains) of this table; row stride of wl_list
     const int32_t *orders;      // [B][n]
-    Partial *part;              // [B][n][chunks]
+    Partial *part;              // [B][chunks][n]
     const int32_t *wl_count;    // [n] or null
     const int32_t *wl_list;     // [n][B]
     const uint64_t *tand;       // [n * S_pad / 256] AND of each 256-entry tile's masks, or null (no skipping)
@@ -351,7 +321,7 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
             p.best = r.best;
             p.second = r.sec;
             p.bmask = r.bm;
-            V.part[((int64_t)ob * n + node) * V.chunks + chunk] = p;
+            V.part[((int64_t)ob * V.chunks + chunk) * n + node] = p;
         }
     }
 }
@@ -453,8 +423,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_multi(const TabView *__
     score_block<BT>(V, node, chunk, blockIdx.y);
 }
 
-constexpr int kMergeWaves = 16;
-constexpr int kMergeNodesPerWave = 4;   // 16 waves x 4 nodes covers n <= 64
+constexpr int kMergeWaves = 8;
 
 __device__ __forceinline__ Acc load_partial(const Partial *p)
 {
@@ -467,66 +436,96 @@ __device__ __forceinline__ Acc load_partial(const Partial *p)
     return a;
 }
 
-// Merge of one order's chunk partials, run by a whole block of kMergeWaves
-// wavefronts.  Wave w merges nodes w, w+16, w+32, w+48 (lanes over chunks,
-// every node's first partial loaded before any merging so the loads overlap,
-// then a fixed butterfly); lanes 0-3 form LSE_i = m + ln s in FP64 for the
-// four nodes at once and write the node outputs.  Wave 0 then sums the per-node terms in FP64 with a fixed
-// butterfly; the sums are valid in lane 0 of wave 0.
-__device__ __forceinline__ void merge_block(const ScoreArgs &A, int b, double *s_l, double *s_b,
-                                            bool &valid, double &lse_out, double &max_out)
+// LDS for the cross-wave step of merge_nodes.
+struct MergeLds {
+    float m[kMergeWaves][64], s[kMergeWaves][64], best[kMergeWaves][64], sec[kMergeWaves][64];
+    uint64_t bm[kMergeWaves][64];
+};
+
+// Merge of one order's chunk partials (base: that order's [chunks][n] block),
+// node-parallel: lane j of every one of the first kMergeWaves wavefronts
+// takes node node_j (< 0: none) and folds the chunks wave, wave + W, ...
+// in increasing order; the waves' states are then combined through LDS in a
+// fixed tree (lower wave always the left operand).  The merged state of node
+// node_j is valid in lane j of wave 0.  All threads of the block must call it.
+__device__ __forceinline__ Acc merge_nodes(const Partial *__restrict__ base, int n, int chunks, int node_j,
+                                           MergeLds &L)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    Acc a;
+    acc_init(a);
+    if (wave < kMergeWaves && node_j >= 0) {
+        const Partial *p = base + node_j;
+        int c = wave;
+        // four loads in flight per step
+        for (; c + 3 * kMergeWaves < chunks; c += 4 * kMergeWaves) {
+            const Acc x0 = load_partial(p + (int64_t)c * n);
+            const Acc x1 = load_partial(p + (int64_t)(c + kMergeWaves) * n);
+            const Acc x2 = load_partial(p + (int64_t)(c + 2 * kMergeWaves) * n);
+            const Acc x3 = load_partial(p + (int64_t)(c + 3 * kMergeWaves) * n);
+            acc_merge(a, x0);
+            acc_merge(a, x1);
+            acc_merge(a, x2);
+            acc_merge(a, x3);
+        }
+        for (; c < chunks; c += kMergeWaves) acc_merge(a, load_partial(p + (int64_t)c * n));
+    }
+    if (wave < kMergeWaves) {
+        L.m[wave][lane] = a.m;
+        L.s[wave][lane] = a.s;
+        L.best[wave][lane] = a.best;
+        L.sec[wave][lane] = a.sec;
+        L.bm[wave][lane] = a.bm;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = kMergeWaves / 2; h >= 1; h >>= 1) {
+        if (wave < h) {
+            Acc o;
+            o.m = L.m[wave + h][lane];
+            o.s = L.s[wave + h][lane];
+            o.best = L.best[wave + h][lane];
+            o.sec = L.sec[wave + h][lane];
+            o.bm = L.bm[wave + h][lane];
+            acc_merge(a, o);
+            L.m[wave][lane] = a.m;
+            L.s[wave][lane] = a.s;
+            L.best[wave][lane] = a.best;
+            L.sec[wave][lane] = a.sec;
+            L.bm[wave][lane] = a.bm;
+        }
+        __syncthreads();
+    }
+    return a;
+}
+
+// Per-order merge (k_merge): node-parallel merge_nodes, then lane i of wave 0
+// forms LSE_i = m + ln s in FP64, writes the node outputs, and the wave sums
+// the per-node terms in FP64 with a fixed butterfly; the sums are valid in
+// lane 0 of wave 0.
+__device__ __forceinline__ void merge_block(const ScoreArgs &A, int b, MergeLds &L, bool &valid, double &lse_out,
+                                            double &max_out)
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int n = A.n;
-    const int chunks = A.chunks;
     (void)wave_pred(A.orders + (int64_t)b * n, n, 0, lane, valid);
-
-    Acc r[kMergeNodesPerWave];
-#pragma unroll
-    for (int k = 0; k < kMergeNodesPerWave; ++k) {
-        const int i = wave + kMergeWaves * k;
-        acc_init(r[k]);
-        if (i < n && lane < chunks) r[k] = load_partial(A.part + ((int64_t)b * n + i) * chunks + lane);
-    }
-#pragma unroll
-    for (int k = 0; k < kMergeNodesPerWave; ++k) {
-        const int i = wave + kMergeWaves * k;
-        if (i >= n) break;
-        const Partial *pp = A.part + ((int64_t)b * n + i) * chunks;
-        for (int c = lane + 64; c < chunks; c += 64) acc_merge(r[k], load_partial(pp + c));
-    }
-    acc_wave_reduce_n<kMergeNodesPerWave>(r, lane);   // nodes beyond n reduce identity states
-    // every lane now holds all of the wave's node states; lane k finishes node wave + 16k
-    float fm = r[0].m, fs = r[0].s, fb = r[0].best, fsec = r[0].sec;
-    uint64_t fbm = r[0].bm;
-#pragma unroll
-    for (int k = 1; k < kMergeNodesPerWave; ++k) {
-        const bool mine = lane == k;
-        fm = mine ? r[k].m : fm;
-        fs = mine ? r[k].s : fs;
-        fb = mine ? r[k].best : fb;
-        fsec = mine ? r[k].sec : fsec;
-        fbm = mine ? r[k].bm : fbm;
-    }
-    const int fi = wave + kMergeWaves * lane;
-    if (lane < kMergeNodesPerWave && fi < n) {
-        const double li = (double)fm + log((double)fs);
-        const int64_t o = (int64_t)b * n + fi;
-        s_l[fi] = li;
-        s_b[fi] = (double)fb;
-        A.best[o] = valid ? fbm : 0ull;
-        if (A.node_lse) A.node_lse[o] = valid ? li : NAN;
-        if (A.node_second) A.node_second[o] = valid ? fsec : NAN;
-    }
-    __syncthreads();
+    const Acc r = merge_nodes(A.part + (int64_t)b * A.chunks * n, n, A.chunks, lane < n ? lane : -1, L);
     lse_out = 0.0;
     max_out = 0.0;
     if (wave == 0) {
-        double l = (lane < n) ? s_l[lane] : 0.0;
-        double m = (lane < n) ? s_b[lane] : 0.0;
-        lse_out = wave_sum_f64(l, lane);
-        max_out = wave_sum_f64(m, lane);
+        double li = 0.0, mi = 0.0;
+        if (lane < n) {
+            li = (double)r.m + log((double)r.s);
+            mi = (double)r.best;
+            const int64_t o = (int64_t)b * n + lane;
+            A.best[o] = valid ? r.bm : 0ull;
+            if (A.node_lse) A.node_lse[o] = valid ? li : NAN;
+            if (A.node_second) A.node_second[o] = valid ? r.sec : NAN;
+        }
+        lse_out = wave_sum_f64(li, lane);
+        max_out = wave_sum_f64(mi, lane);
     }
 }
 
