@@ -76,29 +76,60 @@ __device__ __forceinline__ Acc acc_shfl_xor(const Acc &a, int off)
     return b;
 }
 
-// Butterfly merge over the 64 lanes.  In every pair the lower lane's state is
-// the left operand, so both lanes compute the same value and the result does
-// not depend on scheduling.
-__device__ __forceinline__ void acc_wave_reduce(Acc &a, int lane)
+// Select one of two states field by field (no dynamic struct copies).
+__device__ __forceinline__ Acc acc_sel(bool c, const Acc &x, const Acc &y)
 {
+    Acc r;
+    r.m = c ? x.m : y.m;
+    r.s = c ? x.s : y.s;
+    r.best = c ? x.best : y.best;
+    r.sec = c ? x.sec : y.sec;
+    r.bm = c ? x.bm : y.bm;
+    return r;
+}
+
+// Reduction of BT per-lane states over the 64 lanes of a wavefront, as a
+// reduce-scatter: while more than one state is left, lanes split by the next
+// high lane bit (32, 16, ...) keep one half of the states, receive the
+// partner's copy of that half and merge; then a plain butterfly over the
+// remaining low lane bits.  Every merge takes the lower lane's state as the
+// left operand, so the result does not depend on scheduling.  Returns the
+// lane's state; the full reduction of state j is held by the lanes whose top
+// log2(BT) bits equal j (e.g. lane j * 64 / BT).  Costs log2(BT) + 6 - log2(BT)
+// levels with BT - 1 + (6 - log2 BT) merges per lane, against 6 * BT for BT
+// separate butterflies.
+template <int BT>
+__device__ __forceinline__ Acc acc_wave_reduce_scatter(Acc (&a)[BT], int lane)
+{
+    constexpr int kLevels = BT >= 8 ? 3 : (BT >= 4 ? 2 : (BT >= 2 ? 1 : 0));
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        Acc o = acc_shfl_xor(a, off);
-        const bool upper = (lane & off) != 0;
-        Acc lo, hi;
-        lo.m = upper ? o.m : a.m;
-        hi.m = upper ? a.m : o.m;
-        lo.s = upper ? o.s : a.s;
-        hi.s = upper ? a.s : o.s;
-        lo.best = upper ? o.best : a.best;
-        hi.best = upper ? a.best : o.best;
-        lo.sec = upper ? o.sec : a.sec;
-        hi.sec = upper ? a.sec : o.sec;
-        lo.bm = upper ? o.bm : a.bm;
-        hi.bm = upper ? a.bm : o.bm;
-        acc_merge(lo, hi);
-        a = lo;
+    for (int lvl = 0; lvl < kLevels; ++lvl) {
+        const int off = 32 >> lvl;
+        const int h = (BT >> lvl) / 2;
+        const bool up = (lane & off) != 0;
+#pragma unroll
+        for (int i = 0; i < BT / 2; ++i) {
+            if (i >= h) break;
+            const Acc keep = acc_sel(up, a[i + h], a[i]);
+            const Acc send = acc_sel(up, a[i], a[i + h]);
+            const Acc recv = acc_shfl_xor(send, off);
+            Acc lo = acc_sel(up, recv, keep);
+            const Acc hi = acc_sel(up, keep, recv);
+            acc_merge(lo, hi);
+            a[i] = lo;
+        }
     }
+    Acc r = a[0];
+#pragma unroll
+    for (int off = 1; off < (64 >> kLevels); off <<= 1) {
+        const Acc o = acc_shfl_xor(r, off);
+        const bool up = (lane & off) != 0;
+        Acc lo = acc_sel(up, o, r);
+        const Acc hi = acc_sel(up, r, o);
+        acc_merge(lo, hi);
+        r = lo;
+    }
+    return r;
 }
 
 __device__ __forceinline__ double wave_sum_f64(double v, int lane)
@@ -289,10 +320,16 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         }
     }
 
-#pragma unroll
-    for (int j = 0; j < BT; ++j) {
-        acc_wave_reduce(a[j], lane);
-        if (lane == 0) s_red[wave][j] = a[j];
+    {
+        const Acc r = acc_wave_reduce_scatter<BT>(a, lane);
+        if ((lane & (64 / BT - 1)) == 0) {
+            const int j = lane / (64 / BT);
+            s_red[wave][j].m = r.m;
+            s_red[wave][j].s = r.s;
+            s_red[wave][j].best = r.best;
+            s_red[wave][j].sec = r.sec;
+            s_red[wave][j].bm = r.bm;
+        }
     }
     __syncthreads();
     if (threadIdx.x < BT) {
