@@ -425,12 +425,21 @@ __global__ __launch_bounds__(kScoreThreads) void k_count_tiles(ScoreArgs A, unsi
     }
 }
 
-// Grid: x = node * chunks + chunk, y = group of BT orders.
+// Grid: x = node * chunks + chunk, y = group of BT orders.  With one order
+// per block, x runs over the order's positions from the last one down: the
+// node at the last position has the most predecessors, hence the most tiles
+// to read, so the longest blocks are dispatched first and the shortest fill
+// the tail.  (An entry that is not a node id keeps the plain mapping; such an
+// order is invalid and scores NaN anyway.)
 template <int BT>
 __global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
 {
-    const int node = blockIdx.x / A.chunks;
+    int node = blockIdx.x / A.chunks;
     const int chunk = blockIdx.x - node * A.chunks;
+    if (BT == 1) {
+        const int v = A.orders[(int64_t)blockIdx.y * A.n + (A.n - 1 - node)];
+        node = (v >= 0 && v < A.n) ? v : node;
+    }
     score_block<BT>(view_of(A), node, chunk, blockIdx.y);
 }
 
