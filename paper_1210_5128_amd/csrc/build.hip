@@ -193,6 +193,18 @@ __global__ void k_prior(const float *__restrict__ src, int n, int mode, double *
     dst[g] = v;
 }
 
+// lut[row][c] = lnG(c + a) - lnG(a), a = ess / den[row], c = 0..N (FP64 ocml lgamma).
+__global__ void k_lut(const int32_t *__restrict__ den, int rows, int64_t N, double ess, double *__restrict__ lut)
+{
+    const int64_t total = (int64_t)rows * (N + 1);
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int row = (int)(g / (N + 1));
+        const int64_t c = g - (int64_t)row * (N + 1);
+        const double a = ess / (double)den[row];
+        lut[g] = lgamma((double)c + a) - lgamma(a);
+    }
+}
+
 // One wavefront per (node, entry): enumerate the entry's parent set, count
 // N_ijk in LDS, reduce the BDeu terms in FP64, add the structure penalty and
 // the prior terms, store (mask, FP32 score).  Padding entries get (~0, -inf),
@@ -201,8 +213,8 @@ template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_build(
     const uint8_t *__restrict__ data, int64_t N, int64_t N_pad, const int32_t *__restrict__ ar,
     const double *__restrict__ prior, const int64_t *__restrict__ nsets, int n, int K, double ess,
-    double log_gamma, int64_t S, int64_t S_pad, int cells_cap, uint64_t *__restrict__ masks,
-    float *__restrict__ scores)
+    double log_gamma, int64_t S, int64_t S_pad, int cells_cap, const int32_t *__restrict__ lut_row,
+    const double *__restrict__ lut, uint64_t *__restrict__ masks, float *__restrict__ scores)
 {
     extern __shared__ uint32_t lds_hist[];
     const int wave = threadIdx.x >> 6;
@@ -227,19 +239,36 @@ __global__ __launch_bounds__(WAVES * 64) void k_build(
 
         const double a_ijk = ess / (double)cells;
         const double a_ik = ess / (double)M.q;
-        const double lg_ijk = lgamma(a_ijk);
-        const double lg_ik = lgamma(a_ik);
         double acc = 0.0;
-        for (int k = lane; k < M.q; k += 64) {
-            uint32_t nik = 0;
-            double part = 0.0;
-            for (int j = 0; j < r; ++j) {
-                uint32_t c = hist[k * r + j];
-                nik += c;
-                if (c) part += lgamma((double)c + a_ijk) - lg_ijk;
+        if (lut) {
+            // lnG(c + a) - lnG(a) looked up per count (same FP64 values as computed below)
+            const double *L_ijk = lut + (int64_t)lut_row[cells] * (N + 1);
+            const double *L_ik = lut + (int64_t)lut_row[M.q] * (N + 1);
+            for (int k = lane; k < M.q; k += 64) {
+                uint32_t nik = 0;
+                double part = 0.0;
+                for (int j = 0; j < r; ++j) {
+                    const uint32_t c = hist[k * r + j];
+                    nik += c;
+                    if (c) part += L_ijk[c];
+                }
+                if (nik) part += -L_ik[nik];
+                acc += part;
             }
-            if (nik) part += lg_ik - lgamma(a_ik + (double)nik);
-            acc += part;
+        } else {
+            const double lg_ijk = lgamma(a_ijk);
+            const double lg_ik = lgamma(a_ik);
+            for (int k = lane; k < M.q; k += 64) {
+                uint32_t nik = 0;
+                double part = 0.0;
+                for (int j = 0; j < r; ++j) {
+                    const uint32_t c = hist[k * r + j];
+                    nik += c;
+                    if (c) part += lgamma((double)c + a_ijk) - lg_ijk;
+                }
+                if (nik) part += -(lgamma(a_ik + (double)nik) - lg_ik);
+                acc += part;
+            }
         }
         acc = wave_sum_f64(acc);
         wave_lds_sync();   // every lane has read hist before the next entry clears it
@@ -367,7 +396,7 @@ static int64_t sets_upto(int m, int K)
 static int waves_for_cells(int cells_cap) { return cells_cap <= 4096 ? 4 : 1; }
 
 template <int W>
-static hipError_t launch_build(TableT *t, hipStream_t st, int cells_cap)
+static hipError_t launch_build(TableT *t, hipStream_t st, int cells_cap, const int32_t *lut_row, const double *lut)
 {
     int64_t total = (int64_t)t->n * t->S_pad;
     int64_t blocks = (total + W - 1) / W;
@@ -375,7 +404,7 @@ static hipError_t launch_build(TableT *t, hipStream_t st, int cells_cap)
     size_t lds = (size_t)W * cells_cap * sizeof(uint32_t);
     hipLaunchKernelGGL(k_build<W>, dim3((unsigned)blocks), dim3(W * 64), lds, st, t->d_data, t->N,
                        t->N_pad, t->d_ar, t->d_prior, t->d_nsets, t->n, t->K, t->ess, t->log_gamma,
-                       t->S, t->S_pad, cells_cap, t->d_masks, t->d_scores);
+                       t->S, t->S_pad, cells_cap, lut_row, lut, t->d_masks, t->d_scores);
     return hipGetLastError();
 }
 
@@ -540,6 +569,8 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
 #undef ALLOC
     int8_t *d_rows = nullptr;
     float *d_prior_in = nullptr;
+    int32_t *d_lut_row = nullptr, *d_den = nullptr;
+    double *d_lut = nullptr;
     std::vector<int64_t> nsets(64 * 8, 0);
     for (int b = 0; b < 64; ++b)
         for (int k = 0; k < 8; ++k) nsets[b * 8 + k] = sets_upto(b, k);
@@ -547,6 +578,7 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     if ((e = (call)) != hipSuccess) {                                                     \
         set_error(std::string(#call) + ": " + hipGetErrorString(e));                      \
         hipFree(d_rows); hipFree(d_prior_in);                                             \
+        hipFree(d_lut_row); hipFree(d_den); hipFree(d_lut);                               \
         return fail(BNOS_E_DEVICE);                                                       \
     }
     if (N > 0) CK(hipMalloc((void **)&d_rows, (size_t)N * n));
@@ -565,9 +597,49 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     hipLaunchKernelGGL(k_prior, dim3((n * n + 255) / 256), dim3(256), 0, st, d_prior_in, n, o.prior_mode,
                        t->d_prior);
     CK(hipGetLastError());
+    // lnGamma lookup: the BDeu terms only take alpha = ess / d for d = q (a
+    // product of at most K parent arities) and d = q * r_i; every such d up to
+    // the largest q * r_i gets a row of lnG(c + alpha) - lnG(alpha), c = 0..N,
+    // unless that would take more than kLutBytes (then lgamma is called inline).
+    {
+        std::vector<char> isq(max_cells + 1, 0), isd(max_cells + 1, 0);
+        std::vector<int> ar_set;
+        for (int v = 0; v < n; ++v)
+            if (std::find(ar_set.begin(), ar_set.end(), arities[v]) == ar_set.end()) ar_set.push_back(arities[v]);
+        std::vector<int> qs = {1};
+        isq[1] = 1;
+        for (int depth = 0; depth < K; ++depth) {
+            const size_t m = qs.size();
+            for (size_t i = 0; i < m; ++i)
+                for (int a : ar_set) {
+                    const int64_t q = (int64_t)qs[i] * a;
+                    if (q <= max_cells && !isq[q]) { isq[q] = 1; qs.push_back((int)q); }
+                }
+        }
+        std::vector<int32_t> den, row(max_cells + 1, 0);
+        for (int q : qs) {
+            isd[q] = 1;
+            for (int a : ar_set)
+                if ((int64_t)q * a <= max_cells) isd[(int64_t)q * a] = 1;
+        }
+        for (int d = 1; d <= max_cells; ++d)
+            if (isd[d]) { row[d] = (int32_t)den.size(); den.push_back(d); }
+        constexpr int64_t kLutBytes = 256ll << 20;
+        if ((int64_t)den.size() * (N + 1) * 8 <= kLutBytes) {
+            CK(hipMalloc((void **)&d_den, sizeof(int32_t) * den.size()));
+            CK(hipMalloc((void **)&d_lut_row, sizeof(int32_t) * row.size()));
+            CK(hipMalloc((void **)&d_lut, sizeof(double) * den.size() * (size_t)(N + 1)));
+            CK(hipMemcpyAsync(d_den, den.data(), sizeof(int32_t) * den.size(), hipMemcpyHostToDevice, st));
+            CK(hipMemcpyAsync(d_lut_row, row.data(), sizeof(int32_t) * row.size(), hipMemcpyHostToDevice, st));
+            const int64_t tot = (int64_t)den.size() * (N + 1);
+            hipLaunchKernelGGL(k_lut, dim3((unsigned)std::min<int64_t>((tot + 255) / 256, 1 << 16)), dim3(256), 0, st,
+                               d_den, (int)den.size(), N, ess, d_lut);
+            CK(hipGetLastError());
+        }
+    }
     int cap = cells_cap_for(max_cells);
-    if (waves_for_cells(cap) == 4) { CK(launch_build<4>(t, st, cap)); }
-    else { CK(launch_build<1>(t, st, cap)); }
+    if (waves_for_cells(cap) == 4) { CK(launch_build<4>(t, st, cap, d_lut_row, d_lut)); }
+    else { CK(launch_build<1>(t, st, cap, d_lut_row, d_lut)); }
     hipLaunchKernelGGL(k_node_stats, dim3(n), dim3(1024), 0, st, t->d_scores, t->S, t->S_pad, t->d_prior, n,
                        t->d_nstat);
     CK(hipGetLastError());
@@ -580,6 +652,9 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     CK(hipStreamSynchronize(st));
     hipFree(d_rows);
     hipFree(d_prior_in);
+    hipFree(d_lut_row);
+    hipFree(d_den);
+    hipFree(d_lut);
 #undef CK
     t->magic = kMagic;
     register_handle(t);
