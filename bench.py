@@ -262,6 +262,52 @@ def bench_learned(bnos, datagen, wname: str, chains: int, moves: int, iters: int
     return out
 
 
+def run_only(args, bnos, datagen, dev):
+    """One piece of the path alone (for profiler runs): its wall time as JSON."""
+    import torch
+    out = {"only": args.only}
+    if args.only == "mlp":
+        R, n = args.mlp_samples, 60
+        rng = np.random.default_rng(1)
+        feats = torch.from_numpy(rng.standard_normal((R, n, 8)).astype(np.float32)).to(dev)
+        pairs = torch.from_numpy(np.stack([rng.choice(n, 2, replace=False) for _ in range(R)]).astype(np.int32)).to(dev)
+        m = bnos.Mlp()
+        m.set_params(datagen.mlp_params(3, scale=0.5).astype(np.float32))
+        m.fit_norm(feats)
+        logits = torch.empty((R, n), dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.forward(feats, logits)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        m.train(feats, pairs, epochs=2, batch=1024, lr=1e-3, seed=1)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        m.free()
+        out.update(samples=R, n=n, forward_s=t1 - t0, train_2_epochs_s=t2 - t1)
+        return out
+    w = datagen.WORKLOADS[args.workload]
+    net, prior = datagen.make(w)
+    t0 = time.perf_counter()
+    table = bnos.build_score_table(net.data, net.arities, w.K, ess=w.ess, prior=prior)
+    torch.cuda.synchronize()
+    out.update(workload=w.name, build_s=time.perf_counter() - t0)
+    if args.only == "chains":
+        C, iters = max(1, args.chains), args.chain_iters
+        st = table.new_chain_state(C, iters, trace_every=iters)
+        table.run_chains(st, min(iters, 20), 1, trace_every=min(iters, 20))      # warm-up
+        torch.cuda.synchronize()
+        st = table.new_chain_state(C, iters, trace_every=iters)
+        t0 = time.perf_counter()
+        table.run_chains(st, iters, 2, trace_every=iters)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out.update(chains=C, iterations=iters, seconds=dt, chain_iterations_per_s=C * iters / dt,
+                   ms_per_iteration=dt / iters * 1e3)
+    table.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,6 +335,11 @@ def main():
     ap.add_argument("--uneven", type=int, default=0, metavar="D",
                     help="also run the uneven family: D datasets x 64 chains in one launch vs one at a time")
     ap.add_argument("--uneven-iters", type=int, default=1000)
+    ap.add_argument("--only", choices=("build", "chains", "mlp"), default=None,
+                    help="run one piece alone for a profiler and print its own JSON line: the table build of "
+                         "--workload; --chains chains x --chain-iters iterations on it; or the network's "
+                         "forward and two training epochs on --mlp-samples synthetic n=60 samples")
+    ap.add_argument("--mlp-samples", type=int, default=16384)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (scale for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -315,6 +366,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}), flush=True)
+        return
+
+    if args.only:
+        print(json.dumps(run_only(args, bnos, datagen, dev)), flush=True)
         return
 
     w = datagen.WORKLOADS[args.workload]
