@@ -417,10 +417,12 @@ def main():
                     break
         kernel_avg_ms = k_ms / k_launches
         passes_per_launch = k_passes / k_launches
-        # bytes the launch had to read: with tile skipping, the tiles it loaded
-        # (256 entries x 12 B) plus every tile's 8-byte summary; without, the full scan
+        # bytes the launch had to read: with tile skipping, the 64-entry sub-tiles it
+        # loaded (64 x 12 B) plus the 8-byte summary of every tile of each pass and,
+        # with one order per block, of every sub-tile; without, the full scan
         if skip:
-            alg = tiles / k_launches * 256 * 12 + passes_per_launch * tiles_per_pass * 8
+            sub_summaries = tiles_per_pass if passes_per_launch == Bq else 0
+            alg = tiles / k_launches * 64 * 12 + passes_per_launch * (tiles_per_pass // 4 + sub_summaries) * 8
         else:
             alg = bytes_per_pass * passes_per_launch
         gbs = alg / (kernel_avg_ms / 1e3) / 1e9

@@ -330,13 +330,18 @@ bnos_status bnos_run_chains_multi(const bnos_table *tables, int32_t T, const bno
 bnos_status bnos_table_timing(bnos_table t, int32_t enable);
 
 /*
- * Tile skipping (on by default): the table keeps, for every 256-entry tile,
- * the AND of its masks; a tile whose AND contains a node outside an order's
- * predecessor set holds no consistent entry for that order, and a tile no
- * order of a block needs is not read.  Results are identical with it off.
- * bnos_table_count_tiles (measurement) returns how many tiles a scoring
- * launch of these B orders (DEVICE int32 [B][n]) reads with tile skipping,
- * and the tiles of one full pass (n * padded entries / 256).  Synchronous.
+ * Tile skipping (on by default): the table keeps, for every 256-entry tile
+ * and every 64-entry sub-tile, the AND of its masks; a (sub-)tile whose AND
+ * contains a node outside an order's predecessor set holds no consistent
+ * entry for that order.  A tile no order of a scoring block needs is skipped
+ * by the block, and a block scoring one order does not fetch the sub-tiles of
+ * its tiles that the order cannot use.  Results are identical with it off.
+ * bnos_table_count_tiles (measurement) returns how many 64-entry sub-tiles a
+ * scoring launch of these B orders (DEVICE int32 [B][n]) reads with tile
+ * skipping, and the sub-tiles of one full pass (n * padded entries / 64).
+ * Such a launch also reads every tile summary of each pass (8 B per 256
+ * entries) and, with one order per block, every sub-tile summary (8 B per 64
+ * entries).  Synchronous.
  */
 bnos_status bnos_table_tile_skip(bnos_table t, int32_t enable);
 bnos_status bnos_table_count_tiles(bnos_table t, const int32_t *orders, int32_t B, int64_t *tiles_read,

@@ -49,6 +49,7 @@ struct TableT {
     float *d_scores = nullptr;      // [n][S_pad]
     double *d_nstat = nullptr;      // [n][5]: prior row sum, prior column sum, max, mean, sd of the row
     uint64_t *d_tand = nullptr;     // [n * S_pad / 256]: AND of the masks of each 256-entry tile
+    uint64_t *d_tsub = nullptr;     // [n * S_pad / 64]: AND of the masks of each 64-entry sub-tile
     bool tile_skip = true;
 
     // order-scoring workspace: per (order, node, chunk) partial reductions

@@ -46,7 +46,7 @@ int64_t TableT::device_bytes() const
 {
     return (int64_t)n * S_pad * (int64_t)(sizeof(uint64_t) + sizeof(float)) + (int64_t)n * N_pad +
            (int64_t)n * (int64_t)(sizeof(int32_t) + n * sizeof(double) + 5 * sizeof(double)) + 64 * 8 * 8 +
-           part_bytes + (int64_t)n * (S_pad / 256) * 8;
+           part_bytes + (int64_t)n * (S_pad / 256) * 8 + (int64_t)n * (S_pad / 64) * 8;
 }
 
 // ------------------------------------------------------------------ device helpers
@@ -342,15 +342,19 @@ __global__ __launch_bounds__(1024) void k_node_stats(const float *__restrict__ s
 
 // AND of the masks of every 256-entry tile (one wavefront per tile).
 __global__ __launch_bounds__(256) void k_tile_and(const uint64_t *__restrict__ masks, int64_t tiles,
-                                                  uint64_t *__restrict__ tand)
+                                                  uint64_t *__restrict__ tand, uint64_t *__restrict__ tsub)
 {
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (tile >= tiles) return;                       // uniform per wavefront
     const uint64_t *p = masks + tile * 256 + lane * 4;
     uint64_t v = p[0] & p[1] & p[2] & p[3];
+    // lanes 16s .. 16s+15 hold sub-tile s (entries 64s .. 64s+63)
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v &= (uint64_t)__shfl_xor((unsigned long long)v, off, 64);
+    for (int off = 1; off <= 8; off <<= 1) v &= (uint64_t)__shfl_xor((unsigned long long)v, off, 64);
+    if ((lane & 15) == 0) tsub[tile * 4 + (lane >> 4)] = v;
+#pragma unroll
+    for (int off = 16; off <= 32; off <<= 1) v &= (uint64_t)__shfl_xor((unsigned long long)v, off, 64);
     if (lane == 0) tand[tile] = v;
 }
 
@@ -425,6 +429,7 @@ static void free_device(TableT *t)
     hipFree(t->d_scores);
     hipFree(t->d_nstat);
     hipFree(t->d_tand);
+    hipFree(t->d_tsub);
     hipFree(t->d_part);
     for (auto e : t->ev_start) hipEventDestroy(e);
     for (auto e : t->ev_stop) hipEventDestroy(e);
@@ -566,6 +571,7 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     ALLOC(t->d_scores, sizeof(float) * (size_t)n * t->S_pad);
     ALLOC(t->d_nstat, sizeof(double) * (size_t)n * 5);
     ALLOC(t->d_tand, sizeof(uint64_t) * (size_t)n * (t->S_pad / 256));
+    ALLOC(t->d_tsub, sizeof(uint64_t) * (size_t)n * (t->S_pad / 64));
 #undef ALLOC
     int8_t *d_rows = nullptr;
     float *d_prior_in = nullptr;
@@ -646,7 +652,7 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     {
         const int64_t tiles = (int64_t)n * (t->S_pad / 256);
         hipLaunchKernelGGL(k_tile_and, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, t->d_masks, tiles,
-                           t->d_tand);
+                           t->d_tand, t->d_tsub);
         CK(hipGetLastError());
     }
     CK(hipStreamSynchronize(st));

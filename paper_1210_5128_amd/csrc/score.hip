@@ -97,6 +97,7 @@ ScoreArgs score_args(const TableT *t, const int32_t *orders, int B, double *lse,
     A.wl_count = nullptr;
     A.wl_list = nullptr;
     A.tand = t->tile_skip ? t->d_tand : nullptr;
+    A.tsub = t->d_tsub;
     return A;
 }
 
@@ -246,7 +247,7 @@ extern "C" bnos_status bnos_table_count_tiles(bnos_table h, const int32_t *order
     int64_t tot = 0;
     for (unsigned v : hc) tot += v;
     if (tiles_read) *tiles_read = tot;
-    if (tiles_per_pass) *tiles_per_pass = (int64_t)t->n * (t->S_pad / 256);
+    if (tiles_per_pass) *tiles_per_pass = (int64_t)t->n * (t->S_pad / 64);
     return BNOS_OK;
 }
 

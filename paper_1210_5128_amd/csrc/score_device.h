@@ -191,6 +191,7 @@ struct ScoreArgs {
     const int32_t *wl_count;   // [n] or null (then slot j of group g is order g*BT + j)
     const int32_t *wl_list;    // [n][B]
     const uint64_t *tand;      // tile summaries, or null
+    const uint64_t *tsub;      // sub-tile summaries (with tand)
 };
 
 // What one streaming block needs to know about its table and its orders.
@@ -205,6 +206,7 @@ struct TabView {
     const int32_t *wl_count;    // [n] or null
     const int32_t *wl_list;     // [n][B]
     const uint64_t *tand;       // [n * S_pad / 256] AND of each 256-entry tile's masks, or null (no skipping)
+    const uint64_t *tsub;       // [n * S_pad / 64] the same per 64-entry sub-tile (with tand)
 };
 
 // One block streams chunk `chunk` of node `node`'s entries once and folds each
@@ -226,8 +228,11 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     const int64_t row = (int64_t)node * V.S_pad + (int64_t)chunk * V.chunk_entries;
     const int steps = V.chunk_entries / kEntriesPerStep;    // each wavefront owns tiles wave + 4*i, i < steps
     // this wavefront's tile summaries, requested before the predecessor masks so the latencies overlap
-    uint64_t tsum = 0;
+    uint64_t tsum = 0, tsl = 0;
     if (V.tand && lane < steps) tsum = V.tand[(row >> 8) + (int64_t)lane * 4 + wave];
+    // sub-tile summaries (one order per block): lane 4i + s holds sub-tile s of this wavefront's tile i
+    if (BT == 1 && V.tand && lane < 4 * steps)
+        tsl = V.tsub[(row >> 6) + (int64_t)((lane >> 2) * 4 + wave) * 4 + (lane & 3)];
 
     for (int j = wave; j < BT; j += kScoreThreads / 64) {
         uint64_t np = ~0ull;   // no order in this slot: nothing is consistent
@@ -289,12 +294,30 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     u64x2 n01 = {0ull, 0ull}, n23 = {0ull, 0ull};
     f32x4 nsc = {0.f, 0.f, 0.f, 0.f};
     uint32_t need_n = 0;
+    // With one order per block, a lane reads its 4 entries only if the order
+    // can use its 64-entry sub-tile; otherwise its masks read as ~0 (consistent
+    // with nothing), so the fold is unchanged and the sub-tile's bytes are not
+    // fetched.  (With several orders the union rarely skips a sub-tile and the
+    // test costs more than it saves.)
+    auto lane_needs = [&](int tk) -> bool {
+        if (BT > 1 || !V.tand) return true;
+        const uint64_t sub = (uint64_t)__shfl((unsigned long long)tsl, ((tk - wave) >> 2) * 4 + (lane >> 4), 64);
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < BT; ++j) any |= (sub & npred[j]) == 0ull;
+        return any;
+    };
     if (k < nt) {
-        const int q = s_tile[wave][k] * 64 + lane;           // this lane's 4-entry group
+        const int tk = s_tile[wave][k];
+        const int q = tk * 64 + lane;                        // this lane's 4-entry group
         need_n = s_tneed[wave][k];
-        n01 = __builtin_nontemporal_load(&mp[2 * q]);
-        n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
-        nsc = __builtin_nontemporal_load(&sp[q]);
+        n01 = (u64x2){~0ull, ~0ull};
+        n23 = (u64x2){~0ull, ~0ull};
+        if (lane_needs(tk)) {
+            n01 = __builtin_nontemporal_load(&mp[2 * q]);
+            n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
+            nsc = __builtin_nontemporal_load(&sp[q]);
+        }
     }
     for (; k < nt; ++k) {
         const u64x2 m01 = n01, m23 = n23;
@@ -302,11 +325,16 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         const uint32_t need_c = need_n;
         const int kn = k + 1;
         if (kn < nt) {
-            const int q = s_tile[wave][kn] * 64 + lane;
+            const int tk = s_tile[wave][kn];
+            const int q = tk * 64 + lane;
             need_n = s_tneed[wave][kn];
-            n01 = __builtin_nontemporal_load(&mp[2 * q]);
-            n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
-            nsc = __builtin_nontemporal_load(&sp[q]);
+            n01 = (u64x2){~0ull, ~0ull};
+            n23 = (u64x2){~0ull, ~0ull};
+            if (lane_needs(tk)) {
+                n01 = __builtin_nontemporal_load(&mp[2 * q]);
+                n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
+                nsc = __builtin_nontemporal_load(&sp[q]);
+            }
         }
         const uint64_t mk[4] = {m01.x, m01.y, m23.x, m23.y};
         const float x[4] = {sc.x, sc.y, sc.z, sc.w};
@@ -378,6 +406,7 @@ __device__ __forceinline__ TabView view_of(const ScoreArgs &A)
     V.wl_count = A.wl_count;
     V.wl_list = A.wl_list;
     V.tand = A.tand;
+    V.tsub = A.tsub;
     return V;
 }
 
@@ -407,13 +436,21 @@ __global__ __launch_bounds__(kScoreThreads) void k_count_tiles(ScoreArgs A, unsi
     __syncthreads();
     const int64_t row = (int64_t)node * A.S_pad + (int64_t)chunk * A.chunk_entries;
     const int steps = A.chunk_entries / kEntriesPerStep;
+    // 64-entry sub-tiles read: of the needed tiles, those the order can use (one
+    // order per block) or all four (several)
     unsigned c = 0;
     if (b0 < count) {
         for (int it = 0; it < steps; ++it) {
-            const uint64_t sm = A.tand[(row >> 8) + (int64_t)it * 4 + wave];
+            const int64_t tile = (row >> 8) + (int64_t)it * 4 + wave;
+            const uint64_t sm = A.tand[tile];
             bool any = false;
             for (int j = 0; j < BT; ++j) any |= (sm & s_np[j]) == 0ull;
-            c += any ? 1u : 0u;
+            if (!any) continue;
+            if (BT > 1) {                  // several orders: the whole tile is read
+                c += 4u;
+                continue;
+            }
+            for (int s = 0; s < 4; ++s) c += ((A.tsub[tile * 4 + s] & s_np[0]) == 0ull) ? 1u : 0u;
         }
     }
     if (lane == 0) s_c[wave] = c;
