@@ -216,6 +216,8 @@ def test_empty_data_closed_form(bnos):
     (5, 4, 37, (2, 3, 4)),       # K = n - 1, N not a multiple of 4
     (64, 2, 129, (2,)),          # the largest n, bit 63 in use
     (12, 3, 1, (4,)),            # one sample
+    (9, 6, 200, (2,)),           # the largest K
+    (10, 4, 300, (5, 6)),        # tables of up to 7,776 cells: one wavefront per block
 ])
 def test_edge_shapes(bnos, n, K, N, arities):
     net = datagen.random_network(n, N, arities, min(3, n - 1), seed=n * 31 + K)
