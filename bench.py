@@ -262,6 +262,30 @@ def bench_learned(bnos, datagen, wname: str, chains: int, moves: int, iters: int
     return out
 
 
+def bench_accuracy(bnos, datagen, chains: int, seed: int = 606):
+    """Sec. VI's study on a 20-node binary graph with 1,000 samples: the best
+    graph's edge TPR/FPR without priors and with the four injected-prior
+    settings, at 1,000 and 10,000 iterations, and under bit-flip noise."""
+    from paper_1210_5128_amd import accuracy as A
+    w = datagen.WORKLOADS["roc20"]
+    net, _ = datagen.make(w)
+    out = {"workload": f"{w.name}: n={w.n}, K={w.K}, N={w.N}, binary", "chains_per_run": chains,
+           "true_edges": int(sum(bin(int(m)).count("1") for m in net.true_parent_masks()))}
+    t0 = time.perf_counter()
+    for iters in (1000, 10000):
+        pts = A.roc_study(bnos, net, w.K, iters, chains, seed)
+        out[f"roc_{iters}_iterations"] = [
+            {"prior": p["prior"], "tpr": round(p["tpr"], 4), "fpr": round(p["fpr"], 5)} for p in pts]
+    out["noise_10000_iterations"] = [
+        {"p": p["p"], "tpr": round(p["tpr"], 4), "fpr": round(p["fpr"], 5)}
+        for p in A.noise_study(bnos, net, w.K, 10000, chains, seed)]
+    out["seconds"] = time.perf_counter() - t0
+    print(f"# accuracy: {out['seconds']:.1f} s; no prior, 10k iterations: TPR "
+          f"{out['roc_10000_iterations'][0]['tpr']:.3f} FPR {out['roc_10000_iterations'][0]['fpr']:.4f}",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def run_only(args, bnos, datagen, dev):
     """One piece of the path alone (for profiler runs): its wall time as JSON."""
     import torch
@@ -332,6 +356,8 @@ def main():
     ap.add_argument("--learned-moves", type=int, default=1000000, help="accepted moves harvested for training")
     ap.add_argument("--learned-epochs", type=int, default=16)
     ap.add_argument("--learned-workload", default="mixed60")
+    ap.add_argument("--accuracy", type=int, default=1, metavar="C",
+                    help="structure-recovery study on the roc20 workload with C chains per run (0 = skip)")
     ap.add_argument("--uneven", type=int, default=0, metavar="D",
                     help="also run the uneven family: D datasets x 64 chains in one launch vs one at a time")
     ap.add_argument("--uneven-iters", type=int, default=1000)
@@ -510,6 +536,8 @@ def main():
         out["chains"] = bench_chains(bnos, datagen, "mixed40", args.chains, args.chain_iters)
     if args.uneven:
         out["uneven"] = bench_uneven(bnos, datagen, args.uneven, 64, args.uneven_iters)
+    if args.accuracy:
+        out["accuracy"] = bench_accuracy(bnos, datagen, args.accuracy)
     if args.learned:
         out["learned"] = bench_learned(bnos, datagen, args.learned_workload, args.learned, args.learned_moves,
                                        args.learned_iters, epochs=args.learned_epochs)

@@ -130,14 +130,17 @@ class Workload:
     ess: float = 1.0
 
 
-# The five synthetic workloads: a tiny binary net, a 20-node ternary net with a
+# The synthetic workloads: a tiny binary net, a 20-node ternary net with a
 # prior, a 40-node mixed-arity net, the uneven 20..60-node family (one member
-# per seed), and the 60-node mixed-arity net used for the headline scoring rate.
+# per seed), the 60-node mixed-arity net used for the headline scoring rate, and
+# a 20-node binary net for the structure-recovery study.
 WORKLOADS = {
     "tiny8": Workload("tiny8", 8, 200, (2,), 3, 3, 0, None),
     "prior20": Workload("prior20", 20, 1000, (3,), 4, 4, 1, 11),
     "mixed40": Workload("mixed40", 40, 2000, (2, 3, 4), 4, 4, 2, 12),
     "mixed60": Workload("mixed60", 60, 5000, (2, 3, 4), 4, 4, 4, 14),
+    # the accuracy study's graph: 20 binary nodes, 1,000 samples (Sec. VI)
+    "roc20": Workload("roc20", 20, 1000, (2,), 3, 4, 20, None),
 }
 
 
