@@ -129,7 +129,8 @@ def bench_chains(bnos, datagen, wname: str, chains: int, iters: int, seed: int =
         dt = time.perf_counter() - t0
         tr = st["trace"].cpu().numpy()
         e = E.ess(tr)
-        out[label] = {"chains": C, "seconds": dt, "chain_iterations_per_s": C * iters / dt,
+        out[label] = {"chains": C, "eps": eps if mlp is not None else None, "seconds": dt,
+                      "chain_iterations_per_s": C * iters / dt,
                       "ess": e, "ess_per_s": e / dt,
                       "accept_rate": float(st["accepted"].sum().item()) / (C * iters),
                       "best_score_max": float(st["best_scores"].max().item()),
@@ -177,12 +178,13 @@ def bench_uneven(bnos, datagen, n_datasets: int, chains: int, iters: int, seed: 
 
 
 def bench_learned(bnos, datagen, wname: str, chains: int, moves: int, iters: int, epochs: int,
-                  seed: int = 404):
+                  eps_list=(0.1,), seed: int = 404):
     """Learned swap proposal: harvest `moves` accepted moves from uniform chains
     (which also serves as burn-in), train the network on the device, then resume
     every chain from its harvested state twice, with the uniform and with the
     learned proposal, on the same random-number streams; plus one uniform chain
-    alone.  ESS/s of the log-sum-exp trace, acceptance, best-graph score."""
+    alone.  ESS/s of the log-sum-exp trace and the smallest ESS over the
+    indicators of the 20 most uncertain edges, acceptance, best-graph score."""
     import torch
     from paper_1210_5128_amd import ess as E
     w = datagen.WORKLOADS[wname]
@@ -230,33 +232,66 @@ def bench_learned(bnos, datagen, wname: str, chains: int, moves: int, iters: int
           f"{out['train']['loss_last']:.3f} (uniform {out['train']['uniform_pair_loss']:.3f})",
           file=sys.stderr, flush=True)
     del feats, pairs
-    # 3. resume every chain from its harvested state: uniform vs learned, and one uniform chain alone
+    # 3. the 20 most uncertain edges: greedy graphs of the chains' current orders,
+    # edges whose frequency over chains is closest to 1/2
+    B = st["orders"].shape[0]
+    lse = torch.empty(B, dtype=torch.float64, device=st["orders"].device)
+    mx = torch.empty_like(lse)
+    best = torch.empty((B, n), dtype=torch.int64, device=lse.device)
+    table.score_orders(st["orders"], lse, mx, best)
+    bm = best.cpu().numpy().view(np.uint64)
+    freq = np.zeros((n, n))
+    for i in range(n):
+        for p in range(n):
+            freq[i, p] = np.mean((bm[:, i] >> np.uint64(p)) & np.uint64(1))
+    cand = sorted(((abs(freq[i, p] - 0.5), i, p) for i in range(n) for p in range(n)
+                   if i != p and 0.0 < freq[i, p] < 1.0))[:20]
+    edges = [(i, p) for _, i, p in cand]
+    out["traced_edges"] = {"count": len(edges), "frequencies": [round(float(freq[i, p]), 4) for i, p in edges]}
+    # 4. resume every chain from its harvested state: uniform vs learned, and one uniform chain alone
     base = {k: v for k, v in st.items() if k in ("orders", "scores", "best_graphs", "best_scores", "accepted")}
-    for label, mlp, C in (("uniform", None, chains), ("learned", m, chains), ("single_uniform", None, 1)):
+    runs = [("uniform", None, chains, 0.1)]
+    for k, eps in enumerate(eps_list):
+        runs.append(("learned" if k == 0 else f"learned_eps{eps:g}", m, chains, eps))
+    runs.append(("single_uniform", None, 1, 0.1))
+    for label, mlp, C, eps in runs:
         s2 = {k: v[:C].clone() for k, v in base.items()}
         s2["trace"] = torch.zeros((C, iters + 1), dtype=torch.float64, device=base["scores"].device)
         s2["accept_flags"] = None
+        if edges:
+            s2["edges"] = np.asarray(edges, dtype=np.int32)
+            s2["edge_trace"] = torch.zeros((C, iters + 1), dtype=torch.int32, device=base["scores"].device)
         a0 = s2["accepted"].clone()
         t0 = time.perf_counter()
-        table.run_chains(s2, iters, seed + 5, first_iteration=done, mlp=mlp)
+        table.run_chains(s2, iters, seed + 5, first_iteration=done, mlp=mlp, eps=eps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         trc = s2["trace"].cpu().numpy()
         e = E.ess(trc)
-        out[label] = {"chains": C, "seconds": dt, "chain_iterations_per_s": C * iters / dt,
+        edge_ess = None
+        if edges:
+            et = s2["edge_trace"].cpu().numpy().view(np.uint32)
+            edge_ess = min(E.ess(((et >> np.uint32(k)) & np.uint32(1)).astype(np.float64))
+                           for k in range(len(edges)))
+        out[label] = {"chains": C, "eps": eps if mlp is not None else None, "seconds": dt,
+                      "chain_iterations_per_s": C * iters / dt,
                       "ess": e, "ess_per_s": e / dt, "ess_per_1k_chain_iterations": 1e3 * e / (C * iters),
+                      "edge_ess_min": edge_ess, "edge_ess_min_per_s": None if edge_ess is None else edge_ess / dt,
                       "accept_rate": float((s2["accepted"] - a0).sum().item()) / (C * iters),
                       "best_score_max": float(s2["best_scores"].max().item()),
                       "best_score_mean": float(s2["best_scores"].mean().item()),
                       "score_mean": float(trc.mean()),
                       "split_rhat": E.split_rhat(trc) if C > 1 else None}
-        print(f"# {label}: {dt:.2f} s, ESS {e:.0f}, ESS/s {e / dt:.1f}, accept {out[label]['accept_rate']:.3f}",
-              file=sys.stderr, flush=True)
+        print(f"# {label}: {dt:.2f} s, ESS {e:.0f}, ESS/s {e / dt:.1f}, min edge ESS {edge_ess}, "
+              f"accept {out[label]['accept_rate']:.3f}", file=sys.stderr, flush=True)
     out["ess_per_s_ratio_learned_vs_uniform"] = out["learned"]["ess_per_s"] / max(out["uniform"]["ess_per_s"], 1e-30)
     out["ess_per_s_ratio_learned_vs_single_uniform"] = (out["learned"]["ess_per_s"] /
                                                         max(out["single_uniform"]["ess_per_s"], 1e-30))
     out["ess_per_iteration_ratio_learned_vs_uniform"] = (out["learned"]["ess_per_1k_chain_iterations"] /
                                                          max(out["uniform"]["ess_per_1k_chain_iterations"], 1e-30))
+    if edges:
+        out["edge_ess_min_per_s_ratio_learned_vs_uniform"] = (out["learned"]["edge_ess_min_per_s"] /
+                                                              max(out["uniform"]["edge_ess_min_per_s"], 1e-30))
     m.free()
     table.free()
     return out
@@ -355,11 +390,13 @@ def main():
     ap.add_argument("--learned-iters", type=int, default=4000, help="iterations of each compared run")
     ap.add_argument("--learned-moves", type=int, default=1000000, help="accepted moves harvested for training")
     ap.add_argument("--learned-epochs", type=int, default=16)
+    ap.add_argument("--learned-eps", default="0.5,0.1",
+                    help="comma-separated weights of the uniform pair in the learned q; the first is the headline")
     ap.add_argument("--learned-workload", default="mixed60")
     ap.add_argument("--accuracy", type=int, default=1, metavar="C",
                     help="structure-recovery study on the roc20 workload with C chains per run (0 = skip)")
-    ap.add_argument("--uneven", type=int, default=0, metavar="D",
-                    help="also run the uneven family: D datasets x 64 chains in one launch vs one at a time")
+    ap.add_argument("--uneven", type=int, default=32, metavar="D",
+                    help="uneven family: D datasets x 64 chains in one set of launches vs one at a time (0 = skip)")
     ap.add_argument("--uneven-iters", type=int, default=1000)
     ap.add_argument("--only", choices=("build", "chains", "mlp"), default=None,
                     help="run one piece alone for a profiler and print its own JSON line: the table build of "
@@ -540,7 +577,8 @@ def main():
         out["accuracy"] = bench_accuracy(bnos, datagen, args.accuracy)
     if args.learned:
         out["learned"] = bench_learned(bnos, datagen, args.learned_workload, args.learned, args.learned_moves,
-                                       args.learned_iters, epochs=args.learned_epochs)
+                                       args.learned_iters, epochs=args.learned_epochs,
+                                       eps_list=[float(x) for x in args.learned_eps.split(",")])
     if not args.no_cpu:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(net, prior, K)

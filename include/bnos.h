@@ -260,11 +260,13 @@ typedef struct {
                                  first_iteration + j*trace_every, j = 0..iterations/trace_every */
     int32_t sweep_len;        /* iterations per captured graph; 0 = 32 */
     int32_t proposal;         /* 0: uniform swap of two positions; 1: learned (needs mlp) */
-    float eps;                /* learned: weight of the uniform pair in q, (0, 1]; 0 means 0.1 */
+    float eps;                /* learned: weight of the uniform pair in q, (0, 1]; 0 means 0.5 */
     struct bnos_mlp_s *mlp;   /* learned: the network (see bnos_mlp_*), read during the call */
     int32_t topk;             /* 0..64: keep each chain's topk best distinct graphs (Sec. III.C keeps a
                                  number of best graphs); 0 = off */
-    int32_t reserved[3];      /* must be zero */
+    int32_t trace_edges;      /* 0..32: edges traced per chain (state.edge_trace), for mixing diagnostics */
+    const int32_t *edges;     /* HOST [trace_edges][2] (child, parent) node ids, read during the call */
+    int32_t reserved[2];      /* must be zero */
 } bnos_chain_cfg;
 
 typedef struct {              /* DEVICE pointers; the chain state, read when resuming, written always */
@@ -293,6 +295,11 @@ typedef struct {              /* DEVICE pointers; the chain state, read when res
     uint64_t *top_graphs;     /* [C][topk][n] */
     double *top_scores;       /* [C][topk] */
     int32_t *top_count;       /* [C] records held (in/out) */
+    /* cfg.trace_edges > 0: bit e of edge_trace[c][j] tells whether edge e of
+       cfg.edges (parent -> child) is in the greedy graph of chain c's current
+       order after iteration first_iteration + j*trace_every (j = 0: the
+       starting order), for effective-sample-size estimates of edge indicators. */
+    uint32_t *edge_trace;     /* [C][iterations/trace_every + 1] */
 } bnos_chain_state;
 
 /*

@@ -38,14 +38,15 @@ class ChainCfg(ctypes.Structure):
     _fields_ = [("chains", ctypes.c_int32), ("target", ctypes.c_int32), ("iterations", ctypes.c_int64),
                 ("first_iteration", ctypes.c_int64), ("seed", ctypes.c_uint64), ("chain_offset", ctypes.c_int64),
                 ("trace_every", ctypes.c_int32), ("sweep_len", ctypes.c_int32), ("proposal", ctypes.c_int32),
-                ("eps", ctypes.c_float), ("mlp", P), ("topk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("eps", ctypes.c_float), ("mlp", P), ("topk", ctypes.c_int32), ("trace_edges", ctypes.c_int32),
+                ("edges", P), ("reserved", ctypes.c_int32 * 2)]
 
 
 class ChainState(ctypes.Structure):
     _fields_ = [("orders", P), ("scores", P), ("best_graphs", P), ("best_scores", P), ("accepted", P),
                 ("trace", P), ("accept_flags", P), ("harvest_feats", P), ("harvest_pairs", P),
                 ("harvest_count", P), ("harvest_cap", ctypes.c_int64), ("top_graphs", P), ("top_scores", P),
-                ("top_count", P)]
+                ("top_count", P), ("edge_trace", P)]
 
 
 _SIGS = {
@@ -190,8 +191,10 @@ class Table:
         return out
 
     def new_chain_state(self, chains: int, iterations: int, trace_every: int = 1, flags: bool = False,
-                        device=None, harvest_cap: int = 0, topk: int = 0):
-        """Device tensors holding the state of `chains` chains (see bnos_chain_state)."""
+                        device=None, harvest_cap: int = 0, topk: int = 0, edges=None):
+        """Device tensors holding the state of `chains` chains (see bnos_chain_state).
+        edges: optional (child, parent) pairs (at most 32) whose presence in each
+        chain's current greedy graph is traced into state["edge_trace"]."""
         import torch
         dev = device or torch.device("cuda")
         n = self.n
@@ -209,6 +212,10 @@ class Table:
             st["harvest_feats"] = torch.zeros((chains, harvest_cap, n, 8), dtype=torch.float32, device=dev)
             st["harvest_pairs"] = torch.zeros((chains, harvest_cap, 2), dtype=torch.int32, device=dev)
             st["harvest_count"] = torch.zeros(chains, dtype=torch.int64, device=dev)
+        if edges is not None and len(edges):
+            st["edges"] = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+            st["edge_trace"] = torch.zeros((chains, iterations // max(1, trace_every) + 1), dtype=torch.int32,
+                                           device=dev)
         if topk > 0:
             st["top_graphs"] = torch.zeros((chains, topk, n), dtype=torch.int64, device=dev)
             st["top_scores"] = torch.zeros((chains, topk), dtype=torch.float64, device=dev)
@@ -216,13 +223,14 @@ class Table:
         return st
 
     def run_chains(self, state: dict, iterations: int, seed: int, target: int = 0, first_iteration: int = 0,
-                   trace_every: int = 1, chain_offset: int = 0, sweep_len: int = 0, mlp=None, eps=0.1, stream=None):
+                   trace_every: int = 1, chain_offset: int = 0, sweep_len: int = 0, mlp=None, eps=0.5, stream=None):
         """Run MH chains in place on `state` (from new_chain_state); returns when done.
         With `mlp` the swap pair comes from the learned proposal (exact MH correction)."""
         chains = int(state["orders"].shape[0])
         cfg = _chain_cfg(chains, iterations, seed, target, first_iteration, trace_every, chain_offset, sweep_len,
                          mlp, eps)
         cfg.topk = _state_topk([state])
+        edges = _state_edges(cfg, [state])
         st = _chain_state(state, iterations, trace_every)
         _check(_lib.bnos_run_chains(self._h, ctypes.byref(cfg), ctypes.byref(st), _stream(stream)))
 
@@ -317,7 +325,7 @@ class Mlp:
 
 
 def _chain_cfg(chains, iterations, seed, target, first_iteration, trace_every, chain_offset, sweep_len,
-               mlp=None, eps=0.1):
+               mlp=None, eps=0.5):
     cfg = ChainCfg()
     if mlp is not None:
         cfg.proposal = 1
@@ -342,10 +350,25 @@ def _state_topk(states) -> int:
     return ks.pop()
 
 
+def _state_edges(cfg, states):
+    """Set cfg's traced edges from the states (all must trace the same edges);
+    returns the host array, which must stay alive during the call."""
+    lists = [s.get("edges") for s in states]
+    if all(e is None for e in lists):
+        return None
+    if any(e is None or not np.array_equal(e, lists[0]) for e in lists):
+        raise ValueError("every state needs the same traced edges")
+    e = lists[0]
+    cfg.trace_edges = int(e.shape[0])
+    cfg.edges = e.ctypes.data
+    return e
+
+
 def _chain_state(state: dict, iterations: int, trace_every: int) -> ChainState:
     st = ChainState()
     for k in ("orders", "scores", "best_graphs", "best_scores", "accepted", "trace", "accept_flags",
-              "harvest_feats", "harvest_pairs", "harvest_count", "top_graphs", "top_scores", "top_count"):
+              "harvest_feats", "harvest_pairs", "harvest_count", "top_graphs", "top_scores", "top_count",
+              "edge_trace"):
         v = state.get(k)
         setattr(st, k, None if v is None else v.data_ptr())
     if state.get("harvest_feats") is not None:
@@ -354,11 +377,13 @@ def _chain_state(state: dict, iterations: int, trace_every: int) -> ChainState:
         raise ValueError("trace tensor too small")
     if state.get("accept_flags") is not None and state["accept_flags"].shape[1] < iterations:
         raise ValueError("accept_flags tensor too small")
+    if state.get("edge_trace") is not None and state["edge_trace"].shape[1] < iterations // max(1, trace_every) + 1:
+        raise ValueError("edge_trace tensor too small")
     return st
 
 
 def run_chains_multi(tables, states, iterations: int, seed: int, target: int = 0, first_iteration: int = 0,
-                     trace_every: int = 1, chain_offset: int = 0, sweep_len: int = 0, mlp=None, eps=0.1, stream=None):
+                     trace_every: int = 1, chain_offset: int = 0, sweep_len: int = 0, mlp=None, eps=0.5, stream=None):
     """Advance the chains of several tables in one set of launches (bnos_run_chains_multi)."""
     T = len(tables)
     chains = int(states[0]["orders"].shape[0])
@@ -367,6 +392,7 @@ def run_chains_multi(tables, states, iterations: int, seed: int, target: int = 0
     cfg = _chain_cfg(chains, iterations, seed, target, first_iteration, trace_every, chain_offset, sweep_len,
                      mlp, eps)
     cfg.topk = _state_topk(states)
+    edges = _state_edges(cfg, states)
     hs = (P * T)(*[t.handle.value for t in tables])
     sts = (ChainState * T)(*[_chain_state(s, iterations, trace_every) for s in states])
     _check(_lib.bnos_run_chains_multi(hs, T, ctypes.byref(cfg), sts, _stream(stream)))

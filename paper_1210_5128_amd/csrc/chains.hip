@@ -94,6 +94,10 @@ struct ChainView {
     int32_t *hv_pair;          // [C][hv_cap][2]
     int64_t *hv_count;         // [C]
     int64_t hv_cap;
+    // edges traced per iteration (mixing diagnostics)
+    int n_edges;               // 0 = off
+    const int32_t *edge_cp;    // [n_edges][2] (child, parent), device copy
+    uint32_t *edge_trace;      // [C][trace_len]
     // record of the best distinct graphs
     int topk;                  // 0 = off
     uint64_t *top_graph;       // [C][topk][n]
@@ -357,6 +361,19 @@ __global__ __launch_bounds__(kStepWaves * 64) void k_chain_step(const TabView *_
 #pragma unroll
         for (int j = 0; j < 5; ++j) f[3 + j] = (float)H.nstat[lane * 5 + j];
     }
+    if (H.n_edges > 0) {
+        const int64_t kk = t - H.t_first;
+        if (kk % H.trace_every == 0) {
+            // the current order's greedy graph after this step: the proposal's parents in
+            // the window if accepted, else the cached ones
+            const uint64_t gb = lane < n ? ((acc && in) ? s_bm[lane] : H.node_best[row + lane]) : 0ull;
+            const int ech = lane < H.n_edges ? H.edge_cp[2 * lane] : 0;
+            const int epa = lane < H.n_edges ? H.edge_cp[2 * lane + 1] : 0;
+            const uint64_t gch = (uint64_t)__shfl((unsigned long long)gb, ech, 64);
+            const uint64_t bits = __ballot(lane < H.n_edges && ((gch >> epa) & 1ull));
+            if (lane == 0) H.edge_trace[(int64_t)c * H.trace_len + kk / H.trace_every] = (uint32_t)bits;
+        }
+    }
     int32_t v = 0;
     if (lane < n) {
         v = acc ? H.prop[row + lane] : H.cur[row + lane];
@@ -462,10 +479,12 @@ bnos_status validate_cfg(const bnos_chain_cfg *cfg)
     if (cfg->trace_every < 1) { set_error("trace_every must be >= 1"); return BNOS_E_RANGE; }
     if (cfg->sweep_len < 0) { set_error("sweep_len < 0"); return BNOS_E_RANGE; }
     if (cfg->chain_offset < 0) { set_error("chain_offset < 0"); return BNOS_E_RANGE; }
-    for (int r = 0; r < 3; ++r)
+    for (int r = 0; r < 2; ++r)
         if (cfg->reserved[r] != 0) { set_error("cfg.reserved must be zero"); return BNOS_E_INVALID; }
     if (cfg->proposal != 0 && cfg->proposal != 1) { set_error("proposal must be 0 or 1"); return BNOS_E_INVALID; }
     if (cfg->topk < 0 || cfg->topk > 64) { set_error("topk outside [0, 64]"); return BNOS_E_RANGE; }
+    if (cfg->trace_edges < 0 || cfg->trace_edges > 32) { set_error("trace_edges outside [0, 32]"); return BNOS_E_RANGE; }
+    if (cfg->trace_edges > 0 && !cfg->edges) { set_error("trace_edges > 0 needs edges"); return BNOS_E_INVALID; }
     if (cfg->proposal == 1) {
         if (!mlp_handle_live(cfg->mlp)) { set_error("learned proposal needs a live network handle"); return BNOS_E_STATE; }
         if (!(cfg->eps >= 0.f && cfg->eps <= 1.f)) { set_error("eps outside [0, 1]"); return BNOS_E_RANGE; }
@@ -504,6 +523,16 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
             set_error("topk > 0 needs top_graphs, top_scores and top_count");
             return BNOS_E_INVALID;
         }
+        if (cfg->trace_edges > 0) {
+            if (!st.edge_trace) { set_error("trace_edges > 0 needs edge_trace"); return BNOS_E_INVALID; }
+            for (int e = 0; e < cfg->trace_edges; ++e) {
+                const int ch = cfg->edges[2 * e], pa = cfg->edges[2 * e + 1];
+                if (ch < 0 || ch >= tabs[k]->n || pa < 0 || pa >= tabs[k]->n || ch == pa) {
+                    set_error("traced edge outside the table's nodes");
+                    return BNOS_E_RANGE;
+                }
+            }
+        }
     }
     // scoring steps: the adoption of the starting order (fresh: iteration 0; resume: the
     // saved order, re-scored to rebuild the per-node caches) and one per iteration
@@ -518,6 +547,8 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
     // per-call workspace: descriptors + per table: per-node caches, proposals,
     // windows, work lists, iteration counters
     size_t bytes = sizeof(TabView) * T + sizeof(ChainView) * T + 3 * sizeof(int64_t) * (T + 1) + 256;
+    const size_t edges_off = bytes;
+    bytes += 64 * sizeof(int32_t) + 256;                                        // traced edges
     std::vector<size_t> off(T);
     for (int k = 0; k < T; ++k) {
         const size_t n = tabs[k]->n, cn = (size_t)C * n;
@@ -566,7 +597,7 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
         H.ppos = reinterpret_cast<uint8_t *>(p);
         H.nstat = t->d_nstat;
         H.proposal = cfg->proposal;
-        H.eps = cfg->eps > 0.f ? (double)cfg->eps : 0.1;
+        H.eps = cfg->eps > 0.f ? (double)cfg->eps : 0.5;
         if (cfg->proposal == 1) H.mlp = mlp_view(cfg->mlp);
         else std::memset(&H.mlp, 0, sizeof(H.mlp));
         const bnos_chain_state &st = states[k];
@@ -584,6 +615,9 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
         H.hv_pair = st.harvest_pairs;
         H.hv_count = st.harvest_count;
         H.hv_cap = st.harvest_feats ? st.harvest_cap : 0;
+        H.n_edges = cfg->trace_edges;
+        H.edge_cp = reinterpret_cast<const int32_t *>(ws + edges_off);
+        H.edge_trace = st.edge_trace;
         H.topk = cfg->topk;
         H.top_graph = st.top_graphs;
         H.top_score = st.top_scores;
@@ -622,6 +656,8 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
         hipFree(ws);
     };
 #define CK(call) if ((e = (call)) != hipSuccess) { set_error(std::string(#call) + ": " + hipGetErrorString(e)); cleanup(); return BNOS_E_DEVICE; }
+    if (cfg->trace_edges > 0)
+        CK(hipMemcpy(ws + edges_off, cfg->edges, sizeof(int32_t) * 2 * cfg->trace_edges, hipMemcpyHostToDevice));
     CK(hipMemcpy(d_tv, tv.data(), sizeof(TabView) * T, hipMemcpyHostToDevice));
     CK(hipMemcpy(d_cv, cv.data(), sizeof(ChainView) * T, hipMemcpyHostToDevice));
     CK(hipMemcpy(d_blk, blk_base.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice));

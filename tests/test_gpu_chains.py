@@ -238,6 +238,12 @@ def test_chain_validation(bnos, tiny8):
     with pytest.raises(bnos.BnosError) as e:
         t.run_chains(t.new_chain_state(2, 10, topk=65), 10, 1)
     assert e.value.status == bnos.E_RANGE
+    with pytest.raises(bnos.BnosError) as e:
+        t.run_chains(t.new_chain_state(2, 10, edges=[(1, 0), (w.n, 2)]), 10, 1)
+    assert e.value.status == bnos.E_RANGE
+    with pytest.raises(bnos.BnosError) as e:
+        t.run_chains(t.new_chain_state(2, 10, edges=[(3, 3)]), 10, 1)
+    assert e.value.status == bnos.E_RANGE
 
 
 def test_mixed60_chain_properties(bnos):
@@ -281,3 +287,44 @@ def test_uneven_datasets_in_one_launch_match_one_at_a_time(bnos):
             assert torch.equal(states[k][key], ref[key]), (k, key)
     for t in tabs:
         t.free()
+
+
+def test_edge_trace_matches_oracle_replay(bnos, tiny8):
+    # the traced edge bits are the greedy graph of each chain's current order,
+    # replayed on the oracle from its own accept decisions
+    w, t, orc = tiny8
+    n, K = w.n, w.K
+    edges = [(1, 0), (2, 5), (3, 1), (7, 6), (4, 2), (0, 3), (5, 7)]
+    C, iters, seed, every = 6, 300, 41, 3
+    st = t.new_chain_state(C, iters, trace_every=every, flags=True, edges=edges)
+    t.run_chains(st, iters, seed, trace_every=every)
+    et = st["edge_trace"].cpu().numpy().view(np.uint32)
+    flags = st["accept_flags"].cpu().numpy()
+    compared = 0
+    for c in range(C):
+        res = oracle.run_chain(orc, K, seed, c, iters, target=0, round_f32=True)
+        if not np.array_equal(flags[c, :iters].astype(bool), res["acc"].astype(bool)):
+            continue                       # a near-tie decision went the other way
+        compared += 1
+        cur = list(oracle.initial_order(seed, c, n))
+        for it in range(iters + 1):
+            if it > 0 and res["acc"][it - 1]:
+                a, b = oracle.swap_pair(seed, c, n, it)
+                cur[a], cur[b] = cur[b], cur[a]
+            if it % every:
+                continue
+            best = oracle.score_order(orc, K, cur, round_f32=True)[2]
+            want = sum(1 << e for e, (ch, pa) in enumerate(edges) if (int(best[ch]) >> pa) & 1)
+            assert int(et[c, it // every]) == want, (c, it)
+    assert compared >= C - 1
+    # resumed runs continue the same trace
+    a = t.new_chain_state(C, 120, trace_every=every, edges=edges)
+    t.run_chains(a, 120, seed, trace_every=every)
+    b = dict(a)
+    b["trace"] = torch.zeros((C, 180 // every + 1), dtype=torch.float64, device="cuda")
+    b["edge_trace"] = torch.zeros((C, 180 // every + 1), dtype=torch.int32, device="cuda")
+    t.run_chains(b, 180, seed, first_iteration=120, trace_every=every)
+    torch.cuda.synchronize()
+    whole = et
+    assert np.array_equal(a["edge_trace"].cpu().numpy().view(np.uint32), whole[:, :120 // every + 1])
+    assert np.array_equal(b["edge_trace"].cpu().numpy().view(np.uint32), whole[:, 120 // every:])

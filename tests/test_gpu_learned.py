@@ -235,7 +235,7 @@ def test_trained_network_gains_over_uniform_swaps(bnos):
         s2 = {k: st[k].clone() for k in ("orders", "scores", "best_graphs", "best_scores", "accepted")}
         s2["trace"] = torch.zeros((C, iters + 1), dtype=torch.float64, device="cuda")
         a0 = s2["accepted"].clone()
-        t.run_chains(s2, iters, 21, first_iteration=harvest_iters, mlp=mlp)
+        t.run_chains(s2, iters, 21, first_iteration=harvest_iters, mlp=mlp, eps=0.1)
         tr = s2["trace"].cpu().numpy()
         res[label] = dict(acc=float((s2["accepted"] - a0).sum().item()) / (C * iters), ess=E.ess(tr))
     # measured: acceptance 0.304 vs 0.189, ESS 1,819 vs 1,236, loss 6.44 vs 6.66 nats
