@@ -129,8 +129,7 @@ def bench_chains(bnos, datagen, wname: str, chains: int, iters: int, seed: int =
         dt = time.perf_counter() - t0
         tr = st["trace"].cpu().numpy()
         e = E.ess(tr)
-        out[label] = {"chains": C, "eps": eps if mlp is not None else None, "seconds": dt,
-                      "chain_iterations_per_s": C * iters / dt,
+        out[label] = {"chains": C, "seconds": dt, "chain_iterations_per_s": C * iters / dt,
                       "ess": e, "ess_per_s": e / dt,
                       "accept_rate": float(st["accepted"].sum().item()) / (C * iters),
                       "best_score_max": float(st["best_scores"].max().item()),
