@@ -63,7 +63,11 @@ typedef struct {
     int32_t chunk_steps;   /* scoring blocks stream chunks of chunk_steps * 1024 entries of one node's
                               row; a power of two <= 16 (rows are then padded to a multiple of at
                               least that many steps), or 0 = automatic */
-    int32_t reserved[6];   /* must be zero */
+    int32_t count_mode;    /* 0: one joint histogram per node subset U (|U| <= K+1) serves the |U|
+                              families (i, U \ {i}); 1: one histogram per family.  Same table, bit
+                              for bit; 0 counts about (K+1) times fewer samples.  (0 falls back to 1
+                              when the lnGamma lookup of the build would exceed 256 MB.) */
+    int32_t reserved[5];   /* must be zero */
 } bnos_build_opts;         /* all-zero = defaults */
 
 /*

@@ -31,7 +31,7 @@ i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 
 class BuildOpts(ctypes.Structure):
     _fields_ = [("log_gamma", ctypes.c_double), ("prior_mode", ctypes.c_int32), ("chunk_steps", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("count_mode", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class ChainCfg(ctypes.Structure):
@@ -399,7 +399,7 @@ def run_chains_multi(tables, states, iterations: int, seed: int, target: int = 0
 
 
 def build_score_table(data, arities, K: int, ess: float = 1.0, prior=None, prior_mode: int = 0,
-                      log_gamma: float = 0.0, chunk_steps: int = 0, stream=None) -> Table:
+                      log_gamma: float = 0.0, chunk_steps: int = 0, count_mode: int = 0, stream=None) -> Table:
     """Build the local-score table (host inputs; see bnos_build_score_table)."""
     data = np.ascontiguousarray(data, dtype=np.int8)
     if data.ndim != 2:
@@ -411,6 +411,7 @@ def build_score_table(data, arities, K: int, ess: float = 1.0, prior=None, prior
     opts.log_gamma = log_gamma
     opts.prior_mode = prior_mode
     opts.chunk_steps = chunk_steps
+    opts.count_mode = count_mode
     h = ctypes.c_void_p()
     st = ctypes.c_void_p(0) if stream is None else _stream(stream)
     _check(_lib.bnos_build_score_table(_ptr(data) if N else None, N, n, _ptr(ar), K, ess,

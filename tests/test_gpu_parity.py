@@ -377,3 +377,31 @@ def test_autotune_is_per_batch_bucket(bnos, mixed60):
     # each node moves by a few 1e-7, the per-order sum of 60 nodes by ~1e-6
     np.testing.assert_allclose(after["node_lse"], before["node_lse"], rtol=0, atol=2e-6)
     np.testing.assert_allclose(after["lse"], before["lse"], rtol=0, atol=2e-5)
+
+
+@pytest.mark.parametrize("n,K,N,arities,with_prior", [
+    (8, 3, 200, (2,), False),
+    (20, 4, 1000, (3,), True),
+    (9, 6, 200, (2,), False),
+    (10, 4, 300, (5, 6), True),
+    (64, 2, 129, (2,), False),
+    (1, 0, 50, (3,), False),
+])
+def test_joint_and_family_histograms_give_the_same_table(bnos, n, K, N, arities, with_prior):
+    net = datagen.random_network(n, N, arities, min(3, n - 1), seed=n + 7 * K)
+    prior = datagen.random_prior(n, seed=n) if with_prior else None
+    a = bnos.build_score_table(net.data, net.arities, K, prior=prior, count_mode=0)
+    b = bnos.build_score_table(net.data, net.arities, K, prior=prior, count_mode=1)
+    try:
+        for i in range(n):
+            ma, sa = a.export(i)
+            mb, sb = b.export(i)
+            assert np.array_equal(ma, mb), i
+            assert np.array_equal(sa.view(np.uint32), sb.view(np.uint32)), i
+        orders = datagen.random_orders(n, 4, seed=3)
+        ga, gb = dev_score(a, orders), dev_score(b, orders)
+        for k in ga:
+            assert np.array_equal(ga[k].view(np.uint8), gb[k].view(np.uint8)), k
+    finally:
+        a.free()
+        b.free()
