@@ -670,7 +670,7 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
     CK(hipGetLastError());
     auto one_step = [&](hipStream_t q) -> hipError_t {
         hipLaunchKernelGGL(k_worklist, dim3((unsigned)node_base[T]), dim3(kListThreads), 0, q, d_cv, d_node, T);
-        dim3 grid((unsigned)blk_base[T], groups);
+        dim3 grid((unsigned)((blk_base[T] + kXcds - 1) / kXcds * kXcds), groups);   // padded for xcd_block
         if (bt == 8) hipLaunchKernelGGL(k_score_multi<8>, grid, dim3(kScoreThreads), 0, q, d_tv, d_blk, T);
         else if (bt == 4) hipLaunchKernelGGL(k_score_multi<4>, grid, dim3(kScoreThreads), 0, q, d_tv, d_blk, T);
         else if (bt == 2) hipLaunchKernelGGL(k_score_multi<2>, grid, dim3(kScoreThreads), 0, q, d_tv, d_blk, T);

@@ -106,6 +106,7 @@ ScoreArgs score_args(const TableT *t, const int32_t *orders, int B, double *lse,
 template <int BT>
 static void launch_bt(const ScoreArgs &A, int nblocks_x, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
+    nblocks_x = (nblocks_x + kXcds - 1) / kXcds * kXcds;      // padded for xcd_block
     dim3 grid((unsigned)nblocks_x, (unsigned)((A.B + BT - 1) / BT));
     if (e0) hipExtLaunchKernelGGL(k_score<BT>, grid, dim3(kScoreThreads), 0, st, e0, e1, 0, A);
     else hipLaunchKernelGGL(k_score<BT>, grid, dim3(kScoreThreads), 0, st, A);

@@ -462,6 +462,22 @@ __global__ __launch_bounds__(kScoreThreads) void k_count_tiles(ScoreArgs A, unsi
     }
 }
 
+// Workgroups go to the 8 XCDs round robin by linear id, each XCD with its own
+// L2.  Grids of the scoring kernels have their x extent padded to a multiple of
+// 8; xcd_block maps linear id L to the column x = 8 * (l / G) + L % 8 and the
+// group y = l % G (l = L / 8, G = gridDim.y), so the G groups of orders that read
+// the same rows run back to back on one XCD and share its L2.  A bijection on
+// the padded grid; returns false for the padding columns (x >= real_x).
+constexpr int kXcds = 8;
+__device__ __forceinline__ bool xcd_block(int64_t real_x, int &x, int &y)
+{
+    const int64_t L = blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+    const int64_t l = L / kXcds;
+    x = (int)((l / gridDim.y) * kXcds + L % kXcds);
+    y = (int)(l % gridDim.y);
+    return x < real_x;
+}
+
 // Grid: x = node * chunks + chunk, y = group of BT orders.  With one order
 // per block, x runs over the order's positions from the last one down: the
 // node at the last position has the most predecessors, hence the most tiles
@@ -471,13 +487,15 @@ __global__ __launch_bounds__(kScoreThreads) void k_count_tiles(ScoreArgs A, unsi
 template <int BT>
 __global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
 {
-    int node = blockIdx.x / A.chunks;
-    const int chunk = blockIdx.x - node * A.chunks;
+    int x, y;
+    if (!xcd_block((int64_t)A.n * A.chunks, x, y)) return;
+    int node = x / A.chunks;
+    const int chunk = x - node * A.chunks;
     if (BT == 1) {
-        const int v = A.orders[(int64_t)blockIdx.y * A.n + (A.n - 1 - node)];
+        const int v = A.orders[(int64_t)y * A.n + (A.n - 1 - node)];
         node = (v >= 0 && v < A.n) ? v : node;
     }
-    score_block<BT>(view_of(A), node, chunk, blockIdx.y);
+    score_block<BT>(view_of(A), node, chunk, y);
 }
 
 // Index of the segment holding x, for prefix bases base[0] = 0 < ... < base[T].
@@ -498,12 +516,14 @@ template <int BT>
 __global__ __launch_bounds__(kScoreThreads) void k_score_multi(const TabView *__restrict__ views,
                                                               const int64_t *__restrict__ blk_base, int T)
 {
-    const int k = find_segment(blk_base, T, (int64_t)blockIdx.x);
+    int x, y;
+    if (!xcd_block(blk_base[T], x, y)) return;
+    const int k = find_segment(blk_base, T, (int64_t)x);
     const TabView V = views[k];
-    const int local = (int)((int64_t)blockIdx.x - blk_base[k]);
+    const int local = (int)((int64_t)x - blk_base[k]);
     const int node = local / V.chunks;
     const int chunk = local - node * V.chunks;
-    score_block<BT>(V, node, chunk, blockIdx.y);
+    score_block<BT>(V, node, chunk, y);
 }
 
 constexpr int kMergeWaves = 8;
