@@ -233,20 +233,8 @@ def bench_learned(bnos, datagen, wname: str, chains: int, moves: int, iters: int
     del feats, pairs
     # 3. the 20 most uncertain edges: greedy graphs of the chains' current orders,
     # edges whose frequency over chains is closest to 1/2
-    B = st["orders"].shape[0]
-    lse = torch.empty(B, dtype=torch.float64, device=st["orders"].device)
-    mx = torch.empty_like(lse)
-    best = torch.empty((B, n), dtype=torch.int64, device=lse.device)
-    table.score_orders(st["orders"], lse, mx, best)
-    bm = best.cpu().numpy().view(np.uint64)
-    freq = np.zeros((n, n))
-    for i in range(n):
-        for p in range(n):
-            freq[i, p] = np.mean((bm[:, i] >> np.uint64(p)) & np.uint64(1))
-    cand = sorted(((abs(freq[i, p] - 0.5), i, p) for i in range(n) for p in range(n)
-                   if i != p and 0.0 < freq[i, p] < 1.0))[:20]
-    edges = [(i, p) for _, i, p in cand]
-    out["traced_edges"] = {"count": len(edges), "frequencies": [round(float(freq[i, p]), 4) for i, p in edges]}
+    edges = uncertain_edges(table, st["orders"], n)
+    out["traced_edges"] = len(edges)
     # 4. resume every chain from its harvested state: uniform vs learned, and one uniform chain alone
     base = {k: v for k, v in st.items() if k in ("orders", "scores", "best_graphs", "best_scores", "accepted")}
     runs = [("uniform", None, chains, 0.1)]
@@ -293,6 +281,104 @@ def bench_learned(bnos, datagen, wname: str, chains: int, moves: int, iters: int
                                                               max(out["uniform"]["edge_ess_min_per_s"], 1e-30))
     m.free()
     table.free()
+    return out
+
+
+def uncertain_edges(table, orders, n: int, count: int = 20):
+    """(child, parent) pairs whose frequency over the greedy graphs of these
+    orders (DEVICE int32 [C][n]) is closest to 1/2, at most `count`."""
+    import torch
+    B = orders.shape[0]
+    lse = torch.empty(B, dtype=torch.float64, device=orders.device)
+    mx = torch.empty_like(lse)
+    best = torch.empty((B, n), dtype=torch.int64, device=orders.device)
+    table.score_orders(orders, lse, mx, best)
+    bm = best.cpu().numpy().view(np.uint64)
+    cand = []
+    for i in range(n):
+        for p in range(n):
+            f = float(np.mean((bm[:, i] >> np.uint64(p)) & np.uint64(1)))
+            if i != p and 0.0 < f < 1.0:
+                cand.append((abs(f - 0.5), i, p))
+    return [(i, p) for _, i, p in sorted(cand)[:count]]
+
+
+def bench_generalize(bnos, datagen, train_sets: int, test_sets: int, chains: int = 64, seed: int = 808):
+    """Learned proposal across datasets: one network trained on the accepted moves
+    of uniform chains on `train_sets` members of the uneven family (n ~ U[20,60]),
+    then used on `test_sets` other members (n not seen in training): ESS/s of the
+    score trace and the smallest ESS over 20 uncertain edges, learned vs uniform,
+    every chain resumed from the same burned-in state on the same random streams."""
+    import torch
+    from paper_1210_5128_amd import ess as E
+    t0 = time.perf_counter()
+    feats, pairs, train_n = [], [], []
+    for d in range(train_sets):
+        w = datagen.uneven_workload(d)
+        net, _ = datagen.make(w)
+        t = bnos.build_score_table(net.data, net.arities, w.K)
+        st = t.new_chain_state(chains, 1, trace_every=0, harvest_cap=1024)
+        t.run_chains(st, 6000, seed + d, trace_every=0)
+        torch.cuda.synchronize()
+        cnt = st["harvest_count"].cpu().numpy()
+        feats.append(torch.cat([st["harvest_feats"][c, :int(min(cnt[c], 1024))] for c in range(chains)]))
+        pairs.append(torch.cat([st["harvest_pairs"][c, :int(min(cnt[c], 1024))] for c in range(chains)]))
+        train_n.append(w.n)
+        t.free()
+    harvest_s = time.perf_counter() - t0
+    m = bnos.Mlp()
+    m.set_params(datagen.mlp_params(seed, scale=0.5).astype(np.float32))
+    m.fit_norm(torch.cat([f.reshape(-1, 8) for f in feats]).contiguous())
+    t0 = time.perf_counter()
+    for ep in range(8):
+        for d in range(train_sets):
+            m.train(feats[d], pairs[d], epochs=1, batch=1024, lr=2e-3, seed=seed + 100 * ep + d)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    moves = int(sum(f.shape[0] for f in feats))
+    del feats, pairs
+    tests = []
+    iters, burn = 2000, 4000
+    for d in range(1000, 1000 + test_sets):
+        w = datagen.uneven_workload(d)
+        net, _ = datagen.make(w)
+        t = bnos.build_score_table(net.data, net.arities, w.K)
+        st = t.new_chain_state(chains, 1, trace_every=0)
+        t.run_chains(st, burn, seed + d, trace_every=0)
+        edges = uncertain_edges(t, st["orders"], w.n)
+        rec = {"n": w.n, "N": w.N}
+        for label, mlp in (("uniform", None), ("learned", m)):
+            s2 = {k: st[k].clone() for k in ("orders", "scores", "best_graphs", "best_scores", "accepted")}
+            s2["trace"] = torch.zeros((chains, iters + 1), dtype=torch.float64, device=s2["scores"].device)
+            if edges:
+                s2["edges"] = np.asarray(edges, dtype=np.int32)
+                s2["edge_trace"] = torch.zeros((chains, iters + 1), dtype=torch.int32, device=s2["scores"].device)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            t.run_chains(s2, iters, seed + 7 * d, first_iteration=burn, mlp=mlp)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            e = E.ess(s2["trace"].cpu().numpy())
+            ee = None
+            if edges:
+                et = s2["edge_trace"].cpu().numpy().view(np.uint32)
+                ee = min(E.ess(((et >> np.uint32(k)) & np.uint32(1)).astype(np.float64)) for k in range(len(edges)))
+            rec[label] = {"ess_per_s": e / dt, "edge_ess_min_per_s": None if ee is None else ee / dt}
+        rec["ess_per_s_ratio"] = rec["learned"]["ess_per_s"] / max(rec["uniform"]["ess_per_s"], 1e-30)
+        if edges:
+            rec["edge_ess_min_per_s_ratio"] = (rec["learned"]["edge_ess_min_per_s"] /
+                                               max(rec["uniform"]["edge_ess_min_per_s"], 1e-30))
+        tests.append(rec)
+        t.free()
+    m.free()
+    out = {"train_datasets": train_sets, "train_n": train_n, "harvested_moves": moves, "harvest_s": harvest_s,
+           "train_s": train_s, "chains": chains, "iterations": iters, "tests": tests,
+           "geomean_ess_per_s_ratio": float(np.exp(np.mean([np.log(r["ess_per_s_ratio"]) for r in tests]))),
+           "geomean_edge_ess_min_per_s_ratio": float(np.exp(np.mean(
+               [np.log(r["edge_ess_min_per_s_ratio"]) for r in tests if "edge_ess_min_per_s_ratio" in r])))}
+    print(f"# generalize: {train_sets} training sets, {test_sets} unseen: score ESS/s x"
+          f"{out['geomean_ess_per_s_ratio']:.2f}, min edge ESS/s x{out['geomean_edge_ess_min_per_s_ratio']:.2f}",
+          file=sys.stderr, flush=True)
     return out
 
 
@@ -392,6 +478,9 @@ def main():
     ap.add_argument("--learned-eps", default="0.5,0.1",
                     help="comma-separated weights of the uniform pair in the learned q; the first is the headline")
     ap.add_argument("--learned-workload", default="mixed60")
+    ap.add_argument("--generalize", default="8,4", metavar="TRAIN,TEST",
+                    help="learned proposal trained on TRAIN uneven datasets, evaluated on TEST unseen ones "
+                         "('0' = skip)")
     ap.add_argument("--accuracy", type=int, default=1, metavar="C",
                     help="structure-recovery study on the roc20 workload with C chains per run (0 = skip)")
     ap.add_argument("--uneven", type=int, default=32, metavar="D",
@@ -574,6 +663,9 @@ def main():
         out["uneven"] = bench_uneven(bnos, datagen, args.uneven, 64, args.uneven_iters)
     if args.accuracy:
         out["accuracy"] = bench_accuracy(bnos, datagen, args.accuracy)
+    if args.generalize != "0":
+        tr, te = (int(x) for x in args.generalize.split(","))
+        out["generalize"] = bench_generalize(bnos, datagen, tr, te)
     if args.learned:
         out["learned"] = bench_learned(bnos, datagen, args.learned_workload, args.learned, args.learned_moves,
                                        args.learned_iters, epochs=args.learned_epochs,

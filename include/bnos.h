@@ -209,7 +209,8 @@ bnos_status bnos_mlp_set_params(bnos_mlp m, const float *params, const float *mu
 bnos_status bnos_mlp_get_params(bnos_mlp m, float *params, float *mu, float *sd);
 
 /* mu, sd := per-feature mean and population standard deviation of the rows
- * of feats (DEVICE float [rows][8]); an sd below 1e-6 becomes 1.  Async. */
+ * of feats (DEVICE float [rows][8], 16-byte aligned); an sd below 1e-6
+ * becomes 1.  Async. */
 bnos_status bnos_mlp_fit_norm(bnos_mlp m, const float *feats, int64_t rows, void *stream);
 
 /* logits (DEVICE float [R][n]) of R samples of n nodes (DEVICE float [R][n][8]

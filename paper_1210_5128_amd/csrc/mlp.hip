@@ -89,33 +89,44 @@ __global__ __launch_bounds__(1024) void k_mlp_forward(MlpView P, const float *__
 __global__ __launch_bounds__(1024) void k_feat_norm(const float *__restrict__ feats, int64_t rows,
                                                     float *__restrict__ norm)
 {
-    __shared__ double s1[1024], s2[1024];
+    // one pass: every thread accumulates all 8 features of its rows (two 16-byte loads per row)
+    __shared__ double s1[kF][1024], s2[kF][1024];
+    double a[kF], b[kF];
+#pragma unroll
+    for (int k = 0; k < kF; ++k) a[k] = b[k] = 0.0;
+    const float4 *f4 = reinterpret_cast<const float4 *>(feats);
+    for (int64_t r = threadIdx.x; r < rows; r += 1024) {
+        const float4 lo = f4[2 * r], hi = f4[2 * r + 1];
+        const float v[kF] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+        for (int k = 0; k < kF; ++k) {
+            a[k] += (double)v[k];
+            b[k] += (double)v[k] * (double)v[k];
+        }
+    }
+#pragma unroll
     for (int k = 0; k < kF; ++k) {
-        double a = 0.0, b = 0.0;
-        for (int64_t r = threadIdx.x; r < rows; r += 1024) {
-            const double x = feats[r * kF + k];
-            a += x;
-            b += x * x;
-        }
-        s1[threadIdx.x] = a;
-        s2[threadIdx.x] = b;
-        __syncthreads();
-        for (int w = 512; w >= 1; w >>= 1) {
-            if (threadIdx.x < w) {
-                s1[threadIdx.x] += s1[threadIdx.x + w];
-                s2[threadIdx.x] += s2[threadIdx.x + w];
+        s1[k][threadIdx.x] = a[k];
+        s2[k][threadIdx.x] = b[k];
+    }
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if (threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < kF; ++k) {
+                s1[k][threadIdx.x] += s1[k][threadIdx.x + w];
+                s2[k][threadIdx.x] += s2[k][threadIdx.x + w];
             }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            const double mu = rows ? s1[0] / (double)rows : 0.0;
-            double var = rows ? s2[0] / (double)rows - mu * mu : 1.0;
-            double sd = var > 0 ? sqrt(var) : 0.0;
-            if (!(sd > 1e-6)) sd = 1.0;
-            norm[k] = (float)mu;
-            norm[kF + k] = (float)(1.0 / sd);
-        }
         __syncthreads();
+    }
+    if (threadIdx.x < kF) {
+        const int k = threadIdx.x;
+        const double mu = rows ? s1[k][0] / (double)rows : 0.0;
+        double var = rows ? s2[k][0] / (double)rows - mu * mu : 1.0;
+        double sd = var > 0 ? sqrt(var) : 0.0;
+        if (!(sd > 1e-6)) sd = 1.0;
+        norm[k] = (float)mu;
+        norm[kF + k] = (float)(1.0 / sd);
     }
 }
 
@@ -484,6 +495,7 @@ extern "C" bnos_status bnos_mlp_fit_norm(bnos_mlp h, const float *feats, int64_t
     MlpT *m = reinterpret_cast<MlpT *>(h);
     if (!mlp_live(m)) { set_error("invalid network handle"); return BNOS_E_STATE; }
     if (!feats || rows < 1) { set_error("need at least one feature row"); return BNOS_E_INVALID; }
+    if (reinterpret_cast<uintptr_t>(feats) % 16) { set_error("feats must be 16-byte aligned"); return BNOS_E_INVALID; }
     BNOS_HIP(hipSetDevice(m->device));
     hipLaunchKernelGGL(k_feat_norm, dim3(1), dim3(1024), 0, reinterpret_cast<hipStream_t>(stream), feats, rows, m->d_norm);
     BNOS_HIP(hipGetLastError());
