@@ -349,7 +349,14 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     }
 
     {
-        const Acc r = acc_wave_reduce_scatter<BT>(a, lane);
+        // a wavefront that folded nothing (no needed tile, or no consistent entry)
+        // holds identity states: skip the reduction, whose result would be the identity
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < BT; ++j) any |= a[j].m != -INFINITY;
+        Acc r;
+        if (__ballot(any) != 0ull) r = acc_wave_reduce_scatter<BT>(a, lane);
+        else acc_init(r);
         if ((lane & (64 / BT - 1)) == 0) {
             const int j = lane / (64 / BT);
             s_red[wave][j].m = r.m;
