@@ -1,0 +1,84 @@
+"""Host-side validation of the C ABI (no GPU needed): every invalid argument is
+rejected with its documented status before any device work."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1210_5128_amd import bnos as B
+
+
+def build(data, arities, K, **kw):
+    return B.build_score_table(np.asarray(data, dtype=np.int8), arities, K, **kw)
+
+
+def status_of(fn):
+    with pytest.raises(B.BnosError) as e:
+        fn()
+    assert B._lib.bnos_last_error()          # a message is left for the caller
+    return e.value.status
+
+
+def test_build_argument_errors():
+    d = np.zeros((6, 3), dtype=np.int8)
+    assert status_of(lambda: build(d, [2, 2, 2], 3)) == B.E_RANGE                       # K > n - 1
+    assert status_of(lambda: build(np.zeros((4, 65)), [2] * 65, 1)) == B.E_RANGE        # n > 64
+    bad = d.copy()
+    bad[3, 2] = 2
+    assert status_of(lambda: build(bad, [2, 2, 2], 1)) == B.E_INVALID                   # state >= arity
+    bad[3, 2] = -1
+    assert status_of(lambda: build(bad, [2, 2, 2], 1)) == B.E_INVALID                   # negative state
+    assert status_of(lambda: build(d, [2, 0, 2], 1)) == B.E_RANGE                       # arity 0
+    assert status_of(lambda: build(d, [2, 2, 2], 1, ess=0.0)) == B.E_INVALID
+    assert status_of(lambda: build(d, [2, 2, 2], 1, ess=float("nan"))) == B.E_INVALID
+    assert status_of(lambda: build(d, [2, 2, 2], 1, log_gamma=float("inf"))) == B.E_INVALID
+    pr = np.zeros((3, 3), np.float32)
+    pr[0, 1] = np.nan
+    assert status_of(lambda: build(d, [2, 2, 2], 1, prior=pr)) == B.E_INVALID           # NaN prior
+    pr[0, 1] = 1.5
+    assert status_of(lambda: build(d, [2, 2, 2], 1, prior=pr)) == B.E_INVALID           # w outside [-1, 1]
+    pr[0, 1] = -0.2
+    assert status_of(lambda: build(d, [2, 2, 2], 1, prior=pr, prior_mode=1)) == B.E_INVALID   # R outside [0, 1]
+    assert status_of(lambda: build(d, [2, 2, 2], 1, prior_mode=2)) == B.E_INVALID
+    assert status_of(lambda: build(d, [2, 2, 2], 1, chunk_steps=3)) == B.E_RANGE
+    assert status_of(lambda: build(d, [2, 2, 2], 1, chunk_steps=32)) == B.E_RANGE
+    assert status_of(lambda: build(d, [2, 2, 2], 1, count_mode=2)) == B.E_INVALID
+    big = np.zeros((2, 6), dtype=np.int8)
+    assert status_of(lambda: build(big, [255] * 6, 2)) == B.E_RANGE                     # q * r above 16384
+
+
+def test_null_pointer_errors():
+    h = ctypes.c_void_p()
+    ar = np.array([2, 2], np.int32)
+    st = B._lib.bnos_build_score_table(None, 5, 2, B._ptr(ar), 1, 1.0, None, None, None, ctypes.byref(h))
+    assert st == B.E_INVALID                                                             # data NULL with N > 0
+    d = np.zeros((5, 2), np.int8)
+    st = B._lib.bnos_build_score_table(B._ptr(d), 5, 2, None, 1, 1.0, None, None, None, ctypes.byref(h))
+    assert st == B.E_INVALID                                                             # arities NULL
+    st = B._lib.bnos_build_score_table(B._ptr(d), 5, 2, B._ptr(ar), 1, 1.0, None, None, None, None)
+    assert st == B.E_INVALID                                                             # out NULL
+    opts = B.BuildOpts()
+    opts.reserved[0] = 1
+    st = B._lib.bnos_build_score_table(B._ptr(d), 5, 2, B._ptr(ar), 1, 1.0, None, ctypes.byref(opts), None,
+                                       ctypes.byref(h))
+    assert st == B.E_INVALID                                                             # reserved not zero
+
+
+def test_stale_handles_are_rejected():
+    fake = B.Table(0x1234560, 4, 2)          # never returned by the library
+    assert status_of(lambda: fake.info()) == B.E_STATE
+    assert status_of(lambda: fake.score_order(np.arange(4, dtype=np.int32))) == B.E_STATE
+    assert status_of(lambda: fake.export(0)) == B.E_STATE
+    assert status_of(lambda: fake.tile_skip(True)) == B.E_STATE
+    fake._h = None                           # nothing for __del__ to free
+    # chain configuration errors come first
+    bad = B.ChainCfg()
+    assert B._lib.bnos_run_chains(ctypes.c_void_p(0x1234560), ctypes.byref(bad), ctypes.byref(B.ChainState()),
+                                  None) == B.E_RANGE                  # chains = 0
+    cfg = B.ChainCfg()
+    cfg.chains, cfg.trace_every = 1, 1
+    st = B.ChainState()
+    assert B._lib.bnos_run_chains(ctypes.c_void_p(0x1234560), ctypes.byref(cfg), ctypes.byref(st), None) == B.E_STATE
+    assert B._lib.bnos_mlp_set_params(ctypes.c_void_p(0x7654320), None, None, None) == B.E_STATE
+    B._lib.bnos_table_free(ctypes.c_void_p(0x1234560))     # a no-op, not a crash
+    B._lib.bnos_mlp_free(ctypes.c_void_p(0x7654320))
