@@ -587,10 +587,10 @@ def main():
     tuned = {}
     for Bq in ([] if args.chunk_steps else sorted({B, args.batched_check} - {0})):
         o = torch.from_numpy(datagen.random_orders(n, Bq, seed=900 + Bq)).to(dev)
-        cs, bt, ms = table.autotune(o, reps=20 if Bq < 64 else 3, stream=stream)
-        tuned[str(Bq)] = {"chunk_steps": cs, "orders_per_block": bt, "tune_ms_per_launch": ms}
-        print(f"# autotune B={Bq}: chunk {cs}x1024 entries, {bt} orders/block, {ms * 1e3:.1f} us",
-              file=sys.stderr, flush=True)
+        cs, bt, g, ms = table.autotune(o, reps=20 if Bq < 64 else 3, stream=stream)
+        tuned[str(Bq)] = {"gather": bool(g), "chunk_steps": cs, "orders_per_block": bt, "tune_ms_per_launch": ms}
+        print(f"# autotune B={Bq}: " + ("gather pass" if g else f"chunk {cs}x1024 entries, {bt} orders/block") +
+              f", {ms * 1e3:.1f} us", file=sys.stderr, flush=True)
     if args.chunk_steps:
         tuned = {"fixed_chunk_steps": args.chunk_steps}
     rf = r = None

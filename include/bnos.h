@@ -110,16 +110,29 @@ bnos_status bnos_table_info(bnos_table t, int32_t *n, int32_t *K, int64_t *entri
 /*
  * Autotuner: times scoring launches of the B orders (DEVICE int32 [B][n]) for
  * every chunk length (powers of two dividing the row padding) and every
- * number of orders per block (1, 2, 4, 8, at most B), `reps` launches each
- * after one warm-up, and keeps the fastest pair for this table and batch size
- * (batch sizes are bucketed as 1, 2-3, 4-7, 8-15, 16+).  Outputs (may be
- * NULL): the chosen chunk steps and orders per block, and its mean time per
- * launch in ms.  The chunk length changes the order in which partial sums
- * are combined, so log-sum-exp values move in the last bits; argmax parent
- * sets are unaffected.  Synchronous on `stream`.
+ * number of orders per block (1, 2, 4, 8, at most B), and, when K <= 4, the
+ * gather pass (each block enumerates the consistent parent sets of a node
+ * with a given top member and reads only their scores, at their ranks in the
+ * row: Alg. 2's traversal on the dense table), `reps` launches each after one
+ * warm-up, and keeps the fastest for this table and batch size (batch sizes
+ * are bucketed as 1, 2-3, 4-7, 8-15, 16+).  Outputs (may be NULL): the chosen
+ * chunk steps and orders per block of the streaming pass, whether the gather
+ * pass won (1) or not (0), and the mean time per launch in ms.  Both passes and
+ * every shape give the same argmax parent sets; log-sum-exp values move in the
+ * last bits with the order of the partial sums.  Synchronous on `stream`.
  */
 bnos_status bnos_table_autotune(bnos_table t, const int32_t *orders, int32_t B, int32_t reps, void *stream,
-                                int32_t *chunk_steps, int32_t *orders_per_block, double *ms_per_launch);
+                                int32_t *chunk_steps, int32_t *orders_per_block, int32_t *gather,
+                                double *ms_per_launch);
+
+/*
+ * Fix the launch of scoring batches of B orders (B's bucket, as above):
+ * gather = 1 selects the gather pass (needs K <= 4); otherwise the streaming
+ * pass with chunk_steps (0 = the build's choice) and orders_per_block (1, 2,
+ * 4 or 8; 0 = the default rule).  Waits for launches in flight.
+ */
+bnos_status bnos_table_set_launch(bnos_table t, int32_t B, int32_t gather, int32_t chunk_steps,
+                                  int32_t orders_per_block);
 
 /*
  * Copy node `node`'s entries to host arrays masks[S], scores[S] (S from

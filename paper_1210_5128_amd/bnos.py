@@ -73,7 +73,8 @@ _SIGS = {
     "bnos_table_timing": (i32, [P, i32]),
     "bnos_table_tile_skip": (i32, [P, i32]),
     "bnos_table_count_tiles": (i32, [P, P, i32, P, P]),
-    "bnos_table_autotune": (i32, [P, P, i32, i32, P, P, P, P]),
+    "bnos_table_autotune": (i32, [P, P, i32, i32, P, P, P, P, P]),
+    "bnos_table_set_launch": (i32, [P, i32, i32, i32, i32]),
     "bnos_table_timing_read": (i32, [P, P, P, P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -235,11 +236,17 @@ class Table:
         _check(_lib.bnos_run_chains(self._h, ctypes.byref(cfg), ctypes.byref(st), _stream(stream)))
 
     def autotune(self, orders, reps: int = 5, stream=None):
-        """Pick chunk length and orders per block for this batch size (bnos_table_autotune)."""
-        cs, bt, ms = i32(), i32(), f64()
+        """Pick the launch for this batch size (bnos_table_autotune):
+        -> (chunk steps, orders per block, gather pass chosen, ms per launch)."""
+        cs, bt, g, ms = i32(), i32(), i32(), f64()
         _check(_lib.bnos_table_autotune(self._h, _dptr(orders), int(orders.shape[0]), reps, _stream(stream),
-                                        ctypes.byref(cs), ctypes.byref(bt), ctypes.byref(ms)))
-        return cs.value, bt.value, ms.value
+                                        ctypes.byref(cs), ctypes.byref(bt), ctypes.byref(g), ctypes.byref(ms)))
+        return cs.value, bt.value, g.value, ms.value
+
+    def set_launch(self, B: int, gather: bool = False, chunk_steps: int = 0, orders_per_block: int = 0):
+        """Fix the scoring launch for batches of B orders (bnos_table_set_launch)."""
+        _check(_lib.bnos_table_set_launch(self._h, int(B), int(bool(gather)), int(chunk_steps),
+                                          int(orders_per_block)))
 
     def tile_skip(self, enable: bool):
         _check(_lib.bnos_table_tile_skip(self._h, int(enable)))

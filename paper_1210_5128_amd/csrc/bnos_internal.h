@@ -68,6 +68,7 @@ struct TableT {
     // autotuned per batch-size bucket (1, 2-3, 4-7, 8-15, 16+); 0 = default
     int tuned_bt[5] = {0, 0, 0, 0, 0};   // orders per scoring block
     int tuned_cs[5] = {0, 0, 0, 0, 0};   // chunk length in 1024-entry steps
+    int tuned_gather[5] = {0, 0, 0, 0, 0};   // 1: score by enumerating the consistent sets (K <= 4)
 
     int64_t device_bytes() const;
     static int bucket(int B) { return B >= 16 ? 4 : (B >= 8 ? 3 : (B >= 4 ? 2 : (B >= 2 ? 1 : 0))); }
@@ -83,10 +84,13 @@ struct TableT {
         return B >= 8 ? pad_steps * 1024 : chunk_entries;
     }
     int chunks_for(int B) const { return (int)(S_pad / chunk_entries_for(B)); }
+    // partials of one launch: [B][chunks][n], with n slots per order in gather mode
     int64_t workspace_bytes_for(int B) const
     {
-        return (int64_t)B * n * chunks_for(B) * (int64_t)sizeof(Partial);
+        const int c = chunks_for(B) > n ? chunks_for(B) : n;
+        return (int64_t)B * n * c * (int64_t)sizeof(Partial);
     }
+    bool gather_for(int B) const { return K <= 4 && tuned_gather[bucket(B)] != 0; }
 };
 
 constexpr uint32_t kMagic = 0xB0A5C0DEu;

@@ -28,6 +28,106 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_merge(ScoreArgs A)
     }
 }
 
+// Gather pass: see the comment at kGatherMaxK (score_device.h).
+__global__ __launch_bounds__(kScoreThreads) void k_gather(ScoreArgs A, const int64_t *__restrict__ nsets, int K)
+{
+    __shared__ int64_t s_w[kGatherMaxK][64];
+    __shared__ uint64_t s_nb[64];
+    __shared__ int s_p;
+    __shared__ Acc s_red[kScoreThreads / 64];
+    const int n = A.n;
+    const int node = blockIdx.x / n;
+    const int sub = blockIdx.x - node * n;
+    const int ob = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    if (wave == 0) {
+        bool valid;
+        const uint64_t pred = wave_pred(A.orders + (int64_t)ob * n, n, node, lane, valid);
+        if (lane < n && ((pred >> lane) & 1ull)) {
+            const int i = __popcll(pred & ((1ull << lane) - 1ull));       // rank among the predecessors
+            const int slot = lane < node ? lane : lane - 1;
+#pragma unroll
+            for (int t = 0; t < kGatherMaxK; ++t) s_w[t][i] = t < K ? nsets[slot * 8 + (K - t)] : 0;
+            s_nb[i] = 1ull << lane;
+        }
+        if (lane == 0) s_p = __popcll(pred);
+    }
+    __syncthreads();
+    const int p = s_p;
+    const float *row = A.scores + (int64_t)node * A.S_pad;
+    Acc a;
+    acc_init(a);
+    if (sub == 0) {
+        if (threadIdx.x == 0) acc_push(a, row[0], 0ull);                   // the empty set
+    } else if (K >= 1 && sub - 1 < p) {
+        const int i0 = sub - 1;
+        const int64_t base = s_w[0][i0];
+        const uint64_t m0 = s_nb[i0];
+        if (threadIdx.x == 0) acc_push(a, row[base], m0);                  // {P[i0]}
+        if (K >= 2)
+            for (int x = threadIdx.x; x < i0; x += kScoreThreads)           // {P[i0], P[x]}
+                acc_push(a, row[base + s_w[1][x]], m0 | s_nb[x]);
+        if (K >= 3)
+            for (int q = threadIdx.x; q < i0 * (i0 - 1) / 2; q += kScoreThreads) {
+                int x, y;
+                tri_unrank(q, x, y);
+                acc_push(a, row[base + s_w[1][x] + s_w[2][y]], m0 | s_nb[x] | s_nb[y]);
+            }
+        if (K >= 4)
+            for (int x = 2 + wave; x < i0; x += kScoreThreads / 64) {       // second member, by wavefront
+                const int64_t bx = base + s_w[1][x];
+                const uint64_t mx = m0 | s_nb[x];
+                for (int q = lane; q < x * (x - 1) / 2; q += 64) {
+                    int y, z;
+                    tri_unrank(q, y, z);
+                    acc_push(a, row[bx + s_w[2][y] + s_w[3][z]], mx | s_nb[y] | s_nb[z]);
+                }
+            }
+    }
+    // wavefront butterfly (skipped when nothing was folded), then the waves in order
+    Acc r;
+    if (__ballot(a.m != -INFINITY) != 0ull) {
+        Acc one[1] = {a};
+        r = acc_wave_reduce_scatter<1>(one, lane);
+    } else {
+        acc_init(r);
+    }
+    if (lane == 0) {
+        s_red[wave].m = r.m;
+        s_red[wave].s = r.s;
+        s_red[wave].best = r.best;
+        s_red[wave].sec = r.sec;
+        s_red[wave].bm = r.bm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Acc t;
+        t.m = s_red[0].m;
+        t.s = s_red[0].s;
+        t.best = s_red[0].best;
+        t.sec = s_red[0].sec;
+        t.bm = s_red[0].bm;
+#pragma unroll
+        for (int w = 1; w < kScoreThreads / 64; ++w) {
+            Acc o;
+            o.m = s_red[w].m;
+            o.s = s_red[w].s;
+            o.best = s_red[w].best;
+            o.sec = s_red[w].sec;
+            o.bm = s_red[w].bm;
+            acc_merge(t, o);
+        }
+        Partial pt;
+        pt.m = t.m;
+        pt.s = t.s;
+        pt.best = t.best;
+        pt.second = t.sec;
+        pt.bmask = t.bm;
+        A.part[((int64_t)ob * n + sub) * n + node] = pt;
+    }
+}
+
 // ------------------------------------------------------------------ host side
 
 // Orders per block: a block folds every streamed entry into this many order states.
@@ -136,13 +236,37 @@ bnos_status launch_stream(TableT *t, const ScoreArgs &A, hipStream_t st, int bt)
     return BNOS_OK;
 }
 
+// The gather pass (k_gather) over B orders; A.chunks becomes n (one partial
+// slot per top member plus the empty set).  Timed when enabled.
+static bnos_status launch_gather(TableT *t, ScoreArgs &A, hipStream_t st)
+{
+    bnos_status s;
+    A.chunks = t->n;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (t->timing) {
+        if ((s = next_events(t, e0, e1)) != BNOS_OK) return s;
+    }
+    dim3 grid((unsigned)(t->n * t->n), (unsigned)A.B);
+    if (e0) hipExtLaunchKernelGGL(k_gather, grid, dim3(kScoreThreads), 0, st, e0, e1, 0, A, t->d_nsets, t->K);
+    else hipLaunchKernelGGL(k_gather, grid, dim3(kScoreThreads), 0, st, A, t->d_nsets, t->K);
+    BNOS_HIP(hipGetLastError());
+    if (t->timing) {
+        if (t->ev_passes.size() <= t->ev_used) t->ev_passes.resize(t->ev_used + 1);
+        t->ev_passes[t->ev_used] = 0;
+        t->ev_used++;
+    }
+    return BNOS_OK;
+}
+
 static bnos_status score_impl(TableT *t, const int32_t *orders, int B, double *lse, double *maxs,
                               uint64_t *best, double *node_lse, float *node_second, hipStream_t st)
 {
     bnos_status s = ensure_workspace(t, B);
     if (s != BNOS_OK) return s;
     ScoreArgs A = score_args(t, orders, B, lse, maxs, best, node_lse, node_second);
-    if ((s = launch_stream(t, A, st, 0)) != BNOS_OK) return s;
+    if (t->gather_for(B)) s = launch_gather(t, A, st);
+    else s = launch_stream(t, A, st, 0);
+    if (s != BNOS_OK) return s;
     hipLaunchKernelGGL(k_merge, dim3(B), dim3(kMergeWaves * 64), 0, st, A);
     BNOS_HIP(hipGetLastError());
     return BNOS_OK;
@@ -281,7 +405,8 @@ extern "C" bnos_status bnos_table_timing_read(bnos_table h, double *total_ms, in
 }
 
 extern "C" bnos_status bnos_table_autotune(bnos_table h, const int32_t *orders, int32_t B, int32_t reps, void *stream,
-                                           int32_t *chunk_steps, int32_t *orders_per_block, double *ms_per_launch)
+                                           int32_t *chunk_steps, int32_t *orders_per_block, int32_t *gather,
+                                           double *ms_per_launch)
 {
     TableT *t = reinterpret_cast<TableT *>(h);
     if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
@@ -291,7 +416,8 @@ extern "C" bnos_status bnos_table_autotune(bnos_table h, const int32_t *orders, 
     BNOS_HIP(hipSetDevice(t->device));
     BNOS_HIP(hipDeviceSynchronize());
     const int bk = TableT::bucket(B);
-    const int old_cs = t->tuned_cs[bk], old_bt = t->tuned_bt[bk];
+    const int old_cs = t->tuned_cs[bk], old_bt = t->tuned_bt[bk], old_g = t->tuned_gather[bk];
+    t->tuned_gather[bk] = 0;
     const bool old_timing = t->timing;
     t->timing = false;
     double *d_out = nullptr;
@@ -326,6 +452,27 @@ extern "C" bnos_status bnos_table_autotune(bnos_table h, const int32_t *orders, 
             }
         }
     }
+    // the gather pass (enumerating the consistent sets), where the table allows it
+    int best_g = 0;
+    if (t->K <= kGatherMaxK && e == hipSuccess && s == BNOS_OK) {
+        t->tuned_cs[bk] = best_cs;
+        if ((s = ensure_workspace(t, B)) == BNOS_OK) {
+            ScoreArgs A = score_args(t, orders, B, d_out, d_out + B, d_best, nullptr, nullptr);
+            for (int r = 0; r <= reps && s == BNOS_OK; ++r) {
+                if (r == 1) e = hipEventRecord(e0, st);
+                if ((s = launch_gather(t, A, st)) != BNOS_OK) break;
+                hipLaunchKernelGGL(k_merge, dim3(B), dim3(kMergeWaves * 64), 0, st, A);
+            }
+            if (e == hipSuccess && s == BNOS_OK) e = hipEventRecord(e1, st);
+            if (e == hipSuccess && s == BNOS_OK) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess && s == BNOS_OK) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && s == BNOS_OK && ms / reps < best_ms) {
+                best_ms = ms / reps;
+                best_g = 1;
+            }
+        }
+    }
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
     hipFree(d_out);
@@ -334,14 +481,43 @@ extern "C" bnos_status bnos_table_autotune(bnos_table h, const int32_t *orders, 
     if (s != BNOS_OK || e != hipSuccess) {
         t->tuned_cs[bk] = old_cs;
         t->tuned_bt[bk] = old_bt;
+        t->tuned_gather[bk] = old_g;
         if (s == BNOS_OK) { set_error(std::string("autotune: ") + hipGetErrorString(e)); s = BNOS_E_DEVICE; }
         return s;
     }
     t->tuned_cs[bk] = best_cs;
     t->tuned_bt[bk] = best_bt;
+    t->tuned_gather[bk] = best_g;
     if ((s = ensure_workspace(t, B)) != BNOS_OK) return s;
     if (chunk_steps) *chunk_steps = best_cs;
     if (orders_per_block) *orders_per_block = best_bt;
+    if (gather) *gather = best_g;
     if (ms_per_launch) *ms_per_launch = best_ms;
     return BNOS_OK;
+}
+
+extern "C" bnos_status bnos_table_set_launch(bnos_table h, int32_t B, int32_t gather, int32_t chunk_steps,
+                                             int32_t orders_per_block)
+{
+    TableT *t = reinterpret_cast<TableT *>(h);
+    if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
+    if (B < 1 || B > (1 << 20)) { set_error("B outside [1, 2^20]"); return BNOS_E_RANGE; }
+    if (gather != 0 && gather != 1) { set_error("gather must be 0 or 1"); return BNOS_E_INVALID; }
+    if (gather && t->K > kGatherMaxK) { set_error("the gather pass needs K <= 4"); return BNOS_E_RANGE; }
+    if (chunk_steps != 0 && (chunk_steps < 1 || chunk_steps > t->pad_steps || (chunk_steps & (chunk_steps - 1)) != 0)) {
+        set_error("chunk_steps must be 0 or a power of two dividing the row padding");
+        return BNOS_E_RANGE;
+    }
+    if (orders_per_block != 0 && orders_per_block != 1 && orders_per_block != 2 && orders_per_block != 4 &&
+        orders_per_block != 8) {
+        set_error("orders_per_block must be 0, 1, 2, 4 or 8");
+        return BNOS_E_RANGE;
+    }
+    BNOS_HIP(hipSetDevice(t->device));
+    BNOS_HIP(hipDeviceSynchronize());        // launches in flight keep their shapes and workspace
+    const int bk = TableT::bucket(B);
+    t->tuned_gather[bk] = gather;
+    t->tuned_cs[bk] = chunk_steps;
+    t->tuned_bt[bk] = orders_per_block;
+    return ensure_workspace(t, B);
 }

@@ -533,6 +533,31 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_multi(const TabView *__
     score_block<BT>(V, node, chunk, y);
 }
 
+// ------------------------------------------------------------------ gather scoring
+//
+// The predecessor-set enumeration of the paper's parent-set traversal, on the
+// dense table: instead of streaming a node's whole row and testing every mask,
+// a block enumerates the consistent parent sets themselves (the subsets of the
+// node's predecessors with at most K members, K <= 4) and reads only their
+// scores, at the set's rank in the row.  Ranks: the row holds the masks over the
+// n-1 slots with <= K bits in ascending order, so a set with slots
+// b_0 > b_1 > ... has rank sum_t nsets[b_t][K - t]; with the predecessors'
+// slots P[0] < P[1] < ... the weights w_t[i] = nsets[P[i]][K - t] make a rank
+// a sum of table lookups.  Block (x = node * n + s, y = order): s = 0 takes the
+// empty set, s = i0 + 1 the sets whose top member is P[i0]; each writes one
+// partial (order, s, node) in the layout k_merge reads with chunks = n.
+constexpr int kGatherMaxK = 4;
+
+// pair index q -> (a > b) with q = a (a - 1) / 2 + b
+__device__ __forceinline__ void tri_unrank(int q, int &a, int &b)
+{
+    int x = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)q)) * 0.5f);
+    if (x * (x - 1) / 2 > q) --x;
+    if ((x + 1) * x / 2 <= q) ++x;
+    a = x;
+    b = q - x * (x - 1) / 2;
+}
+
 constexpr int kMergeWaves = 8;
 
 __device__ __forceinline__ Acc load_partial(const Partial *p)

@@ -361,11 +361,11 @@ def test_autotune_is_per_batch_bucket(bnos, mixed60):
     o1 = torch.from_numpy(datagen.random_orders(w.n, 1, seed=70)).cuda()
     o20 = torch.from_numpy(datagen.random_orders(w.n, 20, seed=71)).cuda()
     before = dev_score(t, o20.cpu().numpy())
-    cs1, bt1, ms1 = t.autotune(o1, reps=2)
-    assert cs1 in (1, 2, 4, 8, 16) and bt1 == 1 and ms1 > 0
+    cs1, bt1, g1, ms1 = t.autotune(o1, reps=2)
+    assert cs1 in (1, 2, 4, 8, 16) and bt1 == 1 and g1 in (0, 1) and ms1 > 0
     single = dev_score(t, o1.cpu().numpy())
-    cs20, bt20, ms20 = t.autotune(o20, reps=2)
-    assert cs20 in (1, 2, 4, 8, 16) and bt20 in (1, 2, 4, 8) and ms20 > 0
+    cs20, bt20, g20, ms20 = t.autotune(o20, reps=2)
+    assert cs20 in (1, 2, 4, 8, 16) and bt20 in (1, 2, 4, 8) and g20 in (0, 1) and ms20 > 0
     # tuning the 16+ bucket leaves the single-order launch as it was
     again = dev_score(t, o1.cpu().numpy())
     for k in single:
@@ -405,3 +405,53 @@ def test_joint_and_family_histograms_give_the_same_table(bnos, n, K, N, arities,
     finally:
         a.free()
         b.free()
+
+
+@pytest.mark.parametrize("n,K,N,arities", [
+    (8, 3, 200, (2,)), (20, 4, 1000, (3,)), (64, 2, 129, (2,)), (7, 1, 60, (2, 3)), (5, 0, 40, (2,)),
+])
+def test_gather_pass_matches_streaming_and_oracle(bnos, n, K, N, arities):
+    net = datagen.random_network(n, N, arities, min(3, n - 1), seed=3 * n + K)
+    t = bnos.build_score_table(net.data, net.arities, K)
+    orc = oracle.build_table(net.data, net.arities, K)
+    try:
+        orders = datagen.random_orders(n, 6, seed=11 + n)
+        stream = dev_score(t, orders)
+        t.set_launch(6, gather=True)
+        got = dev_score(t, orders)
+        assert check_orders_against_oracle(got, orc, K, orders) == 0
+        assert np.array_equal(got["best"], stream["best"])
+        assert np.array_equal(got["node_second"].view(np.uint32), stream["node_second"].view(np.uint32))
+        np.testing.assert_allclose(got["lse"], stream["lse"], rtol=1e-9)
+        again = dev_score(t, orders)                     # deterministic
+        for k in got:
+            assert np.array_equal(got[k].view(np.uint8), again[k].view(np.uint8)), k
+        bad = orders.copy()
+        bad[2, 0] = bad[2, 1]                             # not a permutation
+        b = dev_score(t, bad)
+        assert np.isnan(b["lse"][2]) and np.all(b["best"][2] == 0)
+        assert np.array_equal(b["best"][[0, 1, 3, 4, 5]], got["best"][[0, 1, 3, 4, 5]])
+    finally:
+        t.free()
+
+
+def test_gather_pass_on_the_60_node_table(bnos, mixed60):
+    w, net, prior, t = mixed60
+    orders = datagen.random_orders(w.n, 3, seed=77)
+    t.set_launch(3, gather=False)
+    stream = dev_score(t, orders)
+    t.set_launch(3, gather=True)
+    got = dev_score(t, orders)
+    t.set_launch(3, gather=False)
+    assert np.array_equal(got["best"], stream["best"])
+    np.testing.assert_allclose(got["node_lse"], stream["node_lse"], rtol=1e-9)
+    assert np.array_equal(got["node_second"].view(np.uint32), stream["node_second"].view(np.uint32))
+
+
+def test_gather_needs_small_K(bnos):
+    net = datagen.random_network(8, 50, (2,), 3, seed=1)
+    t = bnos.build_score_table(net.data, net.arities, 5)
+    with pytest.raises(bnos.BnosError) as e:
+        t.set_launch(1, gather=True)
+    assert e.value.status == bnos.E_RANGE
+    t.free()
