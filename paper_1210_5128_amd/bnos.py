@@ -4,6 +4,13 @@ Argument marshalling only: every step of table build and order scoring runs
 in the library's HIP kernels.  Device buffers and streams come from PyTorch
 (``tensor.data_ptr()``, ``torch.cuda.current_stream().cuda_stream``).
 Importing this module loads the library and raises if it is missing.
+
+PyTorch is imported before the library is opened.  A PyTorch ROCm wheel
+carries its own HIP and HSA runtimes under the same sonames as the system's;
+with PyTorch's copy already mapped, ``libbnos.so`` binds to it, so device
+pointers and streams from PyTorch are valid in the library's calls.  Opened
+first, the library would map the system runtimes beside PyTorch's, and the
+second runtime to start in the process sees no device.
 """
 from __future__ import annotations
 
@@ -12,6 +19,7 @@ import os
 from typing import Optional
 
 import numpy as np
+import torch  # noqa: F401  (maps the HIP runtime the library must share)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbnos.so")
