@@ -178,6 +178,10 @@ bnos_status bnos_counts(bnos_table t, int32_t Q, const int32_t *nodes, const uin
  *                consistent sets (-inf if the empty set is the only one).
  * An order that is not a permutation of 0..n-1 yields lse = maxs = NaN and
  * best = 0 for that order; other orders are unaffected.
+ * The table owns the scoring workspace (the chunk partials), grown on demand
+ * with a device synchronisation: scoring calls on one table that may overlap
+ * (different streams, or host threads) race and must be serialised by the
+ * caller.
  */
 bnos_status bnos_score_orders(bnos_table t, const int32_t *orders, int32_t B, double *lse,
                               double *maxs, uint64_t *best, double *node_lse,
