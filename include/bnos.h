@@ -60,9 +60,10 @@ typedef struct {
     int32_t prior_mode;    /* 0: prior entries are weights w in [-1,1], R = (1 + w)/2;
                               1: prior entries are the paper's R in [0,1] (Sec. IV).
                               Either way the added term is ln(10) * 100 * (R - 0.5)^3. */
-    int32_t chunk_steps;   /* scoring blocks stream chunks of chunk_steps * 1024 entries of one node's
-                              row; a power of two <= 16 (rows are then padded to a multiple of at
-                              least that many steps), or 0 = automatic */
+    int32_t chunk_steps;   /* scoring blocks stream chunk_steps * 1024 entries of one node's row (a
+                              chunk: every chunks-th 1024-entry step of the row, chunks = padded
+                              row / chunk length); a power of two <= 16 (rows are then padded to
+                              a multiple of at least that many steps), or 0 = automatic */
     int32_t count_mode;    /* 0: one joint histogram per node subset U (|U| <= K+1) serves the |U|
                               families (i, U \ {i}); 1: one histogram per family.  Same table, bit
                               for bit; 0 counts about (K+1) times fewer samples.  (0 falls back to 1

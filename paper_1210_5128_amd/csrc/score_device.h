@@ -209,9 +209,9 @@ struct TabView {
     const uint64_t *tsub;       // [n * S_pad / 64] the same per 64-entry sub-tile (with tand)
 };
 
-// One block streams chunk `chunk` of node `node`'s entries once and folds each
-// entry into BT order states (group `group` of the batch, or of the node's work
-// list); it writes one Partial per order.
+// One block streams chunk `chunk` of node `node`'s entries once and folds
+// each entry into BT order states (group `group` of the batch, or of the node's
+// work list); it writes one Partial per order.
 template <int BT>
 __device__ __forceinline__ void score_block(const TabView &V, int node, int chunk, int group)
 {
@@ -225,14 +225,23 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     // orders this block folds: slots b0..b0+BT-1 of the plain batch or of node's work list
     const int count = V.wl_count ? V.wl_count[node] : V.B;
     if (b0 >= count) return;                     // uniform: nothing listed for this group
-    const int64_t row = (int64_t)node * V.S_pad + (int64_t)chunk * V.chunk_entries;
-    const int steps = V.chunk_entries / kEntriesPerStep;    // each wavefront owns tiles wave + 4*i, i < steps
+    // The block's entries are chunk `chunk` of the node's row: the row's
+    // 1024-entry steps chunk, chunk + chunks, chunk + 2 * chunks, ...; local
+    // tile tl = 4 i + w is tile w of the block's i-th step.  Spread over the
+    // row, a block's share of its node's work is about the same for every
+    // chunk, wherever the order concentrates that work in the row (the masks
+    // whose top member is one predecessor sit together, for example); a step's
+    // 16 sub-tile summaries still fill one 128-byte line.
+    const int64_t row = (int64_t)node * V.S_pad;             // the node's first entry
+    const int64_t trow = row >> 8;                            // and first tile
+    const int steps = V.chunk_entries / kEntriesPerStep;      // each wavefront owns local tiles wave + 4*i, i < steps
+    auto gtile = [&](int tl) -> int64_t { return ((chunk + (int64_t)(tl >> 2) * V.chunks) << 2) + (tl & 3); };
     // this wavefront's tile summaries, requested before the predecessor masks so the latencies overlap
     uint64_t tsum = 0, tsl = 0;
-    if (V.tand && lane < steps) tsum = V.tand[(row >> 8) + (int64_t)lane * 4 + wave];
+    if (V.tand && lane < steps) tsum = V.tand[trow + gtile(lane * 4 + wave)];
     // sub-tile summaries (one order per block): lane 4i + s holds sub-tile s of this wavefront's tile i
     if (BT == 1 && V.tand && lane < 4 * steps)
-        tsl = V.tsub[(row >> 6) + (int64_t)((lane >> 2) * 4 + wave) * 4 + (lane & 3)];
+        tsl = V.tsub[(trow + gtile((lane >> 2) * 4 + wave)) * 4 + (lane & 3)];
 
     for (int j = wave; j < BT; j += kScoreThreads / 64) {
         uint64_t np = ~0ull;   // no order in this slot: nothing is consistent
@@ -281,7 +290,7 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         const uint64_t bal = __ballot(m != 0u);
         if (m != 0u) {
             const int pos = __popcll(bal & ((1ull << lane) - 1ull));
-            s_tile[wave][pos] = lane * 4 + wave;
+            s_tile[wave][pos] = lane * 4 + wave;             // local index
             s_tneed[wave][pos] = m;
         }
         if (lane == 0) s_ntile[wave] = __popcll(bal);
@@ -309,7 +318,7 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     };
     if (k < nt) {
         const int tk = s_tile[wave][k];
-        const int q = tk * 64 + lane;                        // this lane's 4-entry group
+        const int64_t q = gtile(tk) * 64 + lane;             // this lane's 4-entry group in the row
         need_n = s_tneed[wave][k];
         n01 = (u64x2){~0ull, ~0ull};
         n23 = (u64x2){~0ull, ~0ull};
@@ -326,7 +335,7 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         const int kn = k + 1;
         if (kn < nt) {
             const int tk = s_tile[wave][kn];
-            const int q = tk * 64 + lane;
+            const int64_t q = gtile(tk) * 64 + lane;
             need_n = s_tneed[wave][kn];
             n01 = (u64x2){~0ull, ~0ull};
             n23 = (u64x2){~0ull, ~0ull};
@@ -441,14 +450,14 @@ __global__ __launch_bounds__(kScoreThreads) void k_count_tiles(ScoreArgs A, unsi
         if (lane == 0) s_np[j] = np;
     }
     __syncthreads();
-    const int64_t row = (int64_t)node * A.S_pad + (int64_t)chunk * A.chunk_entries;
+    const int64_t trow = (int64_t)node * (A.S_pad >> 8);
     const int steps = A.chunk_entries / kEntriesPerStep;
     // 64-entry sub-tiles read: of the needed tiles, those the order can use (one
     // order per block) or all four (several)
     unsigned c = 0;
     if (b0 < count) {
         for (int it = 0; it < steps; ++it) {
-            const int64_t tile = (row >> 8) + (int64_t)it * 4 + wave;
+            const int64_t tile = trow + ((chunk + (int64_t)it * A.chunks) << 2) + wave;   // as in score_block
             const uint64_t sm = A.tand[tile];
             bool any = false;
             for (int j = 0; j < BT; ++j) any |= (sm & s_np[j]) == 0ull;
