@@ -468,6 +468,9 @@ def main():
     ap.add_argument("--passes", choices=("both", "skip", "full"), default="both",
                     help="which scoring passes to time: tile skipping (the headline), full scan, or both; "
                          "one alone keeps a profiler's per-kernel figures unmixed")
+    ap.add_argument("--computed-masks", type=int, choices=(0, 1), default=1,
+                    help="1: one-order scoring blocks compute the masks from per-4-entry anchors (6 B/entry); "
+                         "0: they read the stored masks (12 B/entry)")
     ap.add_argument("--chains", type=int, default=256, help="batched chains on the mixed40 table (0 = skip)")
     ap.add_argument("--chain-iters", type=int, default=20000)
     ap.add_argument("--learned", type=int, default=256, metavar="C",
@@ -530,6 +533,7 @@ def main():
     t0 = time.perf_counter()
     table = bnos.build_score_table(net.data, net.arities, K, ess=w.ess, prior=prior, chunk_steps=args.chunk_steps)
     build_s = time.perf_counter() - t0
+    table.computed_masks(bool(args.computed_masks))
     info = table.info()
     S = info["entries_per_node"]
     print(f"# table built in {build_s:.3f} s, S={S}", file=sys.stderr, flush=True)
@@ -571,14 +575,18 @@ def main():
         # bytes the launch had to read: with tile skipping, the 64-entry sub-tiles it
         # loaded (64 x 12 B) plus the 8-byte summary of every tile of each pass and,
         # with one order per block, of every sub-tile; without, the full scan
+        # bytes per entry: a one-order block with computed masks reads the score and a quarter
+        # of an 8-byte anchor mask (6 B); otherwise mask + score (12 B)
+        eb = 6 if (args.computed_masks and passes_per_launch == Bq) else 12
         if skip:
             sub_summaries = tiles_per_pass if passes_per_launch == Bq else 0
-            alg = tiles / k_launches * 64 * 12 + passes_per_launch * (tiles_per_pass // 4 + sub_summaries) * 8
+            alg = tiles / k_launches * 64 * eb + passes_per_launch * (tiles_per_pass // 4 + sub_summaries) * 8
         else:
-            alg = bytes_per_pass * passes_per_launch
+            alg = eb * n * S * passes_per_launch
         gbs = alg / (kernel_avg_ms / 1e3) / 1e9
         return dict(total_ms=total_ms, ms_per_step=total_ms / steps, value=Bq * steps / (total_ms / 1e3),
                     kernel_avg_ms=kernel_avg_ms, passes_per_launch=passes_per_launch, gbs=gbs, alg_bytes=alg,
+                    entry_bytes=eb,
                     tile_fraction=tiles / max(1, k_passes * tiles_per_pass),
                     full_scan_equiv_gbs=bytes_per_pass * passes_per_launch / (kernel_avg_ms / 1e3) / 1e9)
 
@@ -647,6 +655,7 @@ def main():
             "kernel": "k_score (full scan)" if args.passes == "full" else "k_score (tile skipping)",
             "kernel_avg_us": kernel_avg_ms * 1e3,
             "algorithmic_bytes_per_launch": r["alg_bytes"],
+            "bytes_per_entry": r["entry_bytes"],
             "tile_fraction_read": r["tile_fraction"] if args.passes != "full" else 1.0,
             "full_scan_equivalent_GBs": r["full_scan_equiv_gbs"],
         },

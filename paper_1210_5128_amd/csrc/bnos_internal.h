@@ -51,6 +51,8 @@ struct TableT {
     uint64_t *d_tand = nullptr;     // [n * S_pad / 256]: AND of the masks of each 256-entry tile
     uint64_t *d_tsub = nullptr;     // [n * S_pad / 64]: AND of the masks of each 64-entry sub-tile
     bool tile_skip = true;
+    uint64_t *d_anchor = nullptr;   // [n * S_pad / 4]: slot-space mask of every 4th entry
+    bool computed_masks = true;     // one-order blocks compute masks from the anchors
 
     // order-scoring workspace: per (order, node, chunk) partial reductions
     void *d_part = nullptr;

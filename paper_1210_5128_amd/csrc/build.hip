@@ -46,7 +46,8 @@ int64_t TableT::device_bytes() const
 {
     return (int64_t)n * S_pad * (int64_t)(sizeof(uint64_t) + sizeof(float)) + (int64_t)n * N_pad +
            (int64_t)n * (int64_t)(sizeof(int32_t) + n * sizeof(double) + 5 * sizeof(double)) + 64 * 8 * 8 +
-           part_bytes + (int64_t)n * (S_pad / 256) * 8 + (int64_t)n * (S_pad / 64) * 8;
+           part_bytes + (int64_t)n * (S_pad / 256) * 8 + (int64_t)n * (S_pad / 64) * 8 +
+           (int64_t)n * (S_pad / 4) * 8;
 }
 
 // ------------------------------------------------------------------ device helpers
@@ -500,6 +501,21 @@ __global__ __launch_bounds__(256) void k_tile_and(const uint64_t *__restrict__ m
     if (lane == 0) tand[tile] = v;
 }
 
+// The slot-space mask (the node's own bit removed: slot s is node s below the
+// node, node s + 1 above it) of the first entry of every 4-entry group of each
+// row, for the scoring pass that computes the other masks; ~0 for padding.
+__global__ __launch_bounds__(256) void k_anchor(const uint64_t *__restrict__ masks, int n, int64_t S_pad,
+                                                uint64_t *__restrict__ anchor)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t per_row = S_pad / 4;
+    if (g >= (int64_t)n * per_row) return;
+    const int node = (int)(g / per_row);
+    const uint64_t m = masks[g * 4];
+    const uint64_t low = (1ull << node) - 1ull;
+    anchor[g] = (m == ~0ull) ? ~0ull : ((m & low) | ((m >> 1) & ~low));
+}
+
 // Counts for explicit (node, parent mask) queries, with the build's counting code.
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_counts(
@@ -591,6 +607,7 @@ static void free_device(TableT *t)
     hipFree(t->d_nstat);
     hipFree(t->d_tand);
     hipFree(t->d_tsub);
+    hipFree(t->d_anchor);
     hipFree(t->d_part);
     for (auto e : t->ev_start) hipEventDestroy(e);
     for (auto e : t->ev_stop) hipEventDestroy(e);
@@ -734,6 +751,7 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     ALLOC(t->d_nstat, sizeof(double) * (size_t)n * 5);
     ALLOC(t->d_tand, sizeof(uint64_t) * (size_t)n * (t->S_pad / 256));
     ALLOC(t->d_tsub, sizeof(uint64_t) * (size_t)n * (t->S_pad / 64));
+    ALLOC(t->d_anchor, sizeof(uint64_t) * (size_t)n * (t->S_pad / 4));
 #undef ALLOC
     int8_t *d_rows = nullptr;
     float *d_prior_in = nullptr;
@@ -820,6 +838,10 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
         const int64_t tiles = (int64_t)n * (t->S_pad / 256);
         hipLaunchKernelGGL(k_tile_and, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, t->d_masks, tiles,
                            t->d_tand, t->d_tsub);
+        CK(hipGetLastError());
+        const int64_t groups = (int64_t)n * (t->S_pad / 4);
+        hipLaunchKernelGGL(k_anchor, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, st, t->d_masks, n,
+                           t->S_pad, t->d_anchor);
         CK(hipGetLastError());
     }
     CK(hipStreamSynchronize(st));

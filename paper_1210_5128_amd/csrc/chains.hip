@@ -636,6 +636,8 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
         V.wl_list = H.wl_list;
         V.tand = t->tile_skip ? t->d_tand : nullptr;
         V.tsub = t->d_tsub;
+        V.anchor = nullptr;            // chain blocks read the stored masks
+        V.K = t->K;
         blk_base[k + 1] = blk_base[k] + (int64_t)n * V.chunks;
         chain_base[k + 1] = chain_base[k] + C;
         node_base[k + 1] = node_base[k] + n;

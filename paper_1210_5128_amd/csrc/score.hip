@@ -198,6 +198,8 @@ ScoreArgs score_args(const TableT *t, const int32_t *orders, int B, double *lse,
     A.wl_list = nullptr;
     A.tand = t->tile_skip ? t->d_tand : nullptr;
     A.tsub = t->d_tsub;
+    A.anchor = t->computed_masks ? t->d_anchor : nullptr;
+    A.K = t->K;
     return A;
 }
 
@@ -208,6 +210,11 @@ static void launch_bt(const ScoreArgs &A, int nblocks_x, hipStream_t st, hipEven
 {
     nblocks_x = (nblocks_x + kXcds - 1) / kXcds * kXcds;      // padded for xcd_block
     dim3 grid((unsigned)nblocks_x, (unsigned)((A.B + BT - 1) / BT));
+    if (BT == 1 && A.anchor) {
+        if (e0) hipExtLaunchKernelGGL((k_score<1, true>), grid, dim3(kScoreThreads), 0, st, e0, e1, 0, A);
+        else hipLaunchKernelGGL((k_score<1, true>), grid, dim3(kScoreThreads), 0, st, A);
+        return;
+    }
     if (e0) hipExtLaunchKernelGGL(k_score<BT>, grid, dim3(kScoreThreads), 0, st, e0, e1, 0, A);
     else hipLaunchKernelGGL(k_score<BT>, grid, dim3(kScoreThreads), 0, st, A);
 }
@@ -381,6 +388,14 @@ extern "C" bnos_status bnos_table_tile_skip(bnos_table h, int32_t enable)
     TableT *t = reinterpret_cast<TableT *>(h);
     if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
     t->tile_skip = enable != 0;
+    return BNOS_OK;
+}
+
+extern "C" bnos_status bnos_table_computed_masks(bnos_table h, int32_t enable)
+{
+    TableT *t = reinterpret_cast<TableT *>(h);
+    if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
+    t->computed_masks = enable != 0;
     return BNOS_OK;
 }
 

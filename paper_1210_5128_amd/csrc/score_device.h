@@ -192,6 +192,8 @@ struct ScoreArgs {
     const int32_t *wl_list;    // [n][B]
     const uint64_t *tand;      // tile summaries, or null
     const uint64_t *tsub;      // sub-tile summaries (with tand)
+    const uint64_t *anchor;    // first mask of every 4 entries in slot space, or null
+    int K;
 };
 
 // What one streaming block needs to know about its table and its orders.
@@ -207,14 +209,50 @@ struct TabView {
     const int32_t *wl_list;     // [n][B]
     const uint64_t *tand;       // [n * S_pad / 256] AND of each 256-entry tile's masks, or null (no skipping)
     const uint64_t *tsub;       // [n * S_pad / 64] the same per 64-entry sub-tile (with tand)
+    const uint64_t *anchor;     // [n * S_pad / 4] slot-space first mask of each 4-entry group (computed masks)
+    int K;
 };
+
+// A row lists every mask over the node's n - 1 slots (slot s is node s below
+// the node, node s + 1 above it) with at most K members, in ascending order.
+// The mask after m is m + 1 if that has at most K members, else m plus its
+// lowest member (adding it carries the run of members above it into the next
+// free slot, and no number in between has few enough members).  Past the last
+// mask the result holds a slot >= n - 1, which no predecessor set contains;
+// a result not above m (the end of the 64 bits, or K = 0) saturates to ~0.
+__device__ __forceinline__ uint64_t next_mask(uint64_t m, int K)
+{
+    const uint64_t t = m + 1ull;
+    const uint64_t r = (__popcll(t) <= K) ? t : m + (m & (0ull - m));
+    return r <= m ? ~0ull : r;
+}
+
+// Node-space mask (bit `node` clear) -> slot space, and back.
+__device__ __forceinline__ uint64_t to_slots(uint64_t m, int node)
+{
+    const uint64_t low = (1ull << node) - 1ull;
+    return (m & low) | ((m >> 1) & ~low);
+}
+__device__ __forceinline__ uint64_t to_nodes(uint64_t s, int node)
+{
+    const uint64_t low = (1ull << node) - 1ull;
+    return (s & low) | ((s & ~low) << 1);
+}
 
 // One block streams chunk `chunk` of node `node`'s entries once and folds
 // each entry into BT order states (group `group` of the batch, or of the node's
 // work list); it writes one Partial per order.
-template <int BT>
+//
+// CM (one order per block): the masks are not read but computed -- each lane
+// reads the slot-space mask of its first entry (V.anchor) and steps to the
+// next three with next_mask; the entries are tested against the predecessor
+// set in slot space and the best mask goes back to node space for the partial.
+// The states and partials are bitwise those of reading the stored masks, for
+// 6 bytes per entry read instead of 12.
+template <int BT, bool CM = false>
 __device__ __forceinline__ void score_block(const TabView &V, int node, int chunk, int group)
 {
+    static_assert(!CM || BT == 1, "computed masks serve one order per block");
     __shared__ uint64_t s_npred[BT];
     __shared__ Acc s_red[kScoreThreads / 64][BT];
     __shared__ int s_ord[BT];
@@ -268,6 +306,9 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
 
     const u64x2 *mp = reinterpret_cast<const u64x2 *>(V.masks + row);
     const f32x4 *sp = reinterpret_cast<const f32x4 *>(V.scores + row);
+    const uint64_t *ap = CM ? V.anchor + (row >> 2) : nullptr;
+    // slot-space predecessor complement, with every slot >= n - 1 (none exists) included
+    const uint64_t npred_s = CM ? (to_slots(npred[0], node) | (~0ull << (n - 1))) : 0ull;
     // Tile skipping: if the AND of a tile's masks holds a node outside an
     // order's predecessor set, every entry of the tile does, and the order
     // skips the tile; tiles no order of the block needs are not read.  Each
@@ -323,8 +364,12 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         n01 = (u64x2){~0ull, ~0ull};
         n23 = (u64x2){~0ull, ~0ull};
         if (lane_needs(tk)) {
-            n01 = __builtin_nontemporal_load(&mp[2 * q]);
-            n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
+            if (CM) {
+                n01.x = __builtin_nontemporal_load(&ap[q]);
+            } else {
+                n01 = __builtin_nontemporal_load(&mp[2 * q]);
+                n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
+            }
             nsc = __builtin_nontemporal_load(&sp[q]);
         }
     }
@@ -340,19 +385,29 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
             n01 = (u64x2){~0ull, ~0ull};
             n23 = (u64x2){~0ull, ~0ull};
             if (lane_needs(tk)) {
-                n01 = __builtin_nontemporal_load(&mp[2 * q]);
-                n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
+                if (CM) {
+                    n01.x = __builtin_nontemporal_load(&ap[q]);
+                } else {
+                    n01 = __builtin_nontemporal_load(&mp[2 * q]);
+                    n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
+                }
                 nsc = __builtin_nontemporal_load(&sp[q]);
             }
         }
-        const uint64_t mk[4] = {m01.x, m01.y, m23.x, m23.y};
+        uint64_t mk[4] = {m01.x, m01.y, m23.x, m23.y};
+        if (CM) {
+            mk[1] = next_mask(mk[0], V.K);
+            mk[2] = next_mask(mk[1], V.K);
+            mk[3] = next_mask(mk[2], V.K);
+        }
         const float x[4] = {sc.x, sc.y, sc.z, sc.w};
 #pragma unroll
         for (int j = 0; j < BT; ++j) {
             if (!((need_c >> j) & 1u)) continue;             // uniform
+            const uint64_t np = CM ? npred_s : npred[j];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                if ((mk[e] & npred[j]) == 0ull) acc_push(a[j], x[e], mk[e]);
+                if ((mk[e] & np) == 0ull) acc_push(a[j], x[e], mk[e]);
             }
         }
     }
@@ -401,7 +456,7 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
             p.s = r.s;
             p.best = r.best;
             p.second = r.sec;
-            p.bmask = r.bm;
+            p.bmask = (CM && r.m != -INFINITY) ? to_nodes(r.bm, node) : r.bm;
             V.part[((int64_t)ob * V.chunks + chunk) * n + node] = p;
         }
     }
@@ -423,6 +478,8 @@ __device__ __forceinline__ TabView view_of(const ScoreArgs &A)
     V.wl_list = A.wl_list;
     V.tand = A.tand;
     V.tsub = A.tsub;
+    V.anchor = A.anchor;
+    V.K = A.K;
     return V;
 }
 
@@ -500,7 +557,7 @@ __device__ __forceinline__ bool xcd_block(int64_t real_x, int &x, int &y)
 // to read, so the longest blocks are dispatched first and the shortest fill
 // the tail.  (An entry that is not a node id keeps the plain mapping; such an
 // order is invalid and scores NaN anyway.)
-template <int BT>
+template <int BT, bool CM = false>
 __global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
 {
     int x, y;
@@ -511,7 +568,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
         const int v = A.orders[(int64_t)y * A.n + (A.n - 1 - node)];
         node = (v >= 0 && v < A.n) ? v : node;
     }
-    score_block<BT>(view_of(A), node, chunk, y);
+    score_block<BT, CM>(view_of(A), node, chunk, y);
 }
 
 // Index of the segment holding x, for prefix bases base[0] = 0 < ... < base[T].

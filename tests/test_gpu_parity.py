@@ -455,3 +455,54 @@ def test_gather_needs_small_K(bnos):
         t.set_launch(1, gather=True)
     assert e.value.status == bnos.E_RANGE
     t.free()
+
+
+# ------------------------------------------------------------------ computed masks (one order per block)
+
+def same_bits(a, b):
+    for k in a:
+        assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), k
+
+
+@pytest.mark.parametrize("n,K,N,arities", [
+    (8, 3, 200, (2,)), (20, 4, 1000, (3,)), (64, 2, 129, (2,)), (64, 1, 60, (2,)), (1, 0, 50, (3,)),
+    (12, 0, 40, (2,)), (9, 6, 200, (2,)), (33, 5, 80, (2,)),
+])
+def test_computed_masks_are_bitwise_the_stored_ones(bnos, n, K, N, arities):
+    net = datagen.random_network(n, N, arities, min(3, n - 1), seed=7 * n + K)
+    t = bnos.build_score_table(net.data, net.arities, K)
+    orc = oracle.build_table(net.data, net.arities, K) if n <= 20 else None
+    try:
+        B = 7
+        orders = datagen.random_orders(n, B, seed=13 + n + K)
+        if n > 1:
+            orders[4, 0] = orders[4, 1]                   # not a permutation
+        t.set_launch(B, orders_per_block=1)
+        for skip in (True, False):
+            t.tile_skip(skip)
+            t.computed_masks(False)
+            stored = dev_score(t, orders)
+            t.computed_masks(True)
+            got = dev_score(t, orders)
+            same_bits(got, stored)
+        t.tile_skip(True)
+        ok = [b for b in range(B) if len(set(orders[b])) == n]
+        if orc is not None:
+            check_orders_against_oracle({k: v[ok] for k, v in got.items()}, orc, K, orders[ok])
+        for b in set(range(B)) - set(ok):
+            assert np.isnan(got["lse"][b]) and np.all(got["best"][b] == 0)
+    finally:
+        t.free()
+
+
+def test_computed_masks_on_the_60_node_table(bnos, mixed60):
+    w, net, prior, t = mixed60
+    orders = datagen.random_orders(w.n, 4, seed=123)
+    for cs in (1, 8, 16):
+        t.set_launch(1, chunk_steps=cs)
+        for b in range(4):
+            t.computed_masks(False)
+            stored = dev_score(t, orders[b:b + 1])
+            t.computed_masks(True)
+            same_bits(dev_score(t, orders[b:b + 1]), stored)
+    t.set_launch(1)
