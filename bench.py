@@ -543,20 +543,26 @@ def main():
     def timed(Bq, steps, warmup, skip=True):
         table.tile_skip(skip)
         pool = max(8, min(64, steps))
+        pool = pool - 1 if pool % 7 == 0 else pool      # sampled launches visit every order
         orders = torch.from_numpy(datagen.random_orders(n, pool * Bq, seed=5 + Bq).reshape(pool, Bq, n)).to(dev)
         lse = torch.empty(Bq, dtype=torch.float64, device=dev)
         mx = torch.empty(Bq, dtype=torch.float64, device=dev)
         best = torch.empty((Bq, n), dtype=torch.int64, device=dev)
+        views = [orders[i] for i in range(pool)]      # made once: the loop only launches
         for s in range(warmup):
-            table.score_orders(orders[s % pool], lse, mx, best, stream=stream)
+            table.score_orders(views[s % pool], lse, mx, best, stream=stream)
         torch.cuda.synchronize()
-        table.timing(True)
+        # events on 1 launch in 7 for short launches (an event pair costs the host ~15 us
+        # per launch, which would make a single-order loop host-bound), spread over the
+        # whole timed region and, 7 being prime to the pool size, over every order of the
+        # pool (whose sub-tiles the algorithmic bytes count); on every launch for batches
+        table.timing(True, every=7 if Bq < 16 else 1)
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         ev0.record(stream)
         for s in range(steps):
-            table.score_orders(orders[s % pool], lse, mx, best, stream=stream)
+            table.score_orders(views[s % pool], lse, mx, best, stream=stream)
         ev1.record(stream)
         torch.cuda.synchronize()
         total_ms = ev0.elapsed_time(ev1)
@@ -580,14 +586,14 @@ def main():
         eb = 6 if (args.computed_masks and passes_per_launch == Bq) else 12
         if skip:
             sub_summaries = tiles_per_pass if passes_per_launch == Bq else 0
-            alg = tiles / k_launches * 64 * eb + passes_per_launch * (tiles_per_pass // 4 + sub_summaries) * 8
+            alg = tiles / steps * 64 * eb + passes_per_launch * (tiles_per_pass // 4 + sub_summaries) * 8
         else:
             alg = eb * n * S * passes_per_launch
         gbs = alg / (kernel_avg_ms / 1e3) / 1e9
         return dict(total_ms=total_ms, ms_per_step=total_ms / steps, value=Bq * steps / (total_ms / 1e3),
                     kernel_avg_ms=kernel_avg_ms, passes_per_launch=passes_per_launch, gbs=gbs, alg_bytes=alg,
                     entry_bytes=eb,
-                    tile_fraction=tiles / max(1, k_passes * tiles_per_pass),
+                    tile_fraction=tiles / max(1, steps * passes_per_launch * tiles_per_pass),
                     full_scan_equiv_gbs=bytes_per_pass * passes_per_launch / (kernel_avg_ms / 1e3) / 1e9)
 
     stream = torch.cuda.current_stream()

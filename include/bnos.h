@@ -347,15 +347,20 @@ bnos_status bnos_run_chains_multi(const bnos_table *tables, int32_t T, const bno
                                   bnos_chain_state *states, void *stream);
 
 /*
- * Kernel timing for measurement: while enabled, every order-scoring launch
- * of this table (bnos_score_orders / bnos_score_order) carries a pair of HIP
- * events that take the streaming kernel's own start and end on the launch
- * stream (hipExtLaunchKernel).  bnos_table_timing_read waits for them and
+ * Kernel timing for measurement: while enabled (enable = k >= 1), every k-th
+ * order-scoring launch of this table (bnos_score_orders / bnos_score_order),
+ * starting with the first, carries a pair of HIP events that take the
+ * streaming kernel's own start and end on the launch stream
+ * (hipExtLaunchKernel); 0 disables, negative values are E_RANGE.  (A launch
+ * with events costs the host about 15 us more than one without: for short
+ * launches, sample with k > 1 so that the timed loop is not host-bound.)  bnos_table_timing_read waits for them and
  * returns the sum of the streaming kernels' durations (ms), the number of
  * launches and the number of passes over the table those launches made (a
  * launch scoring B orders streams the table once per group of orders per
  * block) since the last enable, then keeps counting.  Any output pointer may
- * be NULL.
+ * be NULL.  The events form a ring of 256 pairs created by the enable call;
+ * when 256 timed launches are pending, the next one first waits for the
+ * oldest and adds it to the totals.
  */
 bnos_status bnos_table_timing(bnos_table t, int32_t enable);
 

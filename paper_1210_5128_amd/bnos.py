@@ -272,8 +272,9 @@ class Table:
         return a.value, b.value
 
     # -- timing
-    def timing(self, enable: bool):
-        _check(_lib.bnos_table_timing(self._h, int(enable)))
+    def timing(self, enable, every: int = 1):
+        """Kernel timing (bnos_table_timing): off, or events on every `every`-th scoring launch."""
+        _check(_lib.bnos_table_timing(self._h, int(every) if enable else 0))
 
     def timing_read(self):
         """-> (total kernel ms, launches, table passes) since timing was enabled."""

@@ -58,13 +58,17 @@ struct TableT {
     void *d_part = nullptr;
     int64_t part_bytes = 0;         // capacity in bytes
 
-    // kernel timing
+    // kernel timing: a ring of kEventRing event pairs, created when timing is
+    // first enabled; launches in flight occupy ev_count slots from ev_head on
+    static constexpr size_t kEventRing = 256;
     bool timing = false;
+    int timing_every = 1;           // every timing_every-th launch carries events
+    int64_t timing_seen = 0;        // scoring launches since timing was enabled
     std::vector<hipEvent_t> ev_start, ev_stop;
-    size_t ev_used = 0;
+    size_t ev_head = 0, ev_count = 0;
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
-    std::vector<int64_t> ev_passes;     // table passes of each recorded launch
+    std::vector<int64_t> ev_passes;     // table passes of the launch in each slot
     int64_t timed_passes = 0;
 
     // autotuned per batch-size bucket (1, 2-3, 4-7, 8-15, 16+); 0 = default

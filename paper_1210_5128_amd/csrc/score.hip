@@ -161,18 +161,48 @@ bnos_status ensure_workspace(TableT *t, int B)
     return BNOS_OK;
 }
 
-// The next pair of timing events (created on first use).
-static bnos_status next_events(TableT *t, hipEvent_t &e0, hipEvent_t &e1)
+// Adds the oldest timed launch in the ring to the totals and frees its slot.
+static bnos_status harvest_oldest(TableT *t)
 {
-    for (std::vector<hipEvent_t> *pool : {&t->ev_start, &t->ev_stop}) {
-        if (pool->size() <= t->ev_used) {
-            hipEvent_t e;
-            BNOS_HIP(hipEventCreate(&e));
-            pool->push_back(e);
+    const size_t k = t->ev_head;
+    BNOS_HIP(hipEventSynchronize(t->ev_stop[k]));
+    float ms = 0.f;
+    BNOS_HIP(hipEventElapsedTime(&ms, t->ev_start[k], t->ev_stop[k]));
+    t->timed_ms += ms;
+    t->timed_launches += 1;
+    t->timed_passes += t->ev_passes[k];
+    t->ev_head = (k + 1) % TableT::kEventRing;
+    t->ev_count--;
+    return BNOS_OK;
+}
+
+// The event pair for the next timed launch, which makes `passes` passes over
+// the table.  With the ring full, the oldest launch (kEventRing launches back,
+// long finished in a stream of launches) is read first.
+static bnos_status next_events(TableT *t, hipEvent_t &e0, hipEvent_t &e1, int64_t passes)
+{
+    bnos_status s;
+    if (t->ev_start.size() < TableT::kEventRing) {
+        BNOS_HIP(hipSetDevice(t->device));
+        while (t->ev_start.size() < TableT::kEventRing) {
+            hipEvent_t a, b;
+            BNOS_HIP(hipEventCreate(&a));
+            if (hipEventCreate(&b) != hipSuccess) {
+                hipEventDestroy(a);
+                set_error("hipEventCreate failed");
+                return BNOS_E_DEVICE;
+            }
+            t->ev_start.push_back(a);
+            t->ev_stop.push_back(b);
         }
+        t->ev_passes.assign(TableT::kEventRing, 0);
     }
-    e0 = t->ev_start[t->ev_used];
-    e1 = t->ev_stop[t->ev_used];
+    if (t->ev_count == TableT::kEventRing && (s = harvest_oldest(t)) != BNOS_OK) return s;
+    const size_t k = (t->ev_head + t->ev_count) % TableT::kEventRing;
+    t->ev_passes[k] = passes;
+    t->ev_count++;
+    e0 = t->ev_start[k];
+    e1 = t->ev_stop[k];
     return BNOS_OK;
 }
 
@@ -226,8 +256,8 @@ bnos_status launch_stream(TableT *t, const ScoreArgs &A, hipStream_t st, int bt)
     bnos_status s;
     if (bt <= 0) bt = pick_bt(t, A.B);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (t->timing) {
-        if ((s = next_events(t, e0, e1)) != BNOS_OK) return s;
+    if (t->timing && t->timing_seen++ % t->timing_every == 0) {
+        if ((s = next_events(t, e0, e1, (A.B + bt - 1) / bt)) != BNOS_OK) return s;
     }
     const int nbx = t->n * A.chunks;
     if (bt == 8) launch_bt<8>(A, nbx, st, e0, e1);
@@ -235,11 +265,6 @@ bnos_status launch_stream(TableT *t, const ScoreArgs &A, hipStream_t st, int bt)
     else if (bt == 2) launch_bt<2>(A, nbx, st, e0, e1);
     else launch_bt<1>(A, nbx, st, e0, e1);
     BNOS_HIP(hipGetLastError());
-    if (t->timing) {
-        if (t->ev_passes.size() <= t->ev_used) t->ev_passes.resize(t->ev_used + 1);
-        t->ev_passes[t->ev_used] = (A.B + bt - 1) / bt;
-        t->ev_used++;
-    }
     return BNOS_OK;
 }
 
@@ -250,18 +275,13 @@ static bnos_status launch_gather(TableT *t, ScoreArgs &A, hipStream_t st)
     bnos_status s;
     A.chunks = t->n;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (t->timing) {
-        if ((s = next_events(t, e0, e1)) != BNOS_OK) return s;
+    if (t->timing && t->timing_seen++ % t->timing_every == 0) {
+        if ((s = next_events(t, e0, e1, 0)) != BNOS_OK) return s;
     }
     dim3 grid((unsigned)(t->n * t->n), (unsigned)A.B);
     if (e0) hipExtLaunchKernelGGL(k_gather, grid, dim3(kScoreThreads), 0, st, e0, e1, 0, A, t->d_nsets, t->K);
     else hipLaunchKernelGGL(k_gather, grid, dim3(kScoreThreads), 0, st, A, t->d_nsets, t->K);
     BNOS_HIP(hipGetLastError());
-    if (t->timing) {
-        if (t->ev_passes.size() <= t->ev_used) t->ev_passes.resize(t->ev_used + 1);
-        t->ev_passes[t->ev_used] = 0;
-        t->ev_used++;
-    }
     return BNOS_OK;
 }
 
@@ -337,11 +357,21 @@ extern "C" bnos_status bnos_table_timing(bnos_table h, int32_t enable)
 {
     TableT *t = reinterpret_cast<TableT *>(h);
     if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
+    if (enable < 0) { set_error("timing: enable must be >= 0"); return BNOS_E_RANGE; }
     t->timing = enable != 0;
-    t->ev_used = 0;
+    t->timing_every = enable > 0 ? enable : 1;
+    t->timing_seen = 0;
+    t->ev_head = 0;
+    t->ev_count = 0;
     t->timed_ms = 0.0;
     t->timed_launches = 0;
     t->timed_passes = 0;
+    if (t->timing) {                 // create the event ring now, outside any timed launch
+        hipEvent_t e0, e1;
+        bnos_status s = next_events(t, e0, e1, 0);
+        t->ev_count = 0;
+        if (s != BNOS_OK) return s;
+    }
     return BNOS_OK;
 }
 
@@ -404,15 +434,9 @@ extern "C" bnos_status bnos_table_timing_read(bnos_table h, double *total_ms, in
 {
     TableT *t = reinterpret_cast<TableT *>(h);
     if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
-    for (size_t k = 0; k < t->ev_used; ++k) {
-        BNOS_HIP(hipEventSynchronize(t->ev_stop[k]));
-        float ms = 0.f;
-        BNOS_HIP(hipEventElapsedTime(&ms, t->ev_start[k], t->ev_stop[k]));
-        t->timed_ms += ms;
-        t->timed_launches += 1;
-        t->timed_passes += t->ev_passes[k];
-    }
-    t->ev_used = 0;
+    bnos_status s;
+    while (t->ev_count > 0)
+        if ((s = harvest_oldest(t)) != BNOS_OK) return s;
     if (total_ms) *total_ms = t->timed_ms;
     if (launches) *launches = t->timed_launches;
     if (table_passes) *table_passes = t->timed_passes;

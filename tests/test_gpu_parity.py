@@ -506,3 +506,27 @@ def test_computed_masks_on_the_60_node_table(bnos, mixed60):
             t.computed_masks(True)
             same_bits(dev_score(t, orders[b:b + 1]), stored)
     t.set_launch(1)
+
+
+def test_kernel_timing_samples_and_ring(bnos, prior20):
+    w, net, prior, t, *_ = prior20
+    o = torch.from_numpy(datagen.random_orders(w.n, 1, seed=3)).cuda()
+    lse = torch.empty(1, dtype=torch.float64, device="cuda")
+    mx = torch.empty_like(lse)
+    best = torch.empty((1, w.n), dtype=torch.int64, device="cuda")
+    t.set_launch(1, orders_per_block=1)
+    t.timing(True, every=4)
+    for _ in range(10):
+        t.score_orders(o, lse, mx, best)
+    ms, launches, passes = t.timing_read()
+    assert launches == 3 and passes == 3 and ms > 0          # launches 0, 4 and 8
+    t.timing(True)                                            # every launch; more than the 256-pair ring
+    for _ in range(300):
+        t.score_orders(o, lse, mx, best)
+    ms2, launches2, passes2 = t.timing_read()
+    assert launches2 == 300 and passes2 == 300 and ms2 > 0
+    t.timing(False)
+    with pytest.raises(bnos.BnosError) as e:
+        bnos._check(bnos._lib.bnos_table_timing(t._h, -1))
+    assert e.value.status == bnos.E_RANGE
+    t.set_launch(1)
