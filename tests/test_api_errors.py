@@ -70,6 +70,10 @@ def test_stale_handles_are_rejected():
     assert status_of(lambda: fake.score_order(np.arange(4, dtype=np.int32))) == B.E_STATE
     assert status_of(lambda: fake.export(0)) == B.E_STATE
     assert status_of(lambda: fake.tile_skip(True)) == B.E_STATE
+    assert status_of(lambda: fake.computed_masks(True)) == B.E_STATE
+    assert status_of(lambda: fake.timing(True, every=7)) == B.E_STATE
+    assert status_of(lambda: fake.set_launch(1, gather=True)) == B.E_STATE
+    assert status_of(lambda: fake.timing_read()) == B.E_STATE
     fake._h = None                           # nothing for __del__ to free
     # chain configuration errors come first
     bad = B.ChainCfg()
