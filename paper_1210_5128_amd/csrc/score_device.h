@@ -165,6 +165,18 @@ __device__ __forceinline__ uint64_t wave_pred(const int32_t *__restrict__ ord, i
     return valid ? before : 0ull;
 }
 
+// Whether the order is a permutation of 0..n-1, from lane p's entry v (position p),
+// by the same test as wave_pred.
+__device__ __forceinline__ bool order_valid(int v, int n, int lane)
+{
+    const bool inr = (v >= 0 && v < n);
+    uint64_t all = inr ? (1ull << v) : 0ull;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) all |= (uint64_t)__shfl_xor((unsigned long long)all, off, 64);
+    const uint64_t full = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
+    return (all == full) && (__ballot(lane < n && !inr) == 0ull);
+}
+
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
 {
     uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -711,8 +723,11 @@ __device__ __forceinline__ void merge_block(const ScoreArgs &A, int b, MergeLds 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int n = A.n;
-    (void)wave_pred(A.orders + (int64_t)b * n, n, 0, lane, valid);
+    // the order's entries are requested first and checked after the merge, so the
+    // two loads overlap
+    const int v = lane < n ? A.orders[(int64_t)b * n + lane] : -1;
     const Acc r = merge_nodes(A.part + (int64_t)b * A.chunks * n, n, A.chunks, lane < n ? lane : -1, L);
+    valid = order_valid(v, n, lane);
     lse_out = 0.0;
     max_out = 0.0;
     if (wave == 0) {
