@@ -530,3 +530,42 @@ def test_kernel_timing_samples_and_ring(bnos, prior20):
         bnos._check(bnos._lib.bnos_table_timing(t._h, -1))
     assert e.value.status == bnos.E_RANGE
     t.set_launch(1)
+
+
+def test_maximum_size_64_nodes_K4(bnos):
+    """The largest table the masks allow: n = 64, K = 4 (637,393 entries per node),
+    spot-checked per node against scoring straight from the data, one order per launch
+    (computed masks) and four per launch (stored masks)."""
+    net = datagen.random_network(64, 2000, (2, 3, 4), 3, seed=64)
+    K = 4
+    t = bnos.build_score_table(net.data, net.arities, K)
+    try:
+        assert t.info()["entries_per_node"] == oracle.num_sets(63, K) == 637393
+        orders = datagen.random_orders(64, 4, seed=65)
+        t.set_launch(1, orders_per_block=1)
+        singles = [dev_score(t, orders[b:b + 1]) for b in range(4)]
+        t.computed_masks(False)
+        stored = [dev_score(t, orders[b:b + 1]) for b in range(4)]
+        t.computed_masks(True)
+        for a, b in zip(singles, stored):
+            same_bits(a, b)
+        batch = dev_score(t, orders)
+        for b in range(4):
+            one = singles[b]
+            assert one["lse"][0] >= one["max"][0]
+            np.testing.assert_allclose(one["node_lse"].sum(), one["lse"][0], rtol=1e-12)
+            np.testing.assert_allclose(batch["lse"][b], one["lse"][0], rtol=1e-9)
+            assert np.array_equal(batch["best"][b], one["best"][0])
+        for b, p in [(0, 0), (1, 14), (2, 27), (3, 33)]:
+            node = int(orders[b, p])
+            pred = 0
+            for v in orders[b, :p]:
+                pred |= 1 << int(v)
+            l, best, bm, sec = oracle.score_node_direct(net.data, net.arities, K, node, pred, round_f32=True)
+            for got, row in ((singles[b], 0), (batch, b)):
+                assert abs(got["node_lse"][row, node] - l) <= REL * max(1.0, abs(l))
+                assert int(got["best"][row, node]) == bm
+                assert float(got["node_second"][row, node]) == sec
+    finally:
+        t.set_launch(1)
+        t.free()
