@@ -503,7 +503,8 @@ __global__ __launch_bounds__(256) void k_tile_and(const uint64_t *__restrict__ m
 
 // The slot-space mask (the node's own bit removed: slot s is node s below the
 // node, node s + 1 above it) of the first entry of every 4-entry group of each
-// row, for the scoring pass that computes the other masks; ~0 for padding.
+// row, for the scoring pass that computes the other masks; for padding, the
+// mask of slot n - 1, which no row holds and no step from it leaves.
 __global__ __launch_bounds__(256) void k_anchor(const uint64_t *__restrict__ masks, int n, int64_t S_pad,
                                                 uint64_t *__restrict__ anchor)
 {
@@ -513,7 +514,7 @@ __global__ __launch_bounds__(256) void k_anchor(const uint64_t *__restrict__ mas
     const int node = (int)(g / per_row);
     const uint64_t m = masks[g * 4];
     const uint64_t low = (1ull << node) - 1ull;
-    anchor[g] = (m == ~0ull) ? ~0ull : ((m & low) | ((m >> 1) & ~low));
+    anchor[g] = (m == ~0ull) ? (1ull << (n - 1)) : ((m & low) | ((m >> 1) & ~low));
 }
 
 // Counts for explicit (node, parent mask) queries, with the build's counting code.

@@ -240,6 +240,13 @@ static void launch_bt(const ScoreArgs &A, int nblocks_x, hipStream_t st, hipEven
 {
     nblocks_x = (nblocks_x + kXcds - 1) / kXcds * kXcds;      // padded for xcd_block
     dim3 grid((unsigned)nblocks_x, (unsigned)((A.B + BT - 1) / BT));
+    // without the saturation test when three steps cannot pass 2^64 (with K = 1 a step from
+    // a single slot doubles the mask)
+    if (BT == 1 && A.anchor && ((A.K >= 2 && A.n <= 63) || (A.K == 1 && A.n <= 61))) {
+        if (e0) hipExtLaunchKernelGGL((k_score<1, true, true>), grid, dim3(kScoreThreads), 0, st, e0, e1, 0, A);
+        else hipLaunchKernelGGL((k_score<1, true, true>), grid, dim3(kScoreThreads), 0, st, A);
+        return;
+    }
     if (BT == 1 && A.anchor) {
         if (e0) hipExtLaunchKernelGGL((k_score<1, true>), grid, dim3(kScoreThreads), 0, st, e0, e1, 0, A);
         else hipLaunchKernelGGL((k_score<1, true>), grid, dim3(kScoreThreads), 0, st, A);

@@ -239,6 +239,17 @@ __device__ __forceinline__ uint64_t next_mask(uint64_t m, int K)
     return r <= m ? ~0ull : r;
 }
 
+// The same without the saturation, for K >= 2 with n <= 63 and for K = 1 with
+// n <= 61: starting from a mask of the row or from 2^(n-1) (slot n - 1, which no
+// row has: padding and unused lanes), three steps stay below 2^64 (with K = 1
+// each step past the row doubles the mask) and every mask past the row keeps a
+// slot >= n - 1.
+__device__ __forceinline__ uint64_t next_mask_nosat(uint64_t m, int K)
+{
+    const uint64_t t = m + 1ull;
+    return (__popcll(t) <= K) ? t : m + (m & (0ull - m));
+}
+
 // Node-space mask (bit `node` clear) -> slot space, and back.
 __device__ __forceinline__ uint64_t to_slots(uint64_t m, int node)
 {
@@ -260,8 +271,9 @@ __device__ __forceinline__ uint64_t to_nodes(uint64_t s, int node)
 // next three with next_mask; the entries are tested against the predecessor
 // set in slot space and the best mask goes back to node space for the partial.
 // The states and partials are bitwise those of reading the stored masks, for
-// 6 bytes per entry read instead of 12.
-template <int BT, bool CM = false>
+// 6 bytes per entry read instead of 12.  NOSAT steps without the saturation
+// test where next_mask_nosat allows it.
+template <int BT, bool CM = false, bool NOSAT = false>
 __device__ __forceinline__ void score_block(const TabView &V, int node, int chunk, int group)
 {
     static_assert(!CM || BT == 1, "computed masks serve one order per block");
@@ -321,6 +333,7 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     const uint64_t *ap = CM ? V.anchor + (row >> 2) : nullptr;
     // slot-space predecessor complement, with every slot >= n - 1 (none exists) included
     const uint64_t npred_s = CM ? (to_slots(npred[0], node) | (~0ull << (n - 1))) : 0ull;
+    const uint64_t dead = 1ull << (n - 1);   // anchor of a lane that reads nothing: slot n - 1
     // Tile skipping: if the AND of a tile's masks holds a node outside an
     // order's predecessor set, every entry of the tile does, and the order
     // skips the tile; tiles no order of the block needs are not read.  Each
@@ -373,7 +386,7 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         const int tk = s_tile[wave][k];
         const int64_t q = gtile(tk) * 64 + lane;             // this lane's 4-entry group in the row
         need_n = s_tneed[wave][k];
-        n01 = (u64x2){~0ull, ~0ull};
+        n01 = (u64x2){CM ? dead : ~0ull, ~0ull};
         n23 = (u64x2){~0ull, ~0ull};
         if (lane_needs(tk)) {
             if (CM) {
@@ -394,7 +407,7 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
             const int tk = s_tile[wave][kn];
             const int64_t q = gtile(tk) * 64 + lane;
             need_n = s_tneed[wave][kn];
-            n01 = (u64x2){~0ull, ~0ull};
+            n01 = (u64x2){CM ? dead : ~0ull, ~0ull};
             n23 = (u64x2){~0ull, ~0ull};
             if (lane_needs(tk)) {
                 if (CM) {
@@ -408,9 +421,9 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         }
         uint64_t mk[4] = {m01.x, m01.y, m23.x, m23.y};
         if (CM) {
-            mk[1] = next_mask(mk[0], V.K);
-            mk[2] = next_mask(mk[1], V.K);
-            mk[3] = next_mask(mk[2], V.K);
+            mk[1] = NOSAT ? next_mask_nosat(mk[0], V.K) : next_mask(mk[0], V.K);
+            mk[2] = NOSAT ? next_mask_nosat(mk[1], V.K) : next_mask(mk[1], V.K);
+            mk[3] = NOSAT ? next_mask_nosat(mk[2], V.K) : next_mask(mk[2], V.K);
         }
         const float x[4] = {sc.x, sc.y, sc.z, sc.w};
 #pragma unroll
@@ -569,7 +582,7 @@ __device__ __forceinline__ bool xcd_block(int64_t real_x, int &x, int &y)
 // to read, so the longest blocks are dispatched first and the shortest fill
 // the tail.  (An entry that is not a node id keeps the plain mapping; such an
 // order is invalid and scores NaN anyway.)
-template <int BT, bool CM = false>
+template <int BT, bool CM = false, bool NOSAT = false>
 __global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
 {
     int x, y;
@@ -580,7 +593,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
         const int v = A.orders[(int64_t)y * A.n + (A.n - 1 - node)];
         node = (v >= 0 && v < A.n) ? v : node;
     }
-    score_block<BT, CM>(view_of(A), node, chunk, y);
+    score_block<BT, CM, NOSAT>(view_of(A), node, chunk, y);
 }
 
 // Index of the segment holding x, for prefix bases base[0] = 0 < ... < base[T].

@@ -466,7 +466,8 @@ def same_bits(a, b):
 
 @pytest.mark.parametrize("n,K,N,arities", [
     (8, 3, 200, (2,)), (20, 4, 1000, (3,)), (64, 2, 129, (2,)), (64, 1, 60, (2,)), (1, 0, 50, (3,)),
-    (12, 0, 40, (2,)), (9, 6, 200, (2,)), (33, 5, 80, (2,)),
+    (12, 0, 40, (2,)), (9, 6, 200, (2,)), (33, 5, 80, (2,)), (63, 2, 100, (2,)), (61, 1, 80, (2,)),
+    (62, 1, 80, (2,)),
 ])
 def test_computed_masks_are_bitwise_the_stored_ones(bnos, n, K, N, arities):
     net = datagen.random_network(n, N, arities, min(3, n - 1), seed=7 * n + K)

@@ -34,3 +34,33 @@ def test_saturation_at_64_bits():
     assert next_mask(top, 1) == (1 << 64) - 1          # top + lowest member overflows
     assert next_mask((1 << 64) - 1, 4) == (1 << 64) - 1
     assert next_mask(0, 0) == (1 << 64) - 1            # K = 0: the empty set is the whole row
+
+
+def next_mask_nosat(m, K):
+    t = m + 1
+    return t if bin(t).count("1") <= K else m + (m & -m)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 6])
+def test_steps_without_saturation_stay_in_range(K):
+    """Where the scoring pass drops the saturation test (K >= 2 with n <= 63, K = 1 with
+    n <= 61), three steps from the padding anchor 2^(n-1) or from any of the row's last
+    masks stay below 2^64 and keep a slot >= n - 1 once past the row."""
+    for n in range(2, 64):
+        if not ((K >= 2 and n <= 63) or (K == 1 and n <= 61)):
+            continue
+        slots = n - 1
+        top = sorted(sum(1 << b for b in c) for k in range(1, min(K, slots) + 1)
+                     for c in itertools.combinations(range(max(0, slots - K - 1), slots), k))[-4:]
+        for start in [1 << slots] + top:
+            m = start
+            for _ in range(3):
+                m = next_mask_nosat(m, K)
+                assert m < (1 << 64)
+                if m >= (1 << slots):
+                    assert m >> slots != 0
+    # and the excluded case does overflow: K = 1, n = 62 from the padding anchor
+    m = 1 << 61
+    for _ in range(3):
+        m = next_mask_nosat(m, 1)
+    assert m >= (1 << 64)
