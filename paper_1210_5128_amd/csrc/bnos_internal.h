@@ -17,7 +17,8 @@ constexpr int kMaxCells = 16384;
 constexpr int kMaxK = 6;
 
 // Order-scoring geometry: 256 threads, 4 entries per thread per step, so a
-// block consumes 1024 entries per step; a chunk is 1..16 steps.
+// block consumes 1024 entries per step; a chunk is 1..16 steps, taken from a
+// node's row at a stride of `chunks` steps (chunk c: steps c, c + chunks, ...).
 constexpr int kScoreThreads = 256;
 constexpr int kEntriesPerStep = 1024;
 constexpr int kMaxStepsPerChunk = 16;
