@@ -162,36 +162,65 @@ constexpr int kPosBins = 8;
 __global__ __launch_bounds__(kListThreads) void k_worklist(const ChainView *__restrict__ views,
                                                            const int64_t *__restrict__ node_base, int T)
 {
-    __shared__ int s_wave[kListThreads / 64];
-    __shared__ int s_base;
+    __shared__ int s_cnt[kPosBins][kListThreads / 64];   // per bin, chains listed by each wave
+    __shared__ int s_run[kPosBins];                       // per bin, list position reached
     const int k = find_segment(node_base, T, (int64_t)blockIdx.x);
     const ChainView &H = views[k];
     const int node = (int)((int64_t)blockIdx.x - node_base[k]);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    if (threadIdx.x == 0) s_base = 0;
+    // the bin of chain c for this node, or -1 if its window does not hold the node
+    auto bin_of = [&](int c) -> int {
+        if (c >= H.C || !((H.wmask[c] >> node) & 1ull)) return -1;
+        return (int)H.ppos[(int64_t)c * H.n + node] * kPosBins / H.n;
+    };
+    // pass 1: chains per bin, so that each bin's run of the list starts where the
+    // previous bins' end (the list is bin by bin, chains ascending within a bin)
+    if (threadIdx.x < kPosBins) s_run[threadIdx.x] = 0;
     __syncthreads();
-    for (int bin = 0; bin < kPosBins; ++bin)
     for (int base = 0; base < H.C; base += kListThreads) {
-        const int c = base + threadIdx.x;
-        const bool act = c < H.C && ((H.wmask[c] >> node) & 1ull) &&
-                         (int)H.ppos[(int64_t)c * H.n + node] * kPosBins / H.n == bin;
-        const uint64_t bal = __ballot(act);
-        const int rank = __popcll(bal & ((1ull << lane) - 1ull));
-        if (lane == 0) s_wave[wave] = __popcll(bal);
+        const int bn = bin_of(base + threadIdx.x);
+#pragma unroll
+        for (int b = 0; b < kPosBins; ++b) {
+            const int cnt = __popcll(__ballot(bn == b));
+            if (lane == 0 && cnt) atomicAdd(&s_run[b], cnt);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int start = 0;
+        for (int b = 0; b < kPosBins; ++b) {
+            const int c = s_run[b];
+            s_run[b] = start;
+            start += c;
+        }
+        H.wl_count[node] = start;
+    }
+    __syncthreads();
+    // pass 2: each listed chain at its bin's next free place, in chain order
+    for (int base = 0; base < H.C; base += kListThreads) {
+        const int bn = bin_of(base + threadIdx.x);
+        int rank = 0;
+#pragma unroll
+        for (int b = 0; b < kPosBins; ++b) {
+            const uint64_t bal = __ballot(bn == b);
+            if (bn == b) rank = __popcll(bal & ((1ull << lane) - 1ull));
+            if (lane == 0) s_cnt[b][wave] = __popcll(bal);
+        }
         __syncthreads();
-        int off = s_base;
-        for (int w = 0; w < wave; ++w) off += s_wave[w];
-        if (act) H.wl_list[(int64_t)node * H.C + off + rank] = c;
+        if (bn >= 0) {
+            int off = s_run[bn] + rank;
+            for (int w = 0; w < wave; ++w) off += s_cnt[bn][w];
+            H.wl_list[(int64_t)node * H.C + off] = base + threadIdx.x;
+        }
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (threadIdx.x < kPosBins) {
             int tot = 0;
-            for (int w = 0; w < kListThreads / 64; ++w) tot += s_wave[w];
-            s_base += tot;
+            for (int w = 0; w < kListThreads / 64; ++w) tot += s_cnt[threadIdx.x][w];
+            s_run[threadIdx.x] += tot;
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) H.wl_count[node] = s_base;
 }
 
 // Offer graph g (lane i holds node i's parent mask) with max score M to chain
