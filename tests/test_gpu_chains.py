@@ -328,3 +328,16 @@ def test_edge_trace_matches_oracle_replay(bnos, tiny8):
     whole = et
     assert np.array_equal(a["edge_trace"].cpu().numpy().view(np.uint32), whole[:, :120 // every + 1])
     assert np.array_equal(b["edge_trace"].cpu().numpy().view(np.uint32), whole[:, 120 // every:])
+
+
+@pytest.mark.parametrize("bt", [2, 8])
+def test_chains_match_oracle_other_block_shapes(bnos, tiny8, bt):
+    """Chain sweeps with 2 or 8 chains per scoring block (4 is the default)."""
+    w, t, orc = tiny8
+    iters, C = 1000, 12
+    t.set_launch(C, orders_per_block=bt)
+    try:
+        g = gpu_chains(t, C, iters, seed=103)
+    finally:
+        t.set_launch(C)
+    assert compare_chains(g, orc, w.K, 103, iters, 0) >= C - 1

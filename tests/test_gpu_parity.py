@@ -570,3 +570,16 @@ def test_maximum_size_64_nodes_K4(bnos):
     finally:
         t.set_launch(1)
         t.free()
+
+
+@pytest.mark.parametrize("bt", [2, 8])
+def test_batched_block_shapes_match_oracle(bnos, prior20, bt):
+    """Scoring launches with 2 or 8 orders per block (4 is the default for 4+ orders)."""
+    w, net, prior, t, orc = prior20
+    orders = datagen.random_orders(w.n, 11, seed=40 + bt)
+    t.set_launch(11, orders_per_block=bt)
+    try:
+        got = dev_score(t, orders)
+    finally:
+        t.set_launch(11)
+    check_orders_against_oracle(got, orc, w.K, orders)
