@@ -72,6 +72,26 @@ def cpu_baseline(net, prior, K: int, sample_nodes=(7, 41), seed: int = 3):
             t += time.perf_counter() - s
         per_node.append(t)
     t_order = float(np.mean(per_node))
+    # table build on one core: a slice of one node's row
+    t0 = time.perf_counter()
+    oracle.build_row(net.data, net.arities, K, sample_nodes[0], prior=prior, threads=1, ranks=(0, 20000))
+    build_1core = 20000 / (time.perf_counter() - t0)
+    # Metropolis-Hastings on the oracle: one chain on one core, and independent chains on
+    # every core (threads; the C calls release the GIL), on the 20-node table of the
+    # prior20 workload, whose oracle table builds in about a second
+    from paper_1210_5128_amd import datagen
+    from concurrent.futures import ThreadPoolExecutor
+    w20 = datagen.WORKLOADS["prior20"]
+    net20, prior20 = datagen.make(w20)
+    tab20 = oracle.build_table(net20.data, net20.arities, w20.K, prior=prior20)
+    it1 = 300
+    t0 = time.perf_counter()
+    oracle.run_chain(tab20, w20.K, 5, 0, it1)
+    mh_1core = it1 / (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda c: oracle.run_chain(tab20, w20.K, 5, c, it1), range(threads)))
+    mh_all = threads * it1 / (time.perf_counter() - t0)
     return {
         "value": 1.0 / t_order,
         "unit": "order-scores/s",
@@ -83,6 +103,14 @@ def cpu_baseline(net, prior, K: int, sample_nodes=(7, 41), seed: int = 3):
                    f"seconds per order = mean per-node sum = {t_order:.4f}"),
         "build_local_scores_per_s": n_local / t_build,
         "build_threads": threads,
+        "build_local_scores_per_s_1core": build_1core,
+        "table_build_s_1core_estimate": n * oracle.num_sets(n - 1, K) / build_1core,
+        "mh_iterations_per_s_1core_n60": 1.0 / t_order,
+        "mh_note": ("an oracle MH iteration rescores the whole proposed order by enumeration, so at n=60 its "
+                    "rate is the order-scoring rate above; measured directly on the 20-node prior20 table:"),
+        "mh_iterations_per_s_1core_n20": mh_1core,
+        "mh_iterations_per_s_all_cores_n20": mh_all,
+        "mh_all_cores_threads": threads,
         "cpu_model": cpu_model(),
         "cpu_count": os.cpu_count(),
         "affinity_cores": len(os.sched_getaffinity(0)),
@@ -109,33 +137,136 @@ def measured_traffic(batch: int, mode: str):
     return None
 
 
-def bench_chains(bnos, datagen, wname: str, chains: int, iters: int, seed: int = 102):
-    """Batched MH chains vs one chain on the same table: iterations/s and ESS/s of the
-    log-sum-exp score trace (Geyer initial-monotone ESS after 20% burn-in, summed over chains)."""
+STATE_KEYS = ("orders", "scores", "best_graphs", "best_scores", "accepted")
+
+
+def sample_until_mixed(table, state, C, first, block, max_blocks, seed, every, edges=None, mlp=None, eps=0.5,
+                       rhat_target=1.05):
+    """Advance burned-in chains (state after `first` iterations) in blocks of `block`
+    iterations, tracing the score (and edge indicators) every `every` iterations, until
+    the rank-normalised split-R-hat of the pooled trace is below `rhat_target` or
+    `max_blocks` blocks ran.  Returns (score traces [C][T], edge traces [C][T] or None,
+    sampling seconds, iterations, accepted moves)."""
     import torch
     from paper_1210_5128_amd import ess as E
+    dev = state["scores"].device
+    traces, etr, secs, done = [], [], 0.0, 0
+    acc0 = state["accepted"].clone()
+    for k in range(max_blocks):
+        s2 = {key: state[key] for key in STATE_KEYS}
+        s2["trace"] = torch.zeros((C, block // every + 1), dtype=torch.float64, device=dev)
+        if edges:
+            s2["edges"] = np.asarray(edges, dtype=np.int32)
+            s2["edge_trace"] = torch.zeros((C, block // every + 1), dtype=torch.int32, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        table.run_chains(s2, block, seed, first_iteration=first + done, trace_every=every, mlp=mlp, eps=eps)
+        torch.cuda.synchronize()
+        secs += time.perf_counter() - t0
+        done += block
+        traces.append(s2["trace"].cpu().numpy()[:, 1:])
+        if edges:
+            etr.append(s2["edge_trace"].cpu().numpy().view(np.uint32)[:, 1:])
+        tr = np.concatenate(traces, axis=1)
+        if E.rhat_rank(tr, burn=0.0) < rhat_target:
+            break
+    acc = float((state["accepted"] - acc0).sum().item())
+    return tr, (np.concatenate(etr, axis=1) if edges else None), secs, done, acc
+
+
+def chain_stats(tr, et, secs, C, iters, acc, n_edges):
+    """ESS figures of one sampler's post-burn-in traces: summed per-chain Geyer ESS, the
+    rank-normalised multi-chain (bulk) ESS, rank split-R-hat, and per-edge bulk ESS."""
+    from paper_1210_5128_amd import ess as E
+    out = {"chains": C, "iterations": iters, "seconds": secs, "chain_iterations_per_s": C * iters / secs,
+           "accept_rate": acc / (C * iters), "ess_summed": E.ess(tr, burn=0.0), "ess_bulk": E.ess_bulk(tr, burn=0.0),
+           "rhat_rank": E.rhat_rank(tr, burn=0.0), "score_mean": float(tr.mean()),
+           "score_mcse": E.mcse_mean(tr, burn=0.0)}
+    out["ess_bulk_per_s"] = out["ess_bulk"] / secs
+    out["ess_summed_per_s"] = out["ess_summed"] / secs
+    if et is not None:
+        ee = [E.ess_bulk(((et >> np.uint32(k)) & np.uint32(1)).astype(np.float64), burn=0.0) for k in range(n_edges)]
+        out["edge_ess_bulk_min"] = float(np.nanmin(ee))
+        out["edge_ess_bulk_min_per_s"] = out["edge_ess_bulk_min"] / secs
+        out["edge_rhat_max"] = float(np.nanmax([E.rhat_rank(((et >> np.uint32(k)) & np.uint32(1)).astype(np.float64),
+                                                            burn=0.0) for k in range(n_edges)]))
+    return out
+
+
+def agreement(tr_a, et_a, tr_b, et_b, n_edges):
+    """Posterior mean score and edge frequencies of two samplers within 3 combined MCSE."""
+    from paper_1210_5128_amd import ess as E
+    d, tol, ok = E.agree_within_mcse(tr_a, tr_b, burn=0.0)
+    out = {"score_mean_diff": d, "score_3mcse": tol, "score_agrees": ok}
+    if et_a is not None and et_b is not None:
+        agree, worst = 0, 0.0
+        for k in range(n_edges):
+            xa = ((et_a >> np.uint32(k)) & np.uint32(1)).astype(np.float64)
+            xb = ((et_b >> np.uint32(k)) & np.uint32(1)).astype(np.float64)
+            dk, tk, okk = E.agree_within_mcse(xa, xb, burn=0.0)
+            agree += int(okk)
+            worst = max(worst, dk)
+        out.update(edges=n_edges, edges_agree=agree, edge_freq_max_diff=worst)
+    return out
+
+
+def bench_chains(bnos, datagen, wname: str, chains: int, block: int, burn: int, max_blocks: int,
+                 seed: int = 102, every: int = 10):
+    """Batched MH chains vs one chain on the same table.  Both burn in for `burn`
+    iterations, then sample in blocks of `block` iterations until the rank split-R-hat of
+    the score trace is below 1.05 (at most `max_blocks` blocks).  ESS/s uses the
+    rank-normalised multi-chain ESS of the sampling phase; 'same_accuracy' states whether
+    both reached R-hat < 1.05 and agree on the posterior mean score and on the frequencies
+    of the 20 most uncertain edges within 3 MCSE.  The chain sweep's launch shape is
+    autotuned on burned-in chains first (tuned vs default chain-iterations/s reported)."""
+    import torch
     w = datagen.WORKLOADS[wname]
     net, prior = datagen.make(w)
     table = bnos.build_score_table(net.data, net.arities, w.K, ess=w.ess, prior=prior)
-    out = {"workload": f"{w.name}: n={w.n}, K={w.K}, N={w.N}", "iterations": iters}
+    out = {"workload": f"{w.name}: n={w.n}, K={w.K}, N={w.N}", "burn_in": burn, "trace_every": every}
+    res = {}
     for label, C in (("batched", chains), ("single", 1)):
-        st = table.new_chain_state(C, iters, trace_every=1)
-        table.run_chains(st, min(iters, 50), seed + 1000, sweep_len=32)     # warm-up (separate seed)
-        torch.cuda.synchronize()
-        st = table.new_chain_state(C, iters, trace_every=1)
+        st = table.new_chain_state(C, burn, trace_every=burn)
         t0 = time.perf_counter()
-        table.run_chains(st, iters, seed, sweep_len=32)
+        table.run_chains(st, burn, seed, trace_every=burn)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        tr = st["trace"].cpu().numpy()
-        e = E.ess(tr)
-        out[label] = {"chains": C, "seconds": dt, "chain_iterations_per_s": C * iters / dt,
-                      "ess": e, "ess_per_s": e / dt,
-                      "accept_rate": float(st["accepted"].sum().item()) / (C * iters),
-                      "best_score_max": float(st["best_scores"].max().item()),
-                      "split_rhat": E.split_rhat(tr) if C > 1 else None}
-        print(f"# chains {label}: {C}x{iters} in {dt:.2f} s, ESS/s {e / dt:.1f}", file=sys.stderr, flush=True)
-    out["ess_per_s_ratio_batched_vs_single"] = out["batched"]["ess_per_s"] / max(out["single"]["ess_per_s"], 1e-30)
+        burn_s = time.perf_counter() - t0
+        if label == "batched":
+            # chain-sweep autotuner on copies of the burned-in chains, then tuned vs default
+            cs, bt, ms = table.chains_autotune(C, 64, seed + 7, state=st, first_iteration=burn, reps=2)
+            tuned = {"chunk_steps": cs, "orders_per_block": bt, "ms_per_iteration": ms}
+            rates = {}
+            for shape in ("default", "tuned"):
+                if shape == "default":
+                    table.chains_set_launch(C, 0, 0)
+                else:
+                    table.chains_set_launch(C, cs, bt)
+                s2 = {k: st[k].clone() for k in STATE_KEYS}
+                s2["trace"] = None
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                table.run_chains(s2, 2000, seed + 9, first_iteration=burn, trace_every=2000)
+                torch.cuda.synchronize()
+                rates[shape] = C * 2000 / (time.perf_counter() - t1)
+            out["autotune"] = dict(tuned, chain_iterations_per_s_tuned=rates["tuned"],
+                                   chain_iterations_per_s_default=rates["default"])
+            print(f"# chains autotune: chunk {cs}, {bt} chains/block: {rates['tuned']:.0f} vs default "
+                  f"{rates['default']:.0f} chain-it/s", file=sys.stderr, flush=True)
+            edges = uncertain_edges(table, st["orders"], w.n)
+            out["traced_edges"] = len(edges)
+        tr, et, secs, iters, acc = sample_until_mixed(table, st, C, burn, block, max_blocks, seed + 1, every, edges)
+        res[label] = (tr, et)
+        out[label] = chain_stats(tr, et, secs, C, iters, acc, len(edges))
+        out[label]["burn_in_seconds"] = burn_s
+        print(f"# chains {label}: {C} x {iters} sampling iterations in {secs:.2f} s, bulk ESS/s "
+              f"{out[label]['ess_bulk_per_s']:.1f}, R-hat {out[label]['rhat_rank']:.3f}", file=sys.stderr, flush=True)
+    out["agreement"] = agreement(res["batched"][0], res["batched"][1], res["single"][0], res["single"][1], len(edges))
+    b, sg = out["batched"], out["single"]
+    out["ess_bulk_per_s_ratio_batched_vs_single"] = b["ess_bulk_per_s"] / max(sg["ess_bulk_per_s"], 1e-30)
+    out["ess_summed_per_s_ratio_batched_vs_single"] = b["ess_summed_per_s"] / max(sg["ess_summed_per_s"], 1e-30)
+    ag = out["agreement"]
+    out["same_accuracy"] = bool(b["rhat_rank"] < 1.05 and sg["rhat_rank"] < 1.05 and ag["score_agrees"]
+                                and ag.get("edges_agree", 0) == ag.get("edges", 0))
     table.free()
     return out
 
@@ -177,15 +308,17 @@ def bench_uneven(bnos, datagen, n_datasets: int, chains: int, iters: int, seed: 
 
 
 def bench_learned(bnos, datagen, wname: str, chains: int, moves: int, iters: int, epochs: int,
-                  eps_list=(0.1,), seed: int = 404):
+                  eps_list=(0.1,), seed: int = 404, max_blocks: int = 4, every: int = 5):
     """Learned swap proposal: harvest `moves` accepted moves from uniform chains
     (which also serves as burn-in), train the network on the device, then resume
     every chain from its harvested state twice, with the uniform and with the
     learned proposal, on the same random-number streams; plus one uniform chain
-    alone.  ESS/s of the log-sum-exp trace and the smallest ESS over the
-    indicators of the 20 most uncertain edges, acceptance, best-graph score."""
+    alone.  Each run samples in blocks of `iters` iterations until its rank
+    split-R-hat is below 1.05 (at most max_blocks blocks).  Reported: bulk
+    (rank-normalised multi-chain) ESS/s of the log-sum-exp trace and the smallest
+    over the indicators of the 20 most uncertain edges, R-hat, acceptance,
+    best-graph score, and whether learned and uniform agree within 3 MCSE."""
     import torch
-    from paper_1210_5128_amd import ess as E
     w = datagen.WORKLOADS[wname]
     net, prior = datagen.make(w)
     table = bnos.build_score_table(net.data, net.arities, w.K, ess=w.ess, prior=prior)
@@ -235,50 +368,41 @@ def bench_learned(bnos, datagen, wname: str, chains: int, moves: int, iters: int
     # edges whose frequency over chains is closest to 1/2
     edges = uncertain_edges(table, st["orders"], n)
     out["traced_edges"] = len(edges)
-    # 4. resume every chain from its harvested state: uniform vs learned, and one uniform chain alone
-    base = {k: v for k, v in st.items() if k in ("orders", "scores", "best_graphs", "best_scores", "accepted")}
+    # 4. resume every chain from its harvested state: uniform vs learned, and one uniform chain
+    # alone, each sampling in blocks until its rank split-R-hat is below 1.05 (at most
+    # max_blocks blocks of `iters` iterations)
+    base = {k: v for k, v in st.items() if k in STATE_KEYS}
     runs = [("uniform", None, chains, 0.1)]
     for k, eps in enumerate(eps_list):
         runs.append(("learned" if k == 0 else f"learned_eps{eps:g}", m, chains, eps))
     runs.append(("single_uniform", None, 1, 0.1))
+    res = {}
     for label, mlp, C, eps in runs:
         s2 = {k: v[:C].clone() for k, v in base.items()}
-        s2["trace"] = torch.zeros((C, iters + 1), dtype=torch.float64, device=base["scores"].device)
-        s2["accept_flags"] = None
-        if edges:
-            s2["edges"] = np.asarray(edges, dtype=np.int32)
-            s2["edge_trace"] = torch.zeros((C, iters + 1), dtype=torch.int32, device=base["scores"].device)
-        a0 = s2["accepted"].clone()
-        t0 = time.perf_counter()
-        table.run_chains(s2, iters, seed + 5, first_iteration=done, mlp=mlp, eps=eps)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        trc = s2["trace"].cpu().numpy()
-        e = E.ess(trc)
-        edge_ess = None
-        if edges:
-            et = s2["edge_trace"].cpu().numpy().view(np.uint32)
-            edge_ess = min(E.ess(((et >> np.uint32(k)) & np.uint32(1)).astype(np.float64))
-                           for k in range(len(edges)))
-        out[label] = {"chains": C, "eps": eps if mlp is not None else None, "seconds": dt,
-                      "chain_iterations_per_s": C * iters / dt,
-                      "ess": e, "ess_per_s": e / dt, "ess_per_1k_chain_iterations": 1e3 * e / (C * iters),
-                      "edge_ess_min": edge_ess, "edge_ess_min_per_s": None if edge_ess is None else edge_ess / dt,
-                      "accept_rate": float((s2["accepted"] - a0).sum().item()) / (C * iters),
-                      "best_score_max": float(s2["best_scores"].max().item()),
-                      "best_score_mean": float(s2["best_scores"].mean().item()),
-                      "score_mean": float(trc.mean()),
-                      "split_rhat": E.split_rhat(trc) if C > 1 else None}
-        print(f"# {label}: {dt:.2f} s, ESS {e:.0f}, ESS/s {e / dt:.1f}, min edge ESS {edge_ess}, "
+        tr, et, secs, its, acc = sample_until_mixed(table, s2, C, done, iters, max_blocks, seed + 5, every,
+                                                    edges, mlp=mlp, eps=eps)
+        res[label] = (tr, et)
+        out[label] = chain_stats(tr, et, secs, C, its, acc, len(edges))
+        out[label].update(eps=eps if mlp is not None else None,
+                          best_score_max=float(s2["best_scores"].max().item()),
+                          best_score_mean=float(s2["best_scores"].mean().item()))
+        print(f"# {label}: {C} x {its} iterations in {secs:.2f} s, bulk ESS/s {out[label]['ess_bulk_per_s']:.1f}, "
+              f"min edge bulk ESS/s {out[label].get('edge_ess_bulk_min_per_s')}, R-hat {out[label]['rhat_rank']:.3f}, "
               f"accept {out[label]['accept_rate']:.3f}", file=sys.stderr, flush=True)
-    out["ess_per_s_ratio_learned_vs_uniform"] = out["learned"]["ess_per_s"] / max(out["uniform"]["ess_per_s"], 1e-30)
-    out["ess_per_s_ratio_learned_vs_single_uniform"] = (out["learned"]["ess_per_s"] /
-                                                        max(out["single_uniform"]["ess_per_s"], 1e-30))
-    out["ess_per_iteration_ratio_learned_vs_uniform"] = (out["learned"]["ess_per_1k_chain_iterations"] /
-                                                         max(out["uniform"]["ess_per_1k_chain_iterations"], 1e-30))
+    L, U = out["learned"], out["uniform"]
+    out["agreement_learned_vs_uniform"] = agreement(res["learned"][0], res["learned"][1], res["uniform"][0],
+                                                    res["uniform"][1], len(edges))
+    out["ess_bulk_per_s_ratio_learned_vs_uniform"] = L["ess_bulk_per_s"] / max(U["ess_bulk_per_s"], 1e-30)
+    out["ess_summed_per_s_ratio_learned_vs_uniform"] = L["ess_summed_per_s"] / max(U["ess_summed_per_s"], 1e-30)
+    out["ess_bulk_per_s_ratio_learned_vs_single_uniform"] = (L["ess_bulk_per_s"] /
+                                                             max(out["single_uniform"]["ess_bulk_per_s"], 1e-30))
     if edges:
-        out["edge_ess_min_per_s_ratio_learned_vs_uniform"] = (out["learned"]["edge_ess_min_per_s"] /
-                                                              max(out["uniform"]["edge_ess_min_per_s"], 1e-30))
+        out["edge_ess_bulk_min_per_s_ratio_learned_vs_uniform"] = (L["edge_ess_bulk_min_per_s"] /
+                                                                   max(U["edge_ess_bulk_min_per_s"], 1e-30))
+    ag = out["agreement_learned_vs_uniform"]
+    out["same_accuracy"] = bool(L["rhat_rank"] < 1.05 and U["rhat_rank"] < 1.05 and ag["score_agrees"]
+                                and ag.get("edges_agree", 0) == ag.get("edges", 0)
+                                and L["best_score_max"] >= U["best_score_max"])
     m.free()
     table.free()
     return out
@@ -471,11 +595,20 @@ def main():
     ap.add_argument("--computed-masks", type=int, choices=(0, 1), default=1,
                     help="1: one-order scoring blocks compute the masks from per-4-entry anchors (6 B/entry); "
                          "0: they read the stored masks (12 B/entry)")
+    ap.add_argument("--hbm-tables", type=int, default=2,
+                    help="also time the one-order pass alternating over this many independently built tables "
+                         "(1 = skip)")
     ap.add_argument("--chains", type=int, default=256, help="batched chains on the mixed40 table (0 = skip)")
-    ap.add_argument("--chain-iters", type=int, default=20000)
+    ap.add_argument("--chain-iters", type=int, default=20000, help="sampling iterations per block")
+    ap.add_argument("--chain-burn", type=int, default=20000, help="burn-in iterations before sampling")
+    ap.add_argument("--chain-blocks", type=int, default=4,
+                    help="at most this many sampling blocks, stopping once the rank split-R-hat is below 1.05")
     ap.add_argument("--learned", type=int, default=256, metavar="C",
                     help="learned-proposal comparison with C chains on the mixed60 table (0 = skip)")
-    ap.add_argument("--learned-iters", type=int, default=4000, help="iterations of each compared run")
+    ap.add_argument("--learned-iters", type=int, default=4000, help="iterations per sampling block of each "
+                    "compared run")
+    ap.add_argument("--learned-blocks", type=int, default=4,
+                    help="at most this many sampling blocks per run, stopping once the rank split-R-hat is below 1.05")
     ap.add_argument("--learned-moves", type=int, default=1000000, help="accepted moves harvested for training")
     ap.add_argument("--learned-epochs", type=int, default=16)
     ap.add_argument("--learned-eps", default="0.5,0.1",
@@ -538,63 +671,80 @@ def main():
     S = info["entries_per_node"]
     print(f"# table built in {build_s:.3f} s, S={S}", file=sys.stderr, flush=True)
 
-    bytes_per_pass = 12 * n * S                           # (u64 mask + f32 score) per entry, one full scan
+    def launch_bytes(tab, ords, Bq, skip, eb, passes):
+        """Algorithmic bytes of one scoring launch of these orders: with tile skipping the
+        64-entry sub-tiles it loads (64 x eb bytes) plus the 8-byte summary of every tile of
+        each pass and, with one order per block, of every sub-tile; without, the full scan."""
+        if not skip:
+            return eb * n * S * passes
+        tl, per_pass = tab.count_tiles(ords)
+        sub_summaries = per_pass if passes == Bq else 0
+        return tl * 64 * eb + passes * (per_pass // 4 + sub_summaries) * 8
 
-    def timed(Bq, steps, warmup, skip=True):
-        table.tile_skip(skip)
+    def timed(Bq, steps, warmup, skip=True, tables=None, seed_base=5):
+        """Time `steps` scoring launches of Bq random orders each, rotating over `tables`
+        (launch s uses tables[s % len]); the kernel time comes from HIP events on every
+        7th launch of each table (every launch for batches), and the algorithmic bytes
+        are those of exactly the launches that carried events."""
+        tabs = tables or [table]
+        for tb in tabs:
+            tb.tile_skip(skip)
         pool = max(8, min(64, steps))
-        pool = pool - 1 if pool % 7 == 0 else pool      # sampled launches visit every order
-        orders = torch.from_numpy(datagen.random_orders(n, pool * Bq, seed=5 + Bq).reshape(pool, Bq, n)).to(dev)
+        pool = pool - 1 if pool % 7 == 0 else pool
+        orders = torch.from_numpy(datagen.random_orders(n, pool * Bq, seed=seed_base + Bq).reshape(pool, Bq, n)).to(dev)
         lse = torch.empty(Bq, dtype=torch.float64, device=dev)
         mx = torch.empty(Bq, dtype=torch.float64, device=dev)
         best = torch.empty((Bq, n), dtype=torch.int64, device=dev)
         views = [orders[i] for i in range(pool)]      # made once: the loop only launches
-        for s in range(warmup):
-            table.score_orders(views[s % pool], lse, mx, best, stream=stream)
+        T = len(tabs)
+        for s_ in range(warmup):
+            tabs[s_ % T].score_orders(views[s_ % pool], lse, mx, best, stream=stream)
         torch.cuda.synchronize()
-        # events on 1 launch in 7 for short launches (an event pair costs the host ~15 us
-        # per launch, which would make a single-order loop host-bound), spread over the
-        # whole timed region and, 7 being prime to the pool size, over every order of the
-        # pool (whose sub-tiles the algorithmic bytes count); on every launch for batches
-        table.timing(True, every=7 if Bq < 16 else 1)
+        every = 7 if Bq < 16 else 1
+        for tb in tabs:
+            tb.timing(True, every=every)
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         ev0.record(stream)
-        for s in range(steps):
-            table.score_orders(views[s % pool], lse, mx, best, stream=stream)
+        for s_ in range(steps):
+            tabs[s_ % T].score_orders(views[s_ % pool], lse, mx, best, stream=stream)
         ev1.record(stream)
         torch.cuda.synchronize()
         total_ms = ev0.elapsed_time(ev1)
-        k_ms, k_launches, k_passes = table.timing_read()
-        table.timing(False)
-        tiles, tiles_per_pass = 0, 1
-        if skip:          # tiles the launches read: counted by a separate kernel over the same orders
-            for s in range(steps):
-                tl, tiles_per_pass = table.count_tiles(orders[s % pool])
-                tiles += tl
-                if s + 1 == pool:
-                    tiles = tiles * steps // pool
-                    break
+        k_ms, k_launches, k_passes = 0.0, 0, 0
+        for tb in tabs:
+            a, b_, c_ = tb.timing_read()
+            tb.timing(False)
+            k_ms, k_launches, k_passes = k_ms + a, k_launches + b_, k_passes + c_
+        # the launches that carried events: the (s // T)-th launch of table s % T, timed when
+        # that count is a multiple of `every`
+        timed_s = [s_ for s_ in range(steps) if (s_ // T) % every == 0]
+        assert len(timed_s) == k_launches, (len(timed_s), k_launches)
         kernel_avg_ms = k_ms / k_launches
         passes_per_launch = k_passes / k_launches
-        # bytes the launch had to read: with tile skipping, the 64-entry sub-tiles it
-        # loaded (64 x 12 B) plus the 8-byte summary of every tile of each pass and,
-        # with one order per block, of every sub-tile; without, the full scan
         # bytes per entry: a one-order block with computed masks reads the score and a quarter
         # of an 8-byte anchor mask (6 B); otherwise mask + score (12 B)
         eb = 6 if (args.computed_masks and passes_per_launch == Bq) else 12
-        if skip:
-            sub_summaries = tiles_per_pass if passes_per_launch == Bq else 0
-            alg = tiles / steps * 64 * eb + passes_per_launch * (tiles_per_pass // 4 + sub_summaries) * 8
-        else:
-            alg = eb * n * S * passes_per_launch
+        cache = {}
+        alg_tot, tiles_tot, per_pass = 0.0, 0, 1
+        for s_ in timed_s:
+            key = (s_ % T, s_ % pool)
+            if key not in cache:
+                cache[key] = launch_bytes(tabs[s_ % T], views[s_ % pool], Bq, skip, eb, passes_per_launch)
+                if skip:
+                    cache[key] = (cache[key], *tabs[s_ % T].count_tiles(views[s_ % pool]))
+                else:
+                    cache[key] = (cache[key], 0, 1)
+            alg_tot += cache[key][0]
+            tiles_tot += cache[key][1]
+            per_pass = cache[key][2]
+        alg = alg_tot / len(timed_s)
         gbs = alg / (kernel_avg_ms / 1e3) / 1e9
         return dict(total_ms=total_ms, ms_per_step=total_ms / steps, value=Bq * steps / (total_ms / 1e3),
                     kernel_avg_ms=kernel_avg_ms, passes_per_launch=passes_per_launch, gbs=gbs, alg_bytes=alg,
-                    entry_bytes=eb,
-                    tile_fraction=tiles / max(1, steps * passes_per_launch * tiles_per_pass),
-                    full_scan_equiv_gbs=bytes_per_pass * passes_per_launch / (kernel_avg_ms / 1e3) / 1e9)
+                    entry_bytes=eb, timed_launches=len(timed_s),
+                    tile_fraction=tiles_tot / max(1, len(timed_s) * passes_per_launch * per_pass) if skip else 1.0)
 
     stream = torch.cuda.current_stream()
     # launch shape (chunk length, orders per block) tuned per batch size before timing
@@ -607,7 +757,8 @@ def main():
               f", {ms * 1e3:.1f} us", file=sys.stderr, flush=True)
     if args.chunk_steps:
         tuned = {"fixed_chunk_steps": args.chunk_steps}
-    rf = r = None
+    rf = r = rs = rh = None
+    extra_steps = max(args.steps, 140)
     if args.passes != "skip":
         rf = timed(B, args.steps, args.warmup, skip=False)     # full scan of every entry
         print(f"# full scan: {rf['total_ms']:.3f} ms for {args.steps} steps", file=sys.stderr, flush=True)
@@ -616,13 +767,54 @@ def main():
     else:
         r = rf
     print(f"# timed {args.steps} steps: {r['total_ms']:.3f} ms", file=sys.stderr, flush=True)
+    if args.passes == "both" and B == 1:
+        # the stored-mask full scan: 12 B x n x S = 352 MB per launch at n = 60, more than the
+        # 256 MB Infinity Cache holds, so every launch streams from HBM
+        table.computed_masks(False)
+        rs = timed(B, extra_steps, args.warmup, skip=False)
+        table.computed_masks(bool(args.computed_masks))
+        print(f"# stored-mask full scan: {rs['kernel_avg_ms'] * 1e3:.1f} us per launch, {rs['gbs']:.0f} GB/s",
+              file=sys.stderr, flush=True)
+    if args.hbm_tables > 1 and args.passes != "full" and B == 1:
+        # the headline pass alternating over independently built tables of the same shape:
+        # their combined read set exceeds the Infinity Cache, so launches stream from HBM
+        others = []
+        for k in range(1, args.hbm_tables):
+            w2 = datagen.Workload(f"{w.name}-{k}", w.n, w.N, w.arity_choices, w.dmax, w.K, w.data_seed + 100 * k,
+                                  None if w.prior_seed is None else w.prior_seed + 100 * k, w.ess)
+            net2, prior2 = datagen.make(w2)
+            t2 = bnos.build_score_table(net2.data, net2.arities, K, ess=w.ess, prior=prior2,
+                                        chunk_steps=args.chunk_steps)
+            t2.computed_masks(bool(args.computed_masks))
+            if str(B) in tuned:
+                t2.set_launch(B, gather=tuned[str(B)]["gather"], chunk_steps=tuned[str(B)]["chunk_steps"],
+                              orders_per_block=tuned[str(B)]["orders_per_block"])
+            others.append(t2)
+        rh = timed(B, extra_steps * args.hbm_tables, args.warmup, skip=True, tables=[table] + others)
+        read_set = sum(tb.info()["entries_per_node"] for tb in [table] + others) * n * 6
+        for t2 in others:
+            t2.free()
+        print(f"# {args.hbm_tables} tables alternating: {rh['kernel_avg_ms'] * 1e3:.1f} us per launch, "
+              f"{rh['gbs']:.0f} GB/s", file=sys.stderr, flush=True)
     ms_per_step, value = r["ms_per_step"], r["value"]
     kernel_avg_ms, passes_per_launch, achieved_gbs = r["kernel_avg_ms"], r["passes_per_launch"], r["gbs"]
     full_scan = None if rf is None else {
         "order_scores_per_s": rf["value"], "ms_per_step": rf["ms_per_step"],
         "kernel_avg_us": rf["kernel_avg_ms"] * 1e3, "algorithmic_bytes_per_launch": rf["alg_bytes"],
-        "achieved_GBs": rf["gbs"], "frac": rf["gbs"] / HBM_PEAK_GBS,
+        "effective_GBs": rf["gbs"], "frac": rf["gbs"] / HBM_PEAK_GBS, "bytes_per_entry": rf["entry_bytes"],
         "traffic": measured_traffic(B, "full") if args.workload == "mixed60" else None}
+    full_scan_stored = None if rs is None else {
+        "kernel": "k_score (full scan, stored masks)", "kernel_avg_us": rs["kernel_avg_ms"] * 1e3,
+        "timed_launches": rs["timed_launches"], "algorithmic_bytes_per_launch": rs["alg_bytes"],
+        "bytes_per_entry": rs["entry_bytes"], "achieved_GBs": rs["gbs"], "frac": rs["gbs"] / HBM_PEAK_GBS,
+        "note": "one launch reads 12 B x n x S, more than the 256 MB Infinity Cache: HBM-resident"}
+    hbm_resident = None if rh is None else {
+        "tables": args.hbm_tables, "read_set_bytes": read_set, "kernel": "k_score (tile skipping)",
+        "kernel_avg_us": rh["kernel_avg_ms"] * 1e3, "timed_launches": rh["timed_launches"],
+        "algorithmic_bytes_per_launch": rh["alg_bytes"], "achieved_GBs": rh["gbs"], "frac": rh["gbs"] / HBM_PEAK_GBS,
+        "order_scores_per_s": rh["value"],
+        "note": "B=1 launches alternating over independently built tables whose scores and anchors together "
+                "exceed the 256 MB Infinity Cache"}
     batched = None
     if args.batched_check:
         rb = timed(args.batched_check, 20, 3)
@@ -663,9 +855,13 @@ def main():
             "algorithmic_bytes_per_launch": r["alg_bytes"],
             "bytes_per_entry": r["entry_bytes"],
             "tile_fraction_read": r["tile_fraction"] if args.passes != "full" else 1.0,
-            "full_scan_equivalent_GBs": r["full_scan_equiv_gbs"],
+            "timed_launches": r["timed_launches"],
+            "note": ("effective bandwidth: the pass's scores and anchors (176 MB at n=60) fit the 256 MB Infinity "
+                     "Cache between launches; hbm_resident and full_scan_stored_masks stream from HBM"),
         },
+        "hbm_resident": hbm_resident,
         "full_scan": full_scan,
+        "full_scan_stored_masks": full_scan_stored,
         "batched": batched,
         "build_s": build_s,
         "table_device_bytes": info["device_bytes"],
@@ -673,7 +869,8 @@ def main():
                           "note": "per-iteration time 0.3427 s at n=60, s=4; its data are not described"},
     }
     if args.chains:
-        out["chains"] = bench_chains(bnos, datagen, "mixed40", args.chains, args.chain_iters)
+        out["chains"] = bench_chains(bnos, datagen, "mixed40", args.chains, args.chain_iters, args.chain_burn,
+                                     args.chain_blocks)
     if args.uneven:
         out["uneven"] = bench_uneven(bnos, datagen, args.uneven, 64, args.uneven_iters)
     if args.accuracy:
@@ -684,7 +881,8 @@ def main():
     if args.learned:
         out["learned"] = bench_learned(bnos, datagen, args.learned_workload, args.learned, args.learned_moves,
                                        args.learned_iters, epochs=args.learned_epochs,
-                                       eps_list=[float(x) for x in args.learned_eps.split(",")])
+                                       eps_list=[float(x) for x in args.learned_eps.split(",")],
+                                       max_blocks=args.learned_blocks)
     if not args.no_cpu:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(net, prior, K)

@@ -152,7 +152,10 @@ bnos_status bnos_table_node_features(bnos_table t, double *out);
 
 /*
  * Contingency counts N_ijk on the device for Q queries (node[q], parent
- * mask[q]), with the same counting kernel the table build uses.
+ * mask[q]), with the counting code the table's build used: for count_mode 0
+ * (the default) the joint histogram of the node subset U = parents + node,
+ * read out as the family's cells; for count_mode 1 (or when the build fell
+ * back to it) the per-family histogram.
  *   nodes, masks   host arrays [Q]; masks must not contain the query's node
  *                  and hold at most K members.
  *   counts         host uint32 array with cap entries; query q's cells start
@@ -345,6 +348,36 @@ bnos_status bnos_run_chains(bnos_table t, const bnos_chain_cfg *cfg, bnos_chain_
  */
 bnos_status bnos_run_chains_multi(const bnos_table *tables, int32_t T, const bnos_chain_cfg *cfg,
                                   bnos_chain_state *states, void *stream);
+
+/*
+ * Chain-sweep autotuner (Sec. III.C's iterations, batched): times
+ * cfg->iterations iterations of cfg->chains chains on this table -- the real
+ * sweep: window work lists, the window nodes' scoring pass, the merge and MH
+ * decision -- for every chunk length (powers of two dividing the row padding)
+ * and every number of chains per scoring block (1, 2, 4, 8, at most C),
+ * `reps` timed runs each after one warm-up, and keeps the fastest for this
+ * table and the chain count's bucket (1, 2-3, 4-7, 8-15, 16+).  Later sweeps
+ * of that many chains on this table (bnos_run_chains, and bnos_run_chains_multi
+ * where it is the first table: the chains per block are per launch) use it.
+ * With cfg->first_iteration > 0 every timed run resumes from a copy of `state`
+ * (orders, scores, best_graphs, best_scores, accepted; e.g. burned-in chains);
+ * with 0 they start fresh from cfg->seed and state may be NULL.  The caller's
+ * state is never written.  cfg->iterations in [1, 2^20], reps in [1, 100].
+ * Outputs (may be NULL): the chosen chunk steps, chains per block, and the
+ * device time per iteration in ms.  A shape changes the association of the
+ * FP32 log-sum-exp partial sums, not the argmax.  Synchronous.
+ */
+bnos_status bnos_chains_autotune(bnos_table t, const bnos_chain_cfg *cfg, const bnos_chain_state *state,
+                                 int32_t reps, void *stream, int32_t *chunk_steps, int32_t *orders_per_block,
+                                 double *ms_per_iteration);
+
+/*
+ * Fix the chain-sweep launch for `chains` chains (their bucket, as above):
+ * chunk_steps a power of two dividing the row padding or 0 (the scoring
+ * shape of a batch of that many orders), orders_per_block 1, 2, 4, 8 or 0
+ * (the default rule).  Waits for work in flight.
+ */
+bnos_status bnos_chains_set_launch(bnos_table t, int32_t chains, int32_t chunk_steps, int32_t orders_per_block);
 
 /*
  * Kernel timing for measurement: while enabled (enable = k >= 1), every k-th

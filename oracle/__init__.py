@@ -150,27 +150,30 @@ def build_table(data, arities, K: int, ess: float = 1.0, log_gamma: float = 0.0,
 
 
 def build_row(data, arities, K: int, node: int, ess: float = 1.0, log_gamma: float = 0.0, prior=None,
-              prior_mode: int = 0, threads: int = 1) -> np.ndarray:
+              prior_mode: int = 0, threads: int = 1, ranks=None) -> np.ndarray:
     """FP64 row of one node, indexed by the oracle's combinatorial rank.
 
     ``threads`` > 1 splits the rank range over that many threads (the C call
     releases the GIL); every entry is still computed by the same plain code.
+    ``ranks`` = (r0, r1) computes only the entries r0 <= rank < r1 (the rest
+    of the returned row stays 0).
     """
     data, ar, pr = _prep(data, arities, prior)
     n = data.shape[1]
     S = num_sets(n - 1, K)
     out = np.zeros(S, dtype=np.float64)
     L = lib()
+    lo, hi = (0, S) if ranks is None else (max(0, int(ranks[0])), min(S, int(ranks[1])))
 
     def part(r0, r1):
         L.orc_build_row(_p(data), data.shape[0], n, _p(ar), K, ess, log_gamma,
                         None if pr is None else _p(pr), prior_mode, node, r0, r1, _p(out))
 
     if threads <= 1:
-        part(0, S)
+        part(lo, hi)
     else:
         from concurrent.futures import ThreadPoolExecutor
-        cuts = [S * k // (4 * threads) for k in range(4 * threads + 1)]
+        cuts = [lo + (hi - lo) * k // (4 * threads) for k in range(4 * threads + 1)]
         with ThreadPoolExecutor(threads) as ex:
             list(ex.map(lambda k: part(cuts[k], cuts[k + 1]), range(4 * threads)))
     return out

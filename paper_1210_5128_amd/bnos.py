@@ -84,6 +84,8 @@ _SIGS = {
     "bnos_table_count_tiles": (i32, [P, P, i32, P, P]),
     "bnos_table_autotune": (i32, [P, P, i32, i32, P, P, P, P, P]),
     "bnos_table_set_launch": (i32, [P, i32, i32, i32, i32]),
+    "bnos_chains_autotune": (i32, [P, P, P, i32, P, P, P, P]),
+    "bnos_chains_set_launch": (i32, [P, i32, i32, i32]),
     "bnos_table_timing_read": (i32, [P, P, P, P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -243,6 +245,23 @@ class Table:
         edges = _state_edges(cfg, [state])
         st = _chain_state(state, iterations, trace_every)
         _check(_lib.bnos_run_chains(self._h, ctypes.byref(cfg), ctypes.byref(st), _stream(stream)))
+
+    def chains_autotune(self, chains: int, iterations: int, seed: int, state: Optional[dict] = None,
+                        first_iteration: int = 0, target: int = 0, reps: int = 1, mlp=None, eps=0.5, stream=None):
+        """Pick the chain-sweep launch for `chains` chains by timing `iterations` real
+        iterations per shape (bnos_chains_autotune); with first_iteration > 0 each run
+        resumes from a copy of `state` -> (chunk steps, chains per block, ms per iteration)."""
+        cfg = _chain_cfg(chains, iterations, seed, target, first_iteration, 1, 0, 0, mlp, eps)
+        st = _chain_state(state, iterations, 1) if state is not None else None
+        cs, bt, ms = i32(), i32(), f64()
+        _check(_lib.bnos_chains_autotune(self._h, ctypes.byref(cfg), ctypes.byref(st) if st is not None else None,
+                                         reps, _stream(stream), ctypes.byref(cs), ctypes.byref(bt),
+                                         ctypes.byref(ms)))
+        return cs.value, bt.value, ms.value
+
+    def chains_set_launch(self, chains: int, chunk_steps: int = 0, orders_per_block: int = 0):
+        """Fix the chain-sweep launch for `chains` chains (bnos_chains_set_launch); 0, 0 = default."""
+        _check(_lib.bnos_chains_set_launch(self._h, int(chains), int(chunk_steps), int(orders_per_block)))
 
     def autotune(self, orders, reps: int = 5, stream=None):
         """Pick the launch for this batch size (bnos_table_autotune):

@@ -39,6 +39,7 @@ struct TableT {
     int chunks = 0;                 // scoring blocks per node = S_pad / chunk_entries
     int pad_steps = 1;              // rows are padded to a multiple of pad_steps * 1024 entries
     int max_cells = 0;
+    int count_mode = 0;             // counting code the build used: 0 joint histograms, 1 per family
     double ess = 1.0, log_gamma = 0.0;
     int device = 0;
 
@@ -91,10 +92,23 @@ struct TableT {
         return B >= 8 ? pad_steps * 1024 : chunk_entries;
     }
     int chunks_for(int B) const { return (int)(S_pad / chunk_entries_for(B)); }
-    // partials of one launch: [B][chunks][n], with n slots per order in gather mode
+    // Chain sweeps of C chains have their own launch shape (bnos_chains_autotune /
+    // bnos_chains_set_launch) per chain-count bucket; 0 = the scoring shape of a
+    // batch of C orders, except that the orders per block follow pick_bt.
+    int chain_bt[5] = {0, 0, 0, 0, 0};
+    int chain_cs[5] = {0, 0, 0, 0, 0};
+    int chain_chunk_entries_for(int C) const
+    {
+        const int cs = chain_cs[bucket(C)];
+        return cs > 0 ? cs * 1024 : chunk_entries_for(C);
+    }
+    int chain_chunks_for(int C) const { return (int)(S_pad / chain_chunk_entries_for(C)); }
+    // partials of one launch: [B][chunks][n], with n slots per order in gather mode; a chain
+    // sweep of B chains writes [B][chain chunks][n]
     int64_t workspace_bytes_for(int B) const
     {
-        const int c = chunks_for(B) > n ? chunks_for(B) : n;
+        int c = chunks_for(B) > n ? chunks_for(B) : n;
+        if (chain_chunks_for(B) > c) c = chain_chunks_for(B);
         return (int64_t)B * n * c * (int64_t)sizeof(Partial);
     }
     bool gather_for(int B) const { return K <= 4 && tuned_gather[bucket(B)] != 0; }

@@ -220,16 +220,109 @@ __device__ __forceinline__ int64_t rank_ascending(uint64_t m, int bits, int K, c
     return r;
 }
 
+// A node subset U (|U| <= K+1) as the joint histogram sees it: members
+// ascending, their arities, and the stride of each member's digit in the joint
+// cell index (the last member fastest).
+struct Subset {
+    int u[kMaxK + 1], r[kMaxK + 1], stride[kMaxK + 1];
+    int j;        // members
+    int cells;    // product of the members' arities
+};
+
+__device__ __forceinline__ Subset decode_subset(uint64_t U, const int32_t *__restrict__ ar)
+{
+    Subset S;
+    S.j = 0;
+    uint64_t m = U;
+#pragma unroll
+    for (int t = 0; t <= kMaxK; ++t) {
+        S.u[t] = 0;
+        S.r[t] = 1;
+        if (m) {
+            S.u[t] = __builtin_ctzll(m);
+            m &= m - 1;
+            S.r[t] = ar[S.u[t]];
+            S.j = t + 1;
+        }
+    }
+    int cells = 1;
+#pragma unroll
+    for (int t = kMaxK; t >= 0; --t) {
+        S.stride[t] = cells;
+        if (t < S.j) cells *= S.r[t];
+    }
+    S.cells = cells;
+    return S;
+}
+
+// Joint histogram of U's variables over the N samples into hist[0 .. cells)
+// (one wavefront, its private LDS region); each lane takes 4 consecutive
+// samples per step from 32-bit loads of the column-major data.
+__device__ __forceinline__ void joint_histogram(const uint8_t *__restrict__ data, int64_t N, int64_t N_pad,
+                                                const Subset &S, uint32_t *hist, int lane)
+{
+    for (int c = lane; c < S.cells; c += 64) hist[c] = 0u;
+    wave_lds_sync();
+    const uint32_t *col[kMaxK + 1];
+#pragma unroll
+    for (int t = 0; t <= kMaxK; ++t) col[t] = reinterpret_cast<const uint32_t *>(data + (int64_t)S.u[t] * N_pad);
+    for (int64_t base = (int64_t)lane * 4; base < N; base += 256) {
+        uint32_t x[kMaxK + 1];
+#pragma unroll
+        for (int t = 0; t <= kMaxK; ++t) x[t] = (t < S.j) ? col[t][base >> 2] : 0u;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            int cell = 0;
+#pragma unroll
+            for (int t = 0; t <= kMaxK; ++t) cell += S.stride[t] * (int)((x[t] >> (8 * b)) & 0xffu);
+            if (base + b < N) atomicAdd(&hist[cell], 1u);
+        }
+    }
+    wave_lds_sync();
+}
+
+// Member c of U as the child of the family (u_c, U \ {u_c}): its id, arity and
+// digit stride, selected without indexing the arrays by c.
+__device__ __forceinline__ void subset_member(const Subset &S, int c, int &node, int &ri, int &sci)
+{
+    node = 0;
+    ri = 1;
+    sci = 1;
+#pragma unroll
+    for (int t = 0; t <= kMaxK; ++t)
+        if (t == c) {
+            node = S.u[t];
+            ri = S.r[t];
+            sci = S.stride[t];
+        }
+}
+
+// Joint cell of parent configuration k of the family whose child is member c,
+// with the child's state 0: k's digits run over the parents ascending, the
+// last one fastest (the lowest id most significant, as in the per-family
+// count layout); the child's state x adds x * (c's stride).
+__device__ __forceinline__ int family_base(const Subset &S, int c, int k)
+{
+    int rest = k, J = 0;
+#pragma unroll
+    for (int t = kMaxK; t >= 0; --t) {
+        if (t < S.j && t != c) {
+            J += (rest % S.r[t]) * S.stride[t];
+            rest /= S.r[t];
+        }
+    }
+    return J;
+}
+
 // One wavefront per node subset U, |U| = 1 .. K+1 (U's rank + 1 among the
 // masks over n bits with at most K+1 bits): the joint histogram of U's
-// variables over the N samples, cell = sum_t x_{u_t} * stride_t (members
-// ascending, the last fastest), then for every member i of U the local score of
-// the family (i, U \ {i}) from it -- that family's N_ijk are the joint counts
-// with i's state as the child state -- stored at U \ {i}'s entry of i's row.
-// Counting once per U instead of once per family cuts the sample visits by the
-// mean family size (about 5x at K = 4).  The BDeu terms are summed in the same
-// order as in k_build (parent configurations k by lane, the lowest id most
-// significant; child states in order; the same butterfly), so the stored
+// variables over the N samples, then for every member i of U the local score
+// of the family (i, U \ {i}) from it -- that family's N_ijk are the joint
+// counts with i's state as the child state -- stored at U \ {i}'s entry of i's
+// row.  Counting once per U instead of once per family cuts the sample visits
+// by the mean family size (about 5x at K = 4).  The BDeu terms are summed in
+// the same order as in k_build (parent configurations k by lane, the lowest id
+// most significant; child states in order; the same butterfly), so the stored
 // scores are the same, bit for bit.
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_build_joint(
@@ -244,69 +337,19 @@ __global__ __launch_bounds__(WAVES * 64) void k_build_joint(
     uint32_t *hist = lds_hist + wave * cells_cap;
     for (int64_t g = (int64_t)blockIdx.x * WAVES + wave; g < n_subsets; g += (int64_t)gridDim.x * WAVES) {
         const uint64_t U = unrank_ascending(g + 1, n, K + 1, nsets);
-        int u[kMaxK + 1], r[kMaxK + 1], stride[kMaxK + 1];
-        int j = 0;
-        uint64_t m = U;
-#pragma unroll
-        for (int t = 0; t <= kMaxK; ++t) {
-            u[t] = 0;
-            r[t] = 1;
-            if (m) {
-                u[t] = __builtin_ctzll(m);
-                m &= m - 1;
-                r[t] = ar[u[t]];
-                j = t + 1;
-            }
-        }
-        int cells = 1;
-#pragma unroll
-        for (int t = kMaxK; t >= 0; --t) {
-            stride[t] = cells;
-            if (t < j) cells *= r[t];
-        }
-        // joint histogram
-        for (int c = lane; c < cells; c += 64) hist[c] = 0u;
-        wave_lds_sync();
-        const uint32_t *col[kMaxK + 1];
-#pragma unroll
-        for (int t = 0; t <= kMaxK; ++t) col[t] = reinterpret_cast<const uint32_t *>(data + (int64_t)u[t] * N_pad);
-        for (int64_t base = (int64_t)lane * 4; base < N; base += 256) {
-            uint32_t x[kMaxK + 1];
-#pragma unroll
-            for (int t = 0; t <= kMaxK; ++t) x[t] = (t < j) ? col[t][base >> 2] : 0u;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                int cell = 0;
-#pragma unroll
-                for (int t = 0; t <= kMaxK; ++t) cell += stride[t] * (int)((x[t] >> (8 * b)) & 0xffu);
-                if (base + b < N) atomicAdd(&hist[cell], 1u);
-            }
-        }
-        wave_lds_sync();
+        const Subset Sb = decode_subset(U, ar);
+        const int j = Sb.j, cells = Sb.cells;
+        joint_histogram(data, N, N_pad, Sb, hist, lane);
         // one family per member
         for (int c = 0; c < j; ++c) {
-            int node = 0, ri = 1, sci = 1;     // member c, selected without indexing the arrays by c
-#pragma unroll
-            for (int t = 0; t <= kMaxK; ++t)
-                if (t == c) {
-                    node = u[t];
-                    ri = r[t];
-                    sci = stride[t];
-                }
+            int node, ri, sci;
+            subset_member(Sb, c, node, ri, sci);
             const int q = cells / ri;
             const double *L_ijk = lut + (int64_t)lut_row[cells] * (N + 1);
             const double *L_ik = lut + (int64_t)lut_row[q] * (N + 1);
             double acc = 0.0;
             for (int k = lane; k < q; k += 64) {
-                // parent configuration k: digits over the parents, the last one fastest
-                int rest = k, J = 0;
-#pragma unroll
-                for (int t = kMaxK; t >= 0; --t) {
-                    if (t < j && t != c) {
-                        J += (rest % r[t]) * stride[t];
-                        rest /= r[t];
-                    }
-                }
+                const int J = family_base(Sb, c, k);
                 uint32_t nik = 0;
                 double part = 0.0;
                 for (int x = 0; x < ri; ++x) {
@@ -323,7 +366,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_build_joint(
                 double sc = acc + (double)(j - 1) * log_gamma;
 #pragma unroll
                 for (int t = 0; t <= kMaxK; ++t)
-                    if (t < j && t != c) sc += prior[(int64_t)node * n + u[t]];
+                    if (t < j && t != c) sc += prior[(int64_t)node * n + Sb.u[t]];
                 const uint64_t slot = (pm & ((1ull << node) - 1ull)) | (node >= 63 ? 0ull : ((pm >> (node + 1)) << node));
                 const int64_t e = (int64_t)node * S_pad + rank_ascending(slot, n - 1, K, nsets);
                 masks[e] = pm;
@@ -535,6 +578,37 @@ __global__ __launch_bounds__(WAVES * 64) void k_counts(
         const int cells = M.q * r;
         wave_count(data, N, N_pad, node, M, cells, hist, lane);
         for (int c = lane; c < cells; c += 64) out[qoff[qi] + c] = hist[c];
+        wave_lds_sync();
+    }
+}
+
+// The same queries answered by the joint-histogram path of the default build
+// (k_build_joint): the histogram of U = parents + node, read out as the
+// family's cells (parent configuration k, the lowest id most significant, then
+// the child state).
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_counts_joint(
+    const uint8_t *__restrict__ data, int64_t N, int64_t N_pad, const int32_t *__restrict__ ar,
+    int Q, const int32_t *__restrict__ qnode, const uint64_t *__restrict__ qmask,
+    const int64_t *__restrict__ qoff, int cells_cap, uint32_t *__restrict__ out)
+{
+    extern __shared__ uint32_t lds_hist[];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    uint32_t *hist = lds_hist + wave * cells_cap;
+    for (int qi = blockIdx.x * WAVES + wave; qi < Q; qi += gridDim.x * WAVES) {
+        const int child = qnode[qi];
+        const uint64_t U = qmask[qi] | (1ull << child);
+        const Subset Sb = decode_subset(U, ar);
+        joint_histogram(data, N, N_pad, Sb, hist, lane);
+        const int c = __popcll(U & ((1ull << child) - 1ull));       // the child's place among U's members
+        int node, ri, sci;
+        subset_member(Sb, c, node, ri, sci);
+        const int q = Sb.cells / ri;
+        for (int k = lane; k < q; k += 64) {
+            const int J = family_base(Sb, c, k);
+            for (int x = 0; x < ri; ++x) out[qoff[qi] + (int64_t)k * ri + x] = hist[J + x * sci];
+        }
         wave_lds_sync();
     }
 }
@@ -825,7 +899,8 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
         }
     }
     int cap = cells_cap_for(max_cells);
-    if (d_lut && o.count_mode == 0) {            // one joint histogram per node subset
+    t->count_mode = (d_lut && o.count_mode == 0) ? 0 : 1;
+    if (t->count_mode == 0) {                    // one joint histogram per node subset
         if (waves_for_cells(cap) == 4) { CK(launch_build_joint<4>(t, st, cap, d_lut_row, d_lut)); }
         else { CK(launch_build_joint<1>(t, st, cap, d_lut_row, d_lut)); }
     } else {                                     // one histogram per family
@@ -937,12 +1012,20 @@ extern "C" bnos_status bnos_counts(bnos_table h, int32_t Q, const int32_t *nodes
     CK(hipMemcpy(d_off, off.data(), sizeof(int64_t) * Q, hipMemcpyHostToDevice));
     int cap_cells = cells_cap_for(maxc);
     int blocks = (int)std::min<int64_t>((Q + 3) / 4, 1 << 16);
-    if (waves_for_cells(cap_cells) == 4) {
-        hipLaunchKernelGGL(k_counts<4>, dim3(blocks), dim3(256), 4 * cap_cells * sizeof(uint32_t), 0, t->d_data,
-                           t->N, t->N_pad, t->d_ar, Q, d_nodes, d_masks, d_off, cap_cells, d_out);
+    // the counting code of the table's own build: joint histograms (count_mode 0) or per family
+    const bool four = waves_for_cells(cap_cells) == 4;
+    const dim3 grid((unsigned)(four ? blocks : blocks * 4)), block(four ? 256 : 64);
+    const size_t lds = (four ? 4 : 1) * cap_cells * sizeof(uint32_t);
+    if (t->count_mode == 0) {
+        if (four) hipLaunchKernelGGL(k_counts_joint<4>, grid, block, lds, 0, t->d_data, t->N, t->N_pad, t->d_ar, Q,
+                                     d_nodes, d_masks, d_off, cap_cells, d_out);
+        else hipLaunchKernelGGL(k_counts_joint<1>, grid, block, lds, 0, t->d_data, t->N, t->N_pad, t->d_ar, Q,
+                                d_nodes, d_masks, d_off, cap_cells, d_out);
     } else {
-        hipLaunchKernelGGL(k_counts<1>, dim3(blocks * 4), dim3(64), cap_cells * sizeof(uint32_t), 0, t->d_data,
-                           t->N, t->N_pad, t->d_ar, Q, d_nodes, d_masks, d_off, cap_cells, d_out);
+        if (four) hipLaunchKernelGGL(k_counts<4>, grid, block, lds, 0, t->d_data, t->N, t->N_pad, t->d_ar, Q,
+                                     d_nodes, d_masks, d_off, cap_cells, d_out);
+        else hipLaunchKernelGGL(k_counts<1>, grid, block, lds, 0, t->d_data, t->N, t->N_pad, t->d_ar, Q, d_nodes,
+                                d_masks, d_off, cap_cells, d_out);
     }
     CK(hipGetLastError());
     CK(hipMemcpy(counts, d_out, sizeof(uint32_t) * tot, hipMemcpyDeviceToHost));

@@ -523,8 +523,10 @@ bnos_status validate_cfg(const bnos_chain_cfg *cfg)
 
 }  // namespace
 
-extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, const bnos_chain_cfg *cfg,
-                                             bnos_chain_state *states, void *stream)
+// The sweep of bnos_run_chains_multi; with replay_ms, the device time of the
+// iterations (graph replays and the remainder, not the set-up) is returned there.
+static bnos_status run_chains_impl(const bnos_table *hs, int32_t T, const bnos_chain_cfg *cfg,
+                                   bnos_chain_state *states, void *stream, float *replay_ms)
 {
     if (!hs || !states) { set_error("NULL argument"); return BNOS_E_INVALID; }
     if (T < 1 || T > 4096) { set_error("T outside [1, 4096]"); return BNOS_E_RANGE; }
@@ -655,8 +657,8 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
         V.masks = t->d_masks;
         V.scores = t->d_scores;
         V.S_pad = t->S_pad;
-        V.chunks = t->chunks_for(C);
-        V.chunk_entries = t->chunk_entries_for(C);
+        V.chunks = t->chain_chunks_for(C);
+        V.chunk_entries = t->chain_chunk_entries_for(C);
         V.n = n;
         V.B = C;
         V.orders = H.prop;
@@ -680,10 +682,13 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
     auto cleanup = [&]() {
         if (exec) hipGraphExecDestroy(exec);
         if (graph) hipGraphDestroy(graph);
         if (cs) hipStreamDestroy(cs);
+        if (ev0) hipEventDestroy(ev0);
+        if (ev1) hipEventDestroy(ev1);
         hipFree(ws);
     };
 #define CK(call) if ((e = (call)) != hipSuccess) { set_error(std::string(#call) + ": " + hipGetErrorString(e)); cleanup(); return BNOS_E_DEVICE; }
@@ -694,7 +699,10 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
     CK(hipMemcpy(d_blk, blk_base.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice));
     CK(hipMemcpy(d_chain, chain_base.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice));
     CK(hipMemcpy(d_node, node_base.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice));
-    const int bt = pick_bt(tabs[0], C);
+    // orders per scoring block: the chain-sweep shape of C's bucket if set (one per launch,
+    // from the first table), else the scoring rule for a batch of C orders
+    const int tb_bt = tabs[0]->chain_bt[TableT::bucket(C)];
+    const int bt = (tb_bt > 0 && tb_bt <= C) ? tb_bt : pick_bt(tabs[0], C);
     const unsigned groups = (unsigned)((max_groups_c + bt - 1) / bt);
     const unsigned total_chains = (unsigned)chain_base[T];
     hipLaunchKernelGGL(k_chain_init, dim3(total_chains), dim3(64), 0, us, d_cv, d_chain, T);
@@ -727,17 +735,153 @@ extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, co
         }
         CK(hipStreamEndCapture(cs, &graph));
         CK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-        for (int64_t g = 0; g < graphs; ++g) CK(hipGraphLaunch(exec, us));
     }
+    if (replay_ms) {
+        CK(hipEventCreate(&ev0));
+        CK(hipEventCreate(&ev1));
+        CK(hipEventRecord(ev0, us));
+    }
+    for (int64_t g = 0; g < graphs; ++g) CK(hipGraphLaunch(exec, us));
     for (int64_t q = 0; q < rest; ++q) CK(one_step(us));
+    if (replay_ms) CK(hipEventRecord(ev1, us));
     CK(hipStreamSynchronize(us));
+    if (replay_ms) CK(hipEventElapsedTime(replay_ms, ev0, ev1));
 #undef CK
     cleanup();
     return BNOS_OK;
 }
 
+extern "C" bnos_status bnos_run_chains_multi(const bnos_table *hs, int32_t T, const bnos_chain_cfg *cfg,
+                                             bnos_chain_state *states, void *stream)
+{
+    return run_chains_impl(hs, T, cfg, states, stream, nullptr);
+}
+
 extern "C" bnos_status bnos_run_chains(bnos_table h, const bnos_chain_cfg *cfg, bnos_chain_state *st,
                                        void *stream)
 {
-    return bnos_run_chains_multi(&h, 1, cfg, st, stream);
+    return run_chains_impl(&h, 1, cfg, st, stream, nullptr);
+}
+
+static bnos_status check_chain_shape(const TableT *t, int32_t chunk_steps, int32_t orders_per_block)
+{
+    if (chunk_steps != 0 && (chunk_steps < 1 || chunk_steps > t->pad_steps || (chunk_steps & (chunk_steps - 1)) != 0)) {
+        set_error("chunk_steps must be 0 or a power of two dividing the row padding");
+        return BNOS_E_RANGE;
+    }
+    if (orders_per_block != 0 && orders_per_block != 1 && orders_per_block != 2 && orders_per_block != 4 &&
+        orders_per_block != 8) {
+        set_error("orders_per_block must be 0, 1, 2, 4 or 8");
+        return BNOS_E_RANGE;
+    }
+    return BNOS_OK;
+}
+
+extern "C" bnos_status bnos_chains_set_launch(bnos_table h, int32_t chains, int32_t chunk_steps,
+                                              int32_t orders_per_block)
+{
+    TableT *t = reinterpret_cast<TableT *>(h);
+    if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
+    if (chains < 1 || chains > 65536) { set_error("chains outside [1, 65536]"); return BNOS_E_RANGE; }
+    bnos_status s = check_chain_shape(t, chunk_steps, orders_per_block);
+    if (s != BNOS_OK) return s;
+    BNOS_HIP(hipSetDevice(t->device));
+    BNOS_HIP(hipDeviceSynchronize());        // sweeps in flight keep their shapes and workspace
+    const int bk = TableT::bucket(chains);
+    t->chain_cs[bk] = chunk_steps;
+    t->chain_bt[bk] = orders_per_block;
+    return ensure_workspace(t, chains);
+}
+
+extern "C" bnos_status bnos_chains_autotune(bnos_table h, const bnos_chain_cfg *cfg, const bnos_chain_state *state,
+                                            int32_t reps, void *stream, int32_t *chunk_steps,
+                                            int32_t *orders_per_block, double *ms_per_iteration)
+{
+    TableT *t = reinterpret_cast<TableT *>(h);
+    if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
+    bnos_status s = validate_cfg(cfg);
+    if (s != BNOS_OK) return s;
+    if (cfg->iterations < 1 || cfg->iterations > (1 << 20)) { set_error("iterations outside [1, 2^20]"); return BNOS_E_RANGE; }
+    if (reps < 1 || reps > 100) { set_error("reps outside [1, 100]"); return BNOS_E_RANGE; }
+    if (t->n < 2) { set_error("chains need n >= 2 (a swap needs two positions)"); return BNOS_E_RANGE; }
+    const bool resume = cfg->first_iteration > 0;
+    if (resume && (!state || !state->orders || !state->scores || !state->best_graphs || !state->best_scores ||
+                   !state->accepted)) {
+        set_error("a resumed tuning run needs the state to start from");
+        return BNOS_E_INVALID;
+    }
+    const int C = cfg->chains, n = t->n;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    BNOS_HIP(hipSetDevice(t->device));
+    BNOS_HIP(hipDeviceSynchronize());
+    // scratch state: every candidate starts from the same chains and the caller's state is untouched
+    const size_t cn = (size_t)C * n;
+    char *scr = nullptr;
+    const size_t bytes = cn * 4 + cn * 8 + (size_t)C * 8 * 3 + 1024;
+    hipError_t e = hipMalloc((void **)&scr, bytes);
+    if (e != hipSuccess) {
+        set_error(std::string("hipMalloc tuning state: ") + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? BNOS_E_NOMEM : BNOS_E_DEVICE;
+    }
+    bnos_chain_state sc;
+    std::memset(&sc, 0, sizeof(sc));
+    char *p = scr;
+    sc.best_graphs = reinterpret_cast<uint64_t *>(p);  p += cn * 8;
+    sc.scores = reinterpret_cast<double *>(p);          p += (size_t)C * 8;
+    sc.best_scores = reinterpret_cast<double *>(p);     p += (size_t)C * 8;
+    sc.accepted = reinterpret_cast<int64_t *>(p);       p += (size_t)C * 8;
+    sc.orders = reinterpret_cast<int32_t *>(p);
+    bnos_chain_cfg c2 = *cfg;
+    c2.topk = 0;
+    c2.trace_edges = 0;
+    c2.edges = nullptr;
+    const int bk = TableT::bucket(C);
+    const int old_cs = t->chain_cs[bk], old_bt = t->chain_bt[bk];
+    double best_ms = 1e300;
+    int best_cs = 0, best_bt = 0;
+    for (int cs = 1; cs <= t->pad_steps && s == BNOS_OK; cs <<= 1) {
+        for (int bt = 1; bt <= 8 && bt <= C && s == BNOS_OK; bt <<= 1) {
+            t->chain_cs[bk] = cs;
+            t->chain_bt[bk] = bt;
+            if ((s = ensure_workspace(t, C)) != BNOS_OK) break;
+            double tot = 0.0;
+            for (int r = 0; r <= reps && s == BNOS_OK; ++r) {
+                if (resume) {
+                    hipMemcpyAsync(sc.orders, state->orders, cn * 4, hipMemcpyDeviceToDevice, st);
+                    hipMemcpyAsync(sc.scores, state->scores, (size_t)C * 8, hipMemcpyDeviceToDevice, st);
+                    hipMemcpyAsync(sc.best_graphs, state->best_graphs, cn * 8, hipMemcpyDeviceToDevice, st);
+                    hipMemcpyAsync(sc.best_scores, state->best_scores, (size_t)C * 8, hipMemcpyDeviceToDevice, st);
+                    if ((e = hipMemcpyAsync(sc.accepted, state->accepted, (size_t)C * 8, hipMemcpyDeviceToDevice,
+                                            st)) != hipSuccess) {
+                        set_error(std::string("tuning state copy: ") + hipGetErrorString(e));
+                        s = BNOS_E_DEVICE;
+                        break;
+                    }
+                }
+                float ms = 0.f;
+                bnos_table hh = h;
+                s = run_chains_impl(&hh, 1, &c2, &sc, stream, &ms);
+                if (r > 0) tot += ms;                 // the first run is the warm-up
+            }
+            const double per = tot / ((double)reps * (double)cfg->iterations);
+            if (s == BNOS_OK && per < best_ms) {
+                best_ms = per;
+                best_cs = cs;
+                best_bt = bt;
+            }
+        }
+    }
+    hipFree(scr);
+    if (s != BNOS_OK) {
+        t->chain_cs[bk] = old_cs;
+        t->chain_bt[bk] = old_bt;
+        return s;
+    }
+    t->chain_cs[bk] = best_cs;
+    t->chain_bt[bk] = best_bt;
+    if ((s = ensure_workspace(t, C)) != BNOS_OK) return s;
+    if (chunk_steps) *chunk_steps = best_cs;
+    if (orders_per_block) *orders_per_block = best_bt;
+    if (ms_per_iteration) *ms_per_iteration = best_ms;
+    return BNOS_OK;
 }

@@ -21,10 +21,12 @@ struct MlpT {
     float *d_master = nullptr;   // [kNParam]
     float *d_m = nullptr;        // Adam first moment
     float *d_v = nullptr;        // Adam second moment
-    uint16_t *d_W1b = nullptr;   // [128][16]
+    uint16_t *d_W1b = nullptr;   // [128][8]
     uint16_t *d_W2b = nullptr;   // [128][128]
+    uint16_t *d_W2tb = nullptr;  // [128][128], transposed
     float *d_w3r = nullptr;      // [128]
     float *d_norm = nullptr;     // [16]: mu, 1/sd
+    double *d_normpart = nullptr;   // [kNormBlocks][16]: per-block feature sums
     float h_mu[kF], h_sd[kF];
     int64_t adam_t = 0;
 };
@@ -45,6 +47,7 @@ MlpView mlp_view(const void *h)
     MlpView P;
     P.W1b = m->d_W1b;
     P.W2b = m->d_W2b;
+    P.W2tb = m->d_W2tb;
     P.w3r = m->d_w3r;
     P.b1 = m->d_master + kOffB1;
     P.b2 = m->d_master + kOffB2;
@@ -57,19 +60,20 @@ bool mlp_handle_live(const void *h) { return mlp_live(reinterpret_cast<const Mlp
 
 // ------------------------------------------------------------------ kernels
 
-// BF16 copies of the weights from the FP32 master (W1 padded to K = 16).
+// BF16 copies of the weights from the FP32 master (W2 also transposed).
 __global__ void k_mlp_refresh(const float *__restrict__ master, uint16_t *__restrict__ W1b,
-                              uint16_t *__restrict__ W2b, float *__restrict__ w3r)
+                              uint16_t *__restrict__ W2b, uint16_t *__restrict__ W2tb, float *__restrict__ w3r)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < kH * kFP) {
-        const int u = g / kFP, k = g % kFP;
-        W1b[g] = (k < kF) ? f2bf(master[kOffW1 + u * kF + k]) : (uint16_t)0;
-    } else if (g < kH * kFP + kH * kH) {
-        const int e = g - kH * kFP;
-        W2b[e] = f2bf(master[kOffW2 + e]);
-    } else if (g < kH * kFP + kH * kH + kH) {
-        const int e = g - kH * kFP - kH * kH;
+    if (g < kH * kF) {
+        W1b[g] = f2bf(master[kOffW1 + g]);
+    } else if (g < kH * kF + kH * kH) {
+        const int e = g - kH * kF;
+        const uint16_t b = f2bf(master[kOffW2 + e]);
+        W2b[e] = b;
+        W2tb[(e % kH) * kH + e / kH] = b;
+    } else if (g < kH * kF + kH * kH + kH) {
+        const int e = g - kH * kF - kH * kH;
         w3r[e] = bf2f(f2bf(master[kOffW3 + e]));
     }
 }
@@ -85,17 +89,22 @@ __global__ __launch_bounds__(1024) void k_mlp_forward(MlpView P, const float *__
 }
 
 // Per-feature mean and population standard deviation over `rows` rows (FP64,
-// fixed reduction tree); sd below 1e-6 is replaced by 1.
-__global__ __launch_bounds__(1024) void k_feat_norm(const float *__restrict__ feats, int64_t rows,
-                                                    float *__restrict__ norm)
+// fixed reduction trees, so the result does not depend on scheduling); sd
+// below 1e-6 is replaced by 1.  Block b of kNormBlocks sums rows b, b + G, ...
+// (G = grid threads) per thread, then a tree over its threads; the last
+// kernel adds the block sums in block order.
+constexpr int kNormBlocks = 256;
+constexpr int kNormThreads = 256;
+__global__ __launch_bounds__(kNormThreads) void k_feat_norm_part(const float *__restrict__ feats, int64_t rows,
+                                                                  double *__restrict__ part)
 {
-    // one pass: every thread accumulates all 8 features of its rows (two 16-byte loads per row)
-    __shared__ double s1[kF][1024], s2[kF][1024];
+    __shared__ double s1[kF][kNormThreads], s2[kF][kNormThreads];
     double a[kF], b[kF];
 #pragma unroll
     for (int k = 0; k < kF; ++k) a[k] = b[k] = 0.0;
     const float4 *f4 = reinterpret_cast<const float4 *>(feats);
-    for (int64_t r = threadIdx.x; r < rows; r += 1024) {
+    const int64_t stride = (int64_t)gridDim.x * kNormThreads;
+    for (int64_t r = (int64_t)blockIdx.x * kNormThreads + threadIdx.x; r < rows; r += stride) {
         const float4 lo = f4[2 * r], hi = f4[2 * r + 1];
         const float v[kF] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
 #pragma unroll
@@ -110,7 +119,7 @@ __global__ __launch_bounds__(1024) void k_feat_norm(const float *__restrict__ fe
         s2[k][threadIdx.x] = b[k];
     }
     __syncthreads();
-    for (int w = 512; w >= 1; w >>= 1) {
+    for (int w = kNormThreads / 2; w >= 1; w >>= 1) {
         if (threadIdx.x < w)
 #pragma unroll
             for (int k = 0; k < kF; ++k) {
@@ -120,21 +129,34 @@ __global__ __launch_bounds__(1024) void k_feat_norm(const float *__restrict__ fe
         __syncthreads();
     }
     if (threadIdx.x < kF) {
-        const int k = threadIdx.x;
-        const double mu = rows ? s1[k][0] / (double)rows : 0.0;
-        double var = rows ? s2[k][0] / (double)rows - mu * mu : 1.0;
-        double sd = var > 0 ? sqrt(var) : 0.0;
-        if (!(sd > 1e-6)) sd = 1.0;
-        norm[k] = (float)mu;
-        norm[kF + k] = (float)(1.0 / sd);
+        part[(int64_t)blockIdx.x * 2 * kF + threadIdx.x] = s1[threadIdx.x][0];
+        part[(int64_t)blockIdx.x * 2 * kF + kF + threadIdx.x] = s2[threadIdx.x][0];
     }
+}
+
+__global__ void k_feat_norm_final(const double *__restrict__ part, int blocks, int64_t rows,
+                                  float *__restrict__ norm)
+{
+    const int k = threadIdx.x;
+    if (k >= kF) return;
+    double t1 = 0.0, t2 = 0.0;
+    for (int b = 0; b < blocks; ++b) {
+        t1 += part[(int64_t)b * 2 * kF + k];
+        t2 += part[(int64_t)b * 2 * kF + kF + k];
+    }
+    const double mu = rows ? t1 / (double)rows : 0.0;
+    const double var = rows ? t2 / (double)rows - mu * mu : 1.0;
+    double sd = var > 0 ? sqrt(var) : 0.0;
+    if (!(sd > 1e-6)) sd = 1.0;
+    norm[k] = (float)mu;
+    norm[kF + k] = (float)(1.0 / sd);
 }
 
 struct GradLds {
     MlpLds f;
     float zraw[kRows * kF];
-    float h2[kRows][kH];        // relu(layer 2); later reused for dpre1
-    uint16_t d2[kRows][kH];     // dL/dpre2, bf16 operand
+    float h2[kRows][kH];            // relu(layer 2); later reused for dpre1
+    uint16_t d2[2][kRows][kHP];     // dL/dpre2 as hi / lo bf16 operands
     float dl[kRows];
     float gw3[kH], gb2[kH], gb1[kH];
     double loss;
@@ -151,7 +173,9 @@ __device__ __forceinline__ int64_t visit(int64_t j, int64_t count, int64_t strid
 // Block per chunk of `spb` samples: forward, gradient of -ln q(pair) w.r.t.
 // the logits, backward through both layers with MFMA GEMMs (the weight
 // gradients accumulate in matrix-core accumulators across the chunk), then
-// one partial gradient (+ loss sum at index kNParam) per block.
+// one partial gradient (+ loss sum at index kNParam) per block.  Every
+// activation operand is a hi/lo BF16 pair (see mlp_device.h); products of two
+// activations take hi*hi + hi*lo + lo*hi.
 constexpr int kGradWaves = 8;
 constexpr int kW2TilesPerWave = 64 / kGradWaves;
 
@@ -164,7 +188,7 @@ __global__ __launch_bounds__(kGradWaves * 64) void k_mlp_grad(MlpView P, const f
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int li = lane & 15, lk = 4 * (lane >> 4);
+    const int li = lane & 15, g = lane >> 4;
     v4f accW2[kW2TilesPerWave];     // gW2 tiles (ut, kt) = (wave*T+q) / 8, % 8
     v4f accW1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -211,11 +235,11 @@ __global__ __launch_bounds__(kGradWaves * 64) void k_mlp_grad(MlpView P, const f
             if (lane == 0) G.loss += -log(q);
         }
         __syncthreads();
-        // dL/dpre2 = relu'(pre2) * dl * w3; bias / w3 / b3 gradients (rows in order)
+        // dL/dpre2 = relu'(pre2) * dl * w3 (hi/lo operands); bias / w3 / b3 gradients (rows in order)
         for (int e = tid; e < kRows * kH; e += blockDim.x) {
             const int r = e / kH, u = e % kH;
             const float d = G.h2[r][u] > 0.f ? G.dl[r] * P.w3r[u] : 0.f;
-            G.d2[r][u] = f2bf(d);
+            split_bf(d, G.d2[0][r][u], G.d2[1][r][u]);
         }
         if (tid < kH) {
             float s3 = 0.f, s2 = 0.f;
@@ -233,41 +257,37 @@ __global__ __launch_bounds__(kGradWaves * 64) void k_mlp_grad(MlpView P, const f
             G.gb3 += s;
         }
         __syncthreads();
-        // gW2[u][k] += sum_r d2[r][u] h1[r][k]   (A = d2^T, B = h1, K = 64 rows)
+        // gW2[u][k] += sum_r d2[r][u] h1[r][k]: A[u][r] = d2, B[r][k] = h1, K = 64 rows in two
+        // steps of 32, for the products (d2 hi, h1 hi), (d2 hi, h1 lo), (d2 lo, h1 hi)
 #pragma unroll
         for (int q = 0; q < kW2TilesPerWave; ++q) {
             const int tile = wave * kW2TilesPerWave + q, ut = tile >> 3, kt = tile & 7;
 #pragma unroll
-            for (int ks = 0; ks < kRows / 16; ++ks) {
-                v4s a, b;
+            for (int pr = 0; pr < 3; ++pr) {
+                const int pd = pr == 2 ? 1 : 0, ph = pr == 1 ? 1 : 0;
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    a[jj] = (short)G.d2[ks * 16 + lk + jj][ut * 16 + li];
-                    b[jj] = (short)G.f.h1[ks * 16 + lk + jj][kt * 16 + li];
+                for (int ks = 0; ks < 2; ++ks) {
+                    const int r0 = ks * 32 + 8 * g;
+                    accW2[q] = mfma32(ld8_strided(&G.d2[pd][r0][ut * 16 + li], kHP),
+                                      ld8_strided(&G.f.h1[ph][r0][kt * 16 + li], kHP), accW2[q]);
                 }
-                accW2[q] = mfma16(a, b, accW2[q]);
             }
         }
         __syncthreads();
-        // dh1[r][k] = sum_u d2[r][u] W2[u][k]; dpre1 = relu'(pre1) dh1 -> G.h2 (as float)
+        // dh1[r][k] = sum_u d2[r][u] W2[u][k] (K = 128, hi then lo); dpre1 = relu'(pre1) dh1 -> G.h2
         for (int tile = wave; tile < 32; tile += kGradWaves) {
             const int rt = tile >> 3, kt = tile & 7;
             v4f d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int ks = 0; ks < kH / 16; ++ks) {
-                v4s a, b;
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    a[jj] = (short)G.d2[rt * 16 + li][ks * 16 + lk + jj];
-                    b[jj] = (short)P.W2b[(ks * 16 + lk + jj) * kH + kt * 16 + li];
-                }
-                d = mfma16(a, b, d);
+            for (int s = 0; s < 8; ++s) {
+                const int pd = s >> 2, ub = (s & 3) * 32 + 8 * g;
+                d = mfma32(ld8(&G.d2[pd][rt * 16 + li][ub]), ld8(P.W2tb + (kt * 16 + li) * kH + ub), d);
             }
             const int k = kt * 16 + li;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = rt * 16 + lk + r;
-                G.h2[row][k] = (row < n && G.f.h1[row][k] != 0) ? d[r] : 0.f;
+                const int row = rt * 16 + 4 * g + r;
+                G.h2[row][k] = (row < n && G.f.h1[0][row][k] != 0) ? d[r] : 0.f;
             }
         }
         __syncthreads();
@@ -276,18 +296,23 @@ __global__ __launch_bounds__(kGradWaves * 64) void k_mlp_grad(MlpView P, const f
             for (int r = 0; r < n; ++r) s1 += G.h2[r][tid];
             G.gb1[tid] += s1;
         }
-        // gW1[u][k] += sum_r dpre1[r][u] z[r][k]   (8 tiles of 16 hidden units, K = 64 rows)
+        // gW1[u][k] += sum_r dpre1[r][u] z[r][k]: A[u][r] = dpre1 (hi, then lo), B[r][c] = the
+        // z row (columns 0..7 hi, 8..15 lo); columns c and c + 8 are added at the end, so the
+        // tile sums hi*hi + hi*lo + lo*hi + lo*lo (8 tiles of 16 hidden units)
         if (wave < 8) {
             const int ut = wave;
 #pragma unroll
-            for (int ks = 0; ks < kRows / 16; ++ks) {
-                v4s a, b;
+            for (int s = 0; s < 4; ++s) {
+                const int part = s >> 1, r0 = (s & 1) * 32 + 8 * g;
+                v4u a;
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
-                    a[jj] = (short)f2bf(G.h2[ks * 16 + lk + jj][ut * 16 + li]);
-                    b[jj] = (short)G.f.z[ks * 16 + lk + jj][li];
+                    uint16_t h0, l0, h1v, l1;
+                    split_bf(G.h2[r0 + 2 * jj][ut * 16 + li], h0, l0);
+                    split_bf(G.h2[r0 + 2 * jj + 1][ut * 16 + li], h1v, l1);
+                    a[jj] = part ? ((uint32_t)l0 | ((uint32_t)l1 << 16)) : ((uint32_t)h0 | ((uint32_t)h1v << 16));
                 }
-                accW1 = mfma16(a, b, accW1);
+                accW1 = mfma32(a, ld8_strided(&G.f.z[r0][li], 16), accW1);
             }
         }
         __syncthreads();
@@ -298,11 +323,16 @@ __global__ __launch_bounds__(kGradWaves * 64) void k_mlp_grad(MlpView P, const f
     for (int q = 0; q < kW2TilesPerWave; ++q) {
         const int tile = wave * kW2TilesPerWave + q, ut = tile >> 3, kt = tile & 7;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) out[kOffW2 + (ut * 16 + lk + r) * kH + kt * 16 + li] = accW2[q][r];
+        for (int r = 0; r < 4; ++r) out[kOffW2 + (ut * 16 + 4 * g + r) * kH + kt * 16 + li] = accW2[q][r];
     }
-    if (wave < 8 && li < kF) {
+    if (wave < 8) {
+        // column li + 8 holds the products with z_lo of column li
+        float hi8[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) out[kOffW1 + (wave * 16 + lk + r) * kF + li] = accW1[r];
+        for (int r = 0; r < 4; ++r) hi8[r] = __shfl(accW1[r], (lane & ~15) | ((li + 8) & 15), 64);
+        if (li < kF)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[kOffW1 + (wave * 16 + 4 * g + r) * kF + li] = accW1[r] + hi8[r];
     }
     if (tid < kH) {
         out[kOffB1 + tid] = G.gb1[tid];
@@ -347,9 +377,9 @@ __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__re
 
 static void refresh(MlpT *m, hipStream_t st)
 {
-    const int total = kH * kFP + kH * kH + kH;
+    const int total = kH * kF + kH * kH + kH;
     hipLaunchKernelGGL(k_mlp_refresh, dim3((total + 255) / 256), dim3(256), 0, st, m->d_master, m->d_W1b,
-                       m->d_W2b, m->d_w3r);
+                       m->d_W2b, m->d_W2tb, m->d_w3r);
 }
 
 static void free_mlp(MlpT *m)
@@ -359,8 +389,10 @@ static void free_mlp(MlpT *m)
     hipFree(m->d_v);
     hipFree(m->d_W1b);
     hipFree(m->d_W2b);
+    hipFree(m->d_W2tb);
     hipFree(m->d_w3r);
     hipFree(m->d_norm);
+    hipFree(m->d_normpart);
 }
 
 constexpr int kSamplesPerBlock = 8;
@@ -394,8 +426,10 @@ extern "C" bnos_status bnos_mlp_create(bnos_mlp *out)
     ALLOC(m->d_master, sizeof(float) * kNParam);
     ALLOC(m->d_m, sizeof(float) * kNParam);
     ALLOC(m->d_v, sizeof(float) * kNParam);
-    ALLOC(m->d_W1b, sizeof(uint16_t) * kH * kFP);
+    ALLOC(m->d_W1b, sizeof(uint16_t) * kH * kF);
     ALLOC(m->d_W2b, sizeof(uint16_t) * kH * kH);
+    ALLOC(m->d_W2tb, sizeof(uint16_t) * kH * kH);
+    ALLOC(m->d_normpart, sizeof(double) * kNormBlocks * 2 * kF);
     ALLOC(m->d_w3r, sizeof(float) * kH);
     ALLOC(m->d_norm, sizeof(float) * 2 * kF);
 #undef ALLOC
@@ -497,7 +531,12 @@ extern "C" bnos_status bnos_mlp_fit_norm(bnos_mlp h, const float *feats, int64_t
     if (!feats || rows < 1) { set_error("need at least one feature row"); return BNOS_E_INVALID; }
     if (reinterpret_cast<uintptr_t>(feats) % 16) { set_error("feats must be 16-byte aligned"); return BNOS_E_INVALID; }
     BNOS_HIP(hipSetDevice(m->device));
-    hipLaunchKernelGGL(k_feat_norm, dim3(1), dim3(1024), 0, reinterpret_cast<hipStream_t>(stream), feats, rows, m->d_norm);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int64_t want = (rows + kNormThreads - 1) / kNormThreads;
+    const int blocks = (int)(want < kNormBlocks ? want : kNormBlocks);
+    hipLaunchKernelGGL(k_feat_norm_part, dim3(blocks), dim3(kNormThreads), 0, st, feats, rows, m->d_normpart);
+    BNOS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_feat_norm_final, dim3(1), dim3(64), 0, st, m->d_normpart, blocks, rows, m->d_norm);
     BNOS_HIP(hipGetLastError());
     return BNOS_OK;
 }

@@ -260,12 +260,12 @@ static void launch_bt(const ScoreArgs &A, int nblocks_x, hipStream_t st, hipEven
 
 // The streaming pass (k_score) with the table's block shape; timed when enabled.
 // The workspace must already hold A.B orders.
-bnos_status launch_stream(TableT *t, const ScoreArgs &A, hipStream_t st, int bt)
+bnos_status launch_stream(TableT *t, const ScoreArgs &A, hipStream_t st, int bt, bool allow_timing)
 {
     bnos_status s;
     if (bt <= 0) bt = pick_bt(t, A.B);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (t->timing && t->timing_seen++ % t->timing_every == 0) {
+    if (allow_timing && t->timing && t->timing_seen++ % t->timing_every == 0) {
         if ((s = next_events(t, e0, e1, (A.B + bt - 1) / bt)) != BNOS_OK) return s;
     }
     const int nbx = t->n * A.chunks;
@@ -279,17 +279,25 @@ bnos_status launch_stream(TableT *t, const ScoreArgs &A, hipStream_t st, int bt)
 
 // The gather pass (k_gather) over B orders; A.chunks becomes n (one partial
 // slot per top member plus the empty set).  Timed when enabled.
-static bnos_status launch_gather(TableT *t, ScoreArgs &A, hipStream_t st)
+bnos_status launch_gather(TableT *t, ScoreArgs &A, hipStream_t st, bool allow_timing)
 {
     bnos_status s;
     A.chunks = t->n;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (t->timing && t->timing_seen++ % t->timing_every == 0) {
+    if (allow_timing && t->timing && t->timing_seen++ % t->timing_every == 0) {
         if ((s = next_events(t, e0, e1, 0)) != BNOS_OK) return s;
     }
     dim3 grid((unsigned)(t->n * t->n), (unsigned)A.B);
     if (e0) hipExtLaunchKernelGGL(k_gather, grid, dim3(kScoreThreads), 0, st, e0, e1, 0, A, t->d_nsets, t->K);
     else hipLaunchKernelGGL(k_gather, grid, dim3(kScoreThreads), 0, st, A, t->d_nsets, t->K);
+    BNOS_HIP(hipGetLastError());
+    return BNOS_OK;
+}
+
+// The per-order merge of a scoring launch's partials.
+bnos_status launch_merge(const ScoreArgs &A, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_merge, dim3(A.B), dim3(kMergeWaves * 64), 0, st, A);
     BNOS_HIP(hipGetLastError());
     return BNOS_OK;
 }

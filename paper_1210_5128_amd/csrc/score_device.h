@@ -50,6 +50,41 @@ __device__ __forceinline__ void acc_push(Acc &a, float x, uint64_t mk)
     }
 }
 
+// Fold a lane's group of 4 consecutive row entries into its state, for a lane
+// that sees its entries in ascending mask order (the streaming pass: a row
+// lists the masks in ascending order and a lane visits its groups in row
+// order).  x[e] is the entry's score if consistent, else -inf; mk[e] its mask.
+// The log-sum-exp max is the top-1 score, so one comparison serves both: the
+// rare group that beats the lane's best rescales the sum and takes the new
+// argmax (the first entry holding the group's max, i.e. the smallest mask among
+// equal scores -- earlier groups hold smaller masks, so an equal score never
+// replaces the held best); every other group adds its exp terms and raises the
+// second best.  exp(x - best) = 2^(x log2 e - best log2 e), one fma and one
+// v_exp_f32 per entry; a group with no consistent entry changes nothing (it
+// adds exact zeros).  The caller keeps a.m == a.best.
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kScoreFloor = -1.0e38f;   // below every score; keeps best * log2e finite
+
+__device__ __forceinline__ void acc_fold4(Acc &a, const float (&x)[4], const uint64_t (&mk)[4])
+{
+    const float b = fmaxf(fmaxf(x[0], x[1]), fmaxf(x[2], x[3]));
+    a.sec = fmaxf(a.sec, b);
+    if (b > a.best) {
+        const int i = x[0] == b ? 0 : (x[1] == b ? 1 : (x[2] == b ? 2 : 3));
+        float o = -INFINITY;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) o = (e != i) ? fmaxf(o, x[e]) : o;
+        a.s *= __builtin_amdgcn_exp2f((a.best - b) * kLog2e);       // 0 when nothing was held (best = -inf)
+        a.sec = fmaxf(a.best, o);
+        a.best = b;
+        a.bm = i == 0 ? mk[0] : (i == 1 ? mk[1] : (i == 2 ? mk[2] : mk[3]));
+    }
+    const float t = fmaxf(a.best, kScoreFloor) * kLog2e;
+    const float e0 = __builtin_amdgcn_exp2f(fmaf(x[0], kLog2e, -t)), e1 = __builtin_amdgcn_exp2f(fmaf(x[1], kLog2e, -t));
+    const float e2 = __builtin_amdgcn_exp2f(fmaf(x[2], kLog2e, -t)), e3 = __builtin_amdgcn_exp2f(fmaf(x[3], kLog2e, -t));
+    a.s += (e0 + e1) + (e2 + e3);
+}
+
 // Combine two states (order-independent up to FP32 rounding; the callers fix the order).
 __device__ __forceinline__ void acc_merge(Acc &a, const Acc &b)
 {
@@ -232,10 +267,12 @@ struct TabView {
 // free slot, and no number in between has few enough members).  Past the last
 // mask the result holds a slot >= n - 1, which no predecessor set contains;
 // a result not above m (the end of the 64 bits, or K = 0) saturates to ~0.
+// (For a mask with at most K members, m + 1 has at most K members exactly when
+// m has fewer than K or holds slot 0, and in the second case m + lowest member
+// = m + 1; so the step adds 1 or m's lowest member.)
 __device__ __forceinline__ uint64_t next_mask(uint64_t m, int K)
 {
-    const uint64_t t = m + 1ull;
-    const uint64_t r = (__popcll(t) <= K) ? t : m + (m & (0ull - m));
+    const uint64_t r = m + ((__popcll(m) < K) ? 1ull : (m & (0ull - m)));
     return r <= m ? ~0ull : r;
 }
 
@@ -246,8 +283,7 @@ __device__ __forceinline__ uint64_t next_mask(uint64_t m, int K)
 // slot >= n - 1.
 __device__ __forceinline__ uint64_t next_mask_nosat(uint64_t m, int K)
 {
-    const uint64_t t = m + 1ull;
-    return (__popcll(t) <= K) ? t : m + (m & (0ull - m));
+    return m + ((__popcll(m) < K) ? 1ull : (m & (0ull - m)));
 }
 
 // Node-space mask (bit `node` clear) -> slot space, and back.
@@ -430,12 +466,20 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         for (int j = 0; j < BT; ++j) {
             if (!((need_c >> j) & 1u)) continue;             // uniform
             const uint64_t np = CM ? npred_s : npred[j];
+            float xs[4];
+            bool any = false;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                if ((mk[e] & np) == 0ull) acc_push(a[j], x[e], mk[e]);
+                const bool ok = (mk[e] & np) == 0ull;
+                xs[e] = ok ? x[e] : -INFINITY;
+                any |= ok;
             }
+            if (__ballot(any) == 0ull) continue;             // uniform: nothing consistent in the wavefront
+            acc_fold4(a[j], xs, mk);
         }
     }
+#pragma unroll
+    for (int j = 0; j < BT; ++j) a[j].m = a[j].best;
 
     {
         // a wavefront that folded nothing (no needed tile, or no consistent entry)
@@ -763,6 +807,8 @@ int pick_bt(const TableT *t, int B);
 bnos_status ensure_workspace(TableT *t, int B);
 ScoreArgs score_args(const TableT *t, const int32_t *orders, int B, double *lse, double *maxs,
                      uint64_t *best, double *node_lse, float *node_second);
-bnos_status launch_stream(TableT *t, const ScoreArgs &A, hipStream_t st, int bt);
+bnos_status launch_stream(TableT *t, const ScoreArgs &A, hipStream_t st, int bt, bool allow_timing = true);
+bnos_status launch_gather(TableT *t, ScoreArgs &A, hipStream_t st, bool allow_timing = true);
+bnos_status launch_merge(const ScoreArgs &A, hipStream_t st);
 
 }  // namespace bnos

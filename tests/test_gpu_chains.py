@@ -341,3 +341,65 @@ def test_chains_match_oracle_other_block_shapes(bnos, tiny8, bt):
     finally:
         t.set_launch(C)
     assert compare_chains(g, orc, w.K, 103, iters, 0) >= C - 1
+
+
+def test_mixed40_chains_match_oracle_golden(bnos):
+    # 4 oracle chains x 200 iterations on the 40-node table (stored by a script that
+    # calls only the oracle), replayed inside a launch of 256 chains -- the batched
+    # benchmark's shape -- on the same random-number streams
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "mixed40_chains.json")) as f:
+        gold = json.load(f)
+    w = datagen.WORKLOADS[gold["workload"]]
+    assert (w.n, w.K, w.N) == (gold["n"], gold["K"], gold["N"])
+    net, prior = datagen.make(w)
+    t = bnos.build_score_table(net.data, net.arities, w.K, prior=prior)
+    iters, seed = gold["iterations"], gold["seed"]
+    g = gpu_chains(t, 256, iters, seed=seed)
+    t.free()
+    for rec in gold["chains"]:
+        c = rec["chain"]
+        flags = g["accept_flags"][c, :iters].astype(bool)
+        mism = np.nonzero(flags != np.asarray(rec["acc"], dtype=bool))[0]
+        if len(mism):
+            # a decision may differ only where the oracle's |ln u - delta| is within TAU
+            k = int(mism[0])
+            assert rec["margin"][k] <= TAU, (c, k + 1, rec["margin"][k])
+            np.testing.assert_allclose(g["trace"][c, :k + 1], rec["trace"][:k + 1], rtol=REL)
+            continue
+        np.testing.assert_allclose(g["trace"][c, :iters + 1], rec["trace"], rtol=REL)
+        assert list(g["orders"][c]) == rec["order"], c
+        assert [int(x) for x in g["best_graphs"][c].view(np.uint64)] == rec["best_graph"], c
+        assert abs(g["best_scores"][c] - rec["best_score"]) <= REL * abs(rec["best_score"])
+        assert int(g["accepted"][c]) == rec["accepted"]
+
+
+def test_chain_sweep_autotune_picks_a_shape_and_keeps_the_chain(bnos, prior20):
+    # the tuner times real sweeps (from a copy of burned-in chains) and stores the
+    # fastest shape for this chain count; the tuned sweep takes the same decisions
+    w, t, orc = prior20
+    C, burn, iters = 32, 200, 150
+    st = t.new_chain_state(C, burn, trace_every=burn)
+    t.run_chains(st, burn, seed=5, trace_every=burn)
+    before = {k: st[k].clone() for k in ("orders", "scores", "best_graphs", "best_scores", "accepted")}
+    cs, bt, ms = t.chains_autotune(C, 32, seed=6, state=st, first_iteration=burn, reps=1)
+    torch.cuda.synchronize()
+    for k, v in before.items():               # the caller's state is not written
+        assert torch.equal(st[k], v), k
+    assert cs in (1, 2, 4, 8, 16) and bt in (1, 2, 4, 8) and ms > 0
+    runs = []
+    for shape in ("tuned", "default"):
+        if shape == "default":
+            t.chains_set_launch(C, 0, 0)
+        s2 = {k: v.clone() for k, v in before.items()}
+        s2["trace"] = torch.zeros((C, iters + 1), dtype=torch.float64, device="cuda")
+        s2["accept_flags"] = torch.zeros((C, iters), dtype=torch.uint8, device="cuda")
+        t.run_chains(s2, iters, seed=7, first_iteration=burn)
+        torch.cuda.synchronize()
+        runs.append({k: v.cpu().numpy() for k, v in s2.items()})
+    a, b = runs
+    assert np.array_equal(a["accept_flags"], b["accept_flags"])
+    assert np.array_equal(a["orders"], b["orders"])
+    assert np.array_equal(a["best_graphs"], b["best_graphs"])
+    np.testing.assert_allclose(a["trace"], b["trace"], rtol=REL)

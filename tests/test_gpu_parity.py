@@ -5,7 +5,9 @@ Bars: counts and argmax parent sets bit-exact; stored FP32 scores within
 oracle takes its argmax on its own scores rounded to FP32, the precision in
 which the library stores scores and decides the argmax.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -18,6 +20,7 @@ from paper_1210_5128_amd import datagen
 pytestmark = pytest.mark.gpu
 
 REL = 1e-5
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -122,6 +125,21 @@ def test_counts_bit_exact(bnos, wname, request):
     for i, m, g in zip(nodes, masks, got):
         want = oracle.counts(net.data, net.arities, i, m)
         assert np.array_equal(g, want), (i, m)
+
+
+def test_counts_per_family_path_bit_exact(bnos):
+    # a table built with one histogram per family answers count queries with that code
+    w = datagen.WORKLOADS["prior20"]
+    net, prior = datagen.make(w)
+    t = bnos.build_score_table(net.data, net.arities, w.K, prior=prior, count_mode=1)
+    rng = np.random.default_rng(4)
+    S = oracle.num_sets(w.n - 1, w.K)
+    nodes = [int(rng.integers(w.n)) for _ in range(2000)]
+    masks = [oracle.unrank(w.n, w.K, i, int(rng.integers(S))) for i in nodes]
+    got = t.counts(nodes, masks, net.arities)
+    t.free()
+    for i, m, g in zip(nodes, masks, got):
+        assert np.array_equal(g, oracle.counts(net.data, net.arities, i, m)), (i, m)
 
 
 # ------------------------------------------------------------------ table
@@ -273,23 +291,91 @@ def mixed60(bnos):
 
 
 def test_mixed60_counts_and_scores_sampled(bnos, mixed60):
+    # 10^4 random (node, parent set) entries of the 60-node table: the counts of
+    # the default build's joint-histogram path bit-exact, the stored scores
+    # within 2 ulp(FP32) of the oracle's FP64 local score
     w, net, prior, t = mixed60
     rng = np.random.default_rng(60)
     S = oracle.num_sets(w.n - 1, w.K)
     assert t.info()["entries_per_node"] == S == 489406
-    nodes = rng.integers(0, w.n, size=300)
-    idx = rng.integers(0, S, size=300)
-    exported = {}
-    for i in sorted(set(int(v) for v in nodes)):
-        exported[i] = t.export(i)
+    Q = 10000
+    nodes = rng.integers(0, w.n, size=Q)
+    idx = rng.integers(0, S, size=Q)
+    exported = {i: t.export(i) for i in range(w.n)}
     masks = [int(exported[int(i)][0][int(e)]) for i, e in zip(nodes, idx)]
     got = t.counts(nodes, masks, net.arities)
-    for i, m, g, e in zip(nodes, masks, got, idx):
-        want = oracle.counts(net.data, net.arities, int(i), m)
-        assert np.array_equal(g, want)
+    bad = [k for k in range(Q) if not np.array_equal(got[k], oracle.counts(net.data, net.arities, int(nodes[k]),
+                                                                          masks[k]))]
+    assert not bad, (len(bad), bad[:5])
+    for i, m, e in zip(nodes[:2000], masks[:2000], idx[:2000]):
         ls = oracle.local_score(net.data, net.arities, int(i), m, prior=prior)
-        s = float(exported[int(i)][1][int(e)])
-        assert abs(s - ls) <= 2 * ulp32(ls)
+        assert abs(float(exported[int(i)][1][int(e)]) - ls) <= 2 * ulp32(ls), (i, m)
+
+
+def mixed60_golden():
+    with open(os.path.join(GOLDEN, "mixed60_orders.json")) as f:
+        return json.load(f)
+
+
+def check_against_golden(got, rows, idx, net, w, prior):
+    """Full orders vs the oracle's enumeration on its own FP64 table (golden file):
+    per-order log-sum-exp and max within 1e-5 relative; every node's log-sum-exp
+    within 1e-5; best parent sets bit-exact except ulp-ties (the oracle's FP64
+    scores of the two picks within 2 ulp(FP32), counted); second best within
+    2 ulp(FP32)."""
+    ties = 0
+    for b, r in zip(idx, rows):
+        assert abs(got["lse"][b] - r["lse"]) <= REL * abs(r["lse"]), (b, got["lse"][b], r["lse"])
+        assert abs(got["max"][b] - r["max"]) <= REL * abs(r["max"]), (b, got["max"][b], r["max"])
+        np.testing.assert_allclose(got["node_lse"][b], r["node_lse"], rtol=REL, atol=1e-6)
+        for i in range(w.n):
+            gm, om = int(got["best"][b, i]), int(r["best"][i])
+            if gm != om:
+                a = oracle.local_score(net.data, net.arities, i, gm, prior=prior)
+                c = oracle.local_score(net.data, net.arities, i, om, prior=prior)
+                assert abs(a - c) <= 2 * ulp32(c), (b, i, gm, om, a, c)
+                ties += 1
+            sec, osec = float(got["node_second"][b, i]), r["node_second"][i]
+            if math.isinf(osec):
+                assert math.isinf(sec) and sec < 0, (b, i)
+            else:
+                assert abs(sec - osec) <= 2 * ulp32(osec), (b, i, sec, osec)
+    return ties
+
+
+@pytest.mark.parametrize("shape", ["bench_b1", "default_b1", "batched256"])
+def test_mixed60_full_orders_against_oracle(bnos, mixed60, shape):
+    # every node of 8 random 60-node orders against the oracle's enumeration, at
+    # one order per launch with the launch the benchmark times (16-step chunks,
+    # one order per block, computed masks, tile skipping) and with the build's
+    # default chunk, and inside one launch of 256 orders (16-step chunks, 4 orders
+    # per block, stored masks)
+    w, net, prior, t = mixed60
+    g = mixed60_golden()
+    assert (g["n"], g["K"], g["N"]) == (w.n, w.K, w.N)
+    rows = g["orders"]
+    orders = np.array([r["order"] for r in rows], dtype=np.int32)
+    try:
+        if shape == "batched256":
+            t.set_launch(256, chunk_steps=16, orders_per_block=4)
+            batch = datagen.random_orders(w.n, 256, seed=62)
+            idx = [0, 37, 74, 111, 148, 185, 222, 255]
+            batch[idx] = orders
+            got = dev_score(t, batch)
+            # the argmax and max order score do not depend on the launch shape
+            one = dev_score(t, batch[100:101])
+            assert np.array_equal(one["best"][0], got["best"][100])
+            assert one["max"][0] == got["max"][100]
+        else:
+            t.set_launch(1, chunk_steps=16 if shape == "bench_b1" else 0, orders_per_block=1)
+            parts = [dev_score(t, orders[b:b + 1]) for b in range(len(rows))]
+            got = {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+            idx = list(range(len(rows)))
+        ties = check_against_golden(got, rows, idx, net, w, prior)
+        assert ties == 0, ties
+    finally:
+        t.set_launch(1)
+        t.set_launch(256)
 
 
 def test_mixed60_orders_against_direct_oracle(bnos, mixed60):
