@@ -252,7 +252,10 @@ class Table:
         iterations per shape (bnos_chains_autotune); with first_iteration > 0 each run
         resumes from a copy of `state` -> (chunk steps, chains per block, ms per iteration)."""
         cfg = _chain_cfg(chains, iterations, seed, target, first_iteration, 1, 0, 0, mlp, eps)
-        st = _chain_state(state, iterations, 1) if state is not None else None
+        st = None
+        if state is not None:           # the tuner copies only the chains' positions, never the traces
+            st = _chain_state({k: state.get(k) for k in ("orders", "scores", "best_graphs", "best_scores",
+                                                         "accepted")}, iterations, 1)
         cs, bt, ms = i32(), i32(), f64()
         _check(_lib.bnos_chains_autotune(self._h, ctypes.byref(cfg), ctypes.byref(st) if st is not None else None,
                                          reps, _stream(stream), ctypes.byref(cs), ctypes.byref(bt),

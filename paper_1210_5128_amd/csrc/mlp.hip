@@ -152,7 +152,7 @@ __global__ void k_feat_norm_final(const double *__restrict__ part, int blocks, i
     norm[kF + k] = (float)(1.0 / sd);
 }
 
-struct GradLds {
+struct alignas(16) GradLds {
     MlpLds f;
     float zraw[kRows * kF];
     float h2[kRows][kH];            // relu(layer 2); later reused for dpre1

@@ -95,8 +95,8 @@ __device__ __forceinline__ v4u ld8_strided(const uint16_t *p, int s)
     return v;
 }
 
-// LDS of one forward pass.
-struct MlpLds {
+// LDS of one forward pass (16-byte aligned: operands are read with 16-byte LDS loads).
+struct alignas(16) MlpLds {
     uint16_t z[kRows][16];          // normalised features: hi in columns 0..7, lo in 8..15
     uint16_t h1[2][kRows][kHP];     // relu(layer 1): [0] hi, [1] lo
     float part[kRows][8];           // per column-tile partial logits
