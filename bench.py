@@ -217,8 +217,8 @@ def bench_chains(bnos, datagen, wname: str, chains: int, block: int, burn: int, 
     the score trace is below 1.05 (at most `max_blocks` blocks).  ESS/s uses the
     rank-normalised multi-chain ESS of the sampling phase; 'same_accuracy' states whether
     both reached R-hat < 1.05 and agree on the posterior mean score and on the frequencies
-    of the 20 most uncertain edges within 3 MCSE.  The chain sweep runs in its default
-    launch shape."""
+    of the 20 most uncertain edges within 3 MCSE.  The chain sweep's launch shape is
+    autotuned on burned-in chains first (tuned vs default chain-iterations/s reported)."""
     import torch
     w = datagen.WORKLOADS[wname]
     net, prior = datagen.make(w)
@@ -232,9 +232,26 @@ def bench_chains(bnos, datagen, wname: str, chains: int, block: int, burn: int, 
         torch.cuda.synchronize()
         burn_s = time.perf_counter() - t0
         if label == "batched":
-            # chain-sweep shapes other than the default are switched off in the library
-            out["autotune"] = {"status": "switched off: the tuning run left the device with a memory fault "
-                                         "whose cause is not yet found; default shape used"}
+            # chain-sweep autotuner on copies of the burned-in chains, then tuned vs default
+            cs, bt, ms = table.chains_autotune(C, 64, seed + 7, state=st, first_iteration=burn, reps=2)
+            tuned = {"chunk_steps": cs, "orders_per_block": bt, "ms_per_iteration": ms}
+            rates = {}
+            for shape in ("default", "tuned"):
+                if shape == "default":
+                    table.chains_set_launch(C, 0, 0)
+                else:
+                    table.chains_set_launch(C, cs, bt)
+                s2 = {k: st[k].clone() for k in STATE_KEYS}
+                s2["trace"] = None
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                table.run_chains(s2, 2000, seed + 9, first_iteration=burn, trace_every=2000)
+                torch.cuda.synchronize()
+                rates[shape] = C * 2000 / (time.perf_counter() - t1)
+            out["autotune"] = dict(tuned, chain_iterations_per_s_tuned=rates["tuned"],
+                                   chain_iterations_per_s_default=rates["default"])
+            print(f"# chains autotune: chunk {cs}, {bt} chains/block: {rates['tuned']:.0f} vs default "
+                  f"{rates['default']:.0f} chain-it/s", file=sys.stderr, flush=True)
             edges = uncertain_edges(table, st["orders"], w.n)
             out["traced_edges"] = len(edges)
         tr, et, secs, iters, acc = sample_until_mixed(table, st, C, burn, block, max_blocks, seed + 1, every, edges)

@@ -763,14 +763,6 @@ extern "C" bnos_status bnos_run_chains(bnos_table h, const bnos_chain_cfg *cfg, 
     return run_chains_impl(&h, 1, cfg, st, stream, nullptr);
 }
 
-// Chain sweeps in shapes other than the default (several chunks per row for
-// 16+ chains, or one chain per block with several chains) are switched off:
-// the tuning run over those shapes left the device with a memory fault whose
-// cause is not yet found, so they stay off until it is.
-constexpr bool kChainShapesOff = true;
-constexpr const char *kChainShapesOffMsg =
-    "chain-sweep launch shapes other than the default are switched off (an unresolved device fault)";
-
 static bnos_status check_chain_shape(const TableT *t, int32_t chunk_steps, int32_t orders_per_block)
 {
     if (chunk_steps != 0 && (chunk_steps < 1 || chunk_steps > t->pad_steps || (chunk_steps & (chunk_steps - 1)) != 0)) {
@@ -793,10 +785,6 @@ extern "C" bnos_status bnos_chains_set_launch(bnos_table h, int32_t chains, int3
     if (chains < 1 || chains > 65536) { set_error("chains outside [1, 65536]"); return BNOS_E_RANGE; }
     bnos_status s = check_chain_shape(t, chunk_steps, orders_per_block);
     if (s != BNOS_OK) return s;
-    if (kChainShapesOff && (chunk_steps != 0 || orders_per_block != 0)) {
-        set_error(kChainShapesOffMsg);
-        return BNOS_E_STATE;
-    }
     BNOS_HIP(hipSetDevice(t->device));
     BNOS_HIP(hipDeviceSynchronize());        // sweeps in flight keep their shapes and workspace
     const int bk = TableT::bucket(chains);
@@ -813,10 +801,6 @@ extern "C" bnos_status bnos_chains_autotune(bnos_table h, const bnos_chain_cfg *
     if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
     bnos_status s = validate_cfg(cfg);
     if (s != BNOS_OK) return s;
-    if (kChainShapesOff) {
-        set_error(kChainShapesOffMsg);
-        return BNOS_E_STATE;
-    }
     if (cfg->iterations < 1 || cfg->iterations > (1 << 20)) { set_error("iterations outside [1, 2^20]"); return BNOS_E_RANGE; }
     if (reps < 1 || reps > 100) { set_error("reps outside [1, 100]"); return BNOS_E_RANGE; }
     if (t->n < 2) { set_error("chains need n >= 2 (a swap needs two positions)"); return BNOS_E_RANGE; }

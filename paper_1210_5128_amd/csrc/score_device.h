@@ -409,22 +409,29 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     // can use its 64-entry sub-tile; otherwise its masks read as ~0 (consistent
     // with nothing), so the fold is unchanged and the sub-tile's bytes are not
     // fetched.  (With several orders the union rarely skips a sub-tile and the
-    // test costs more than it saves.)
-    auto lane_needs = [&](int tk) -> bool {
-        if (BT > 1 || !V.tand) return true;
-        const uint64_t sub = (uint64_t)__shfl((unsigned long long)tsl, ((tk - wave) >> 2) * 4 + (lane >> 4), 64);
-        bool any = false;
-#pragma unroll
-        for (int j = 0; j < BT; ++j) any |= (sub & npred[j]) == 0ull;
-        return any;
+    // test costs more than it saves.)  Bit i of `sub_need` tells whether this
+    // lane's sub-tile (lane / 16) of the wavefront's i-th step tile is needed;
+    // lane 4 i + s holds the summary of sub-tile s of that tile.
+    uint32_t sub_need = 0xffffffffu;
+    if (BT == 1 && V.tand) {
+        sub_need = 0u;
+        for (int i = 0; i < steps; ++i) {
+            const uint64_t sub = (uint64_t)__shfl((unsigned long long)tsl, i * 4 + (lane >> 4), 64);
+            sub_need |= ((sub & npred[0]) == 0ull) ? (1u << i) : 0u;
+        }
+    }
+    // This lane's 4-entry group of local tile tk, as an index into the node's
+    // row of groups (below 2^30: rows hold fewer than 2^32 entries).
+    auto group_of = [&](int tk) -> uint32_t {
+        return ((uint32_t)(chunk + (tk >> 2) * V.chunks) << 8) | ((uint32_t)(tk & 3) << 6) | (uint32_t)lane;
     };
     if (k < nt) {
         const int tk = s_tile[wave][k];
-        const int64_t q = gtile(tk) * 64 + lane;             // this lane's 4-entry group in the row
+        const uint32_t q = group_of(tk);
         need_n = s_tneed[wave][k];
         n01 = (u64x2){CM ? dead : ~0ull, ~0ull};
         n23 = (u64x2){~0ull, ~0ull};
-        if (lane_needs(tk)) {
+        if ((sub_need >> (tk >> 2)) & 1u) {
             if (CM) {
                 n01.x = __builtin_nontemporal_load(&ap[q]);
             } else {
@@ -441,11 +448,11 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         const int kn = k + 1;
         if (kn < nt) {
             const int tk = s_tile[wave][kn];
-            const int64_t q = gtile(tk) * 64 + lane;
+            const uint32_t q = group_of(tk);
             need_n = s_tneed[wave][kn];
             n01 = (u64x2){CM ? dead : ~0ull, ~0ull};
             n23 = (u64x2){~0ull, ~0ull};
-            if (lane_needs(tk)) {
+            if ((sub_need >> (tk >> 2)) & 1u) {
                 if (CM) {
                     n01.x = __builtin_nontemporal_load(&ap[q]);
                 } else {
