@@ -59,14 +59,20 @@ __device__ __forceinline__ void acc_push(Acc &a, float x, uint64_t mk)
 // argmax (the first entry holding the group's max, i.e. the smallest mask among
 // equal scores -- earlier groups hold smaller masks, so an equal score never
 // replaces the held best); every other group adds its exp terms and raises the
-// second best.  exp(x - best) = 2^(x log2 e - best log2 e), one fma and one
-// v_exp_f32 per entry; a group with no consistent entry changes nothing (it
-// adds exact zeros).  The caller keeps a.m == a.best.
+// second best.  Each term is 2^fl(x log2e - t), t = fl(best log2e): one fma and
+// one v_exp_f32 per entry.  Against the exact 2^((x - best) log2e) every term
+// carries the same factor 2^(best log2e - t), t's rounding residual, which
+// acc_fold_finish divides out; a change of best rescales the sum by 2^(t_old -
+// t_new), exact, so the sum always holds that one common factor.  A group with
+// no consistent entry changes nothing (it adds exact zeros).
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kScoreFloor = -1.0e38f;   // below every score; keeps best * log2e finite
 
+__device__ __forceinline__ float fold_shift(float best) { return fmaxf(best, kScoreFloor) * kLog2e; }
+
 __device__ __forceinline__ void acc_fold4(Acc &a, const float (&x)[4], const uint64_t (&mk)[4])
 {
+#pragma clang fp contract(off)     // t_old - t_new must subtract the two rounded shifts
     const float b = fmaxf(fmaxf(x[0], x[1]), fmaxf(x[2], x[3]));
     a.sec = fmaxf(a.sec, b);
     if (b > a.best) {
@@ -74,15 +80,27 @@ __device__ __forceinline__ void acc_fold4(Acc &a, const float (&x)[4], const uin
         float o = -INFINITY;
 #pragma unroll
         for (int e = 0; e < 4; ++e) o = (e != i) ? fmaxf(o, x[e]) : o;
-        a.s *= __builtin_amdgcn_exp2f((a.best - b) * kLog2e);       // 0 when nothing was held (best = -inf)
+        a.s *= __builtin_amdgcn_exp2f(fold_shift(a.best) - b * kLog2e);   // 0 when nothing was held
         a.sec = fmaxf(a.best, o);
         a.best = b;
         a.bm = i == 0 ? mk[0] : (i == 1 ? mk[1] : (i == 2 ? mk[2] : mk[3]));
     }
-    const float t = fmaxf(a.best, kScoreFloor) * kLog2e;
+    const float t = fold_shift(a.best);
     const float e0 = __builtin_amdgcn_exp2f(fmaf(x[0], kLog2e, -t)), e1 = __builtin_amdgcn_exp2f(fmaf(x[1], kLog2e, -t));
     const float e2 = __builtin_amdgcn_exp2f(fmaf(x[2], kLog2e, -t)), e3 = __builtin_amdgcn_exp2f(fmaf(x[3], kLog2e, -t));
     a.s += (e0 + e1) + (e2 + e3);
+}
+
+// After the last acc_fold4: divide out 2^(best log2e - t) (the residual of t =
+// fl(best log2e), exact by fma) and make the state an ordinary (m, s) pair.
+__device__ __forceinline__ void acc_fold_finish(Acc &a)
+{
+#pragma clang fp contract(off)
+    if (a.best > -INFINITY) {
+        const float t = a.best * kLog2e;
+        a.s *= __builtin_amdgcn_exp2f(-fmaf(a.best, kLog2e, -t));
+    }
+    a.m = a.best;
 }
 
 // Combine two states (order-independent up to FP32 rounding; the callers fix the order).
@@ -486,7 +504,7 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         }
     }
 #pragma unroll
-    for (int j = 0; j < BT; ++j) a[j].m = a[j].best;
+    for (int j = 0; j < BT; ++j) acc_fold_finish(a[j]);
 
     {
         // a wavefront that folded nothing (no needed tile, or no consistent entry)
