@@ -192,6 +192,25 @@ bnos_status bnos_score_orders(bnos_table t, const int32_t *orders, int32_t B, do
                               float *node_second, void *stream);
 
 /*
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * scoring as bnos_score_orders (same arguments, kernels and results, bit for
+ * bit), with the chunk partials in a fixed device array of 16 MiB that the
+ * library holds on each GPU it runs on until the process ends, instead of
+ * the table's workspace.  It never calls hipMalloc or hipFree; the first call
+ * on a device only looks up that array's address (make it before any capture).
+ * Limit: B orders need B * n * slots * 24 bytes, slots = the launch's chunks
+ * per row (n for the gather pass); above 16 MiB the call returns
+ * BNOS_E_RANGE before any device work (at n = 60, K = 4, in the default
+ * shape for 8+ orders, 30 chunks per row: up to 388 orders in one call).  Every call on a GPU, for any table, uses that GPU's one array:
+ * calls that may overlap on one GPU (streams, host threads) race and must be
+ * serialised by the caller.  Nothing needs clearing between calls.
+ */
+bnos_status bnos_score_orders_noalloc(bnos_table t, const int32_t *orders, int32_t B, double *lse,
+                                      double *maxs, uint64_t *best, double *node_lse, float *node_second,
+                                      void *stream);
+
+/*
  * Host-pointer convenience for one order; synchronous on the null stream.
  * order int32[n]; best_parents uint64[n] (may be NULL).  A non-permutation
  * order is rejected with BNOS_E_INVALID.

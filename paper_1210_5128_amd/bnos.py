@@ -68,6 +68,7 @@ _SIGS = {
     "bnos_counts": (i32, [P, i32, P, P, P, i64]),
     "bnos_score_orders": (i32, [P, P, i32, P, P, P, P, P, P]),
     "bnos_score_order": (i32, [P, P, P, P, P]),
+    "bnos_score_orders_noalloc": (i32, [P, P, i32, P, P, P, P, P, P]),
     "bnos_run_chains": (i32, [P, P, P, P]),
     "bnos_run_chains_multi": (i32, [P, i32, P, P, P]),
     "bnos_mlp_create": (i32, [P]),
@@ -186,6 +187,12 @@ class Table:
         B = int(orders.shape[0])
         _check(_lib.bnos_score_orders(self._h, _dptr(orders), B, _dptr(lse), _dptr(maxs), _dptr(best),
                                       _dptr(node_lse), _dptr(node_second), _stream(stream)))
+
+    def score_orders_noalloc(self, orders, lse, maxs, best, node_lse=None, node_second=None, stream=None):
+        """score_orders with the partials in the library's fixed per-GPU array (bnos_score_orders_noalloc)."""
+        B = int(orders.shape[0])
+        _check(_lib.bnos_score_orders_noalloc(self._h, _dptr(orders), B, _dptr(lse), _dptr(maxs), _dptr(best),
+                                              _dptr(node_lse), _dptr(node_second), _stream(stream)))
 
     def score_order(self, order):
         """Synchronous host-side scoring of one order -> (lse, max, best_parents[n])."""

@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -576,4 +577,74 @@ extern "C" bnos_status bnos_table_set_launch(bnos_table h, int32_t B, int32_t ga
     t->tuned_cs[bk] = chunk_steps;
     t->tuned_bt[bk] = orders_per_block;
     return ensure_workspace(t, B);
+}
+
+// ------------------------------------------------------------------ scoring without allocation
+
+namespace bnos {
+
+// Partials of bnos_score_orders_noalloc: one fixed device array per GPU (every
+// device the library runs on holds its own copy until the process ends).  In
+// host code `scratch` names a host-side stand-in, not device memory: only the
+// address hipGetSymbolAddress returns for the current device may reach a
+// kernel or a copy.
+constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current), resolved on
+// the first call for that device.
+static bnos_status scratch_on(int device, void **out)
+{
+    if (device < 0 || device >= kMaxScratchDevices) {
+        set_error("device id above the library's scratch table");
+        return BNOS_E_RANGE;
+    }
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return BNOS_E_DEVICE;
+        }
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return BNOS_OK;
+}
+
+}  // namespace bnos
+
+extern "C" bnos_status bnos_score_orders_noalloc(bnos_table h, const int32_t *orders, int32_t B, double *lse,
+                                                 double *maxs, uint64_t *best, double *node_lse,
+                                                 float *node_second, void *stream)
+{
+    TableT *t = reinterpret_cast<TableT *>(h);
+    if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
+    if (B < 1 || B > (1 << 20)) { set_error("B outside [1, 2^20]"); return BNOS_E_RANGE; }
+    if (!orders || !lse || !maxs || !best) { set_error("NULL argument"); return BNOS_E_INVALID; }
+    // partials [B][slots][n]: one slot per chunk, or per top member + the empty set in the gather pass
+    const int64_t slots = t->gather_for(B) ? t->n : t->chunks_for(B);
+    const int64_t need = (int64_t)B * slots * t->n * (int64_t)sizeof(Partial);
+    if (need > (int64_t)kNoAllocScratchBytes) {
+        set_error("B = " + std::to_string(B) + " orders need " + std::to_string(need) +
+                  " bytes of scoring partials, above the fixed " + std::to_string(kNoAllocScratchBytes) +
+                  "-byte scratch array of the allocation-free call");
+        return BNOS_E_RANGE;
+    }
+    BNOS_HIP(hipSetDevice(t->device));
+    void *part = nullptr;
+    bnos_status s = scratch_on(t->device, &part);
+    if (s != BNOS_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    ScoreArgs A = score_args(t, orders, B, lse, maxs, best, node_lse, node_second);
+    A.part = reinterpret_cast<Partial *>(part);
+    if (t->gather_for(B)) s = launch_gather(t, A, st, false);
+    else s = launch_stream(t, A, st, 0, false);
+    if (s != BNOS_OK) return s;
+    return launch_merge(A, st);
 }
