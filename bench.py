@@ -753,10 +753,12 @@ def main():
         o = torch.from_numpy(datagen.random_orders(n, Bq, seed=900 + Bq)).to(dev)
         cs, bt, g, ms = table.autotune(o, reps=20 if Bq < 64 else 3, stream=stream)
         tuned[str(Bq)] = {"gather": bool(g), "chunk_steps": cs, "orders_per_block": bt, "tune_ms_per_launch": ms}
-        print(f"# autotune B={Bq}: " + ("gather pass" if g else f"chunk {cs}x1024 entries, {bt} orders/block") +
+        print(f"# autotune B={Bq}: " + ("gather pass" if g else ("balanced schedule, 1 order/block" if cs == 0 else f"chunk {cs}x1024 entries, {bt} orders/block")) +
               f", {ms * 1e3:.1f} us", file=sys.stderr, flush=True)
     if args.chunk_steps:
         tuned = {"fixed_chunk_steps": args.chunk_steps}
+        for Bq in sorted({B, args.batched_check} - {0}):
+            table.set_launch(Bq, chunk_steps=args.chunk_steps)
     rf = r = rs = rh = None
     extra_steps = max(args.steps, 140)
     if args.passes != "skip":
@@ -789,6 +791,8 @@ def main():
             if str(B) in tuned:
                 t2.set_launch(B, gather=tuned[str(B)]["gather"], chunk_steps=tuned[str(B)]["chunk_steps"],
                               orders_per_block=tuned[str(B)]["orders_per_block"])
+            elif args.chunk_steps:
+                t2.set_launch(B, chunk_steps=args.chunk_steps)
             others.append(t2)
         rh = timed(B, extra_steps * args.hbm_tables, args.warmup, skip=True, tables=[table] + others)
         read_set = sum(tb.info()["entries_per_node"] for tb in [table] + others) * n * 6

@@ -17,6 +17,63 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ device helpers
 
+// Wavefront reductions on the data-parallel-primitive (DPP) lane network:
+// quad permutes (lane ^ 1, lane ^ 2), row shifts by 4 and 8 and the two row
+// broadcasts (lane 15 of a row to the next row, lane 31 to rows 2 and 3) leave
+// the reduction of all 64 lanes in lane 63, one VALU instruction per level; a
+// lane whose source does not exist reads the identity.  The association is
+// fixed, so the result does not depend on scheduling; readlane makes it uniform.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v, uint32_t identity)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)identity, (int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v, float identity)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, identity),
+                                                                 __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane63_f32(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ __forceinline__ float wave_max_f32(float v)
+{
+    v = fmaxf(v, dpp_f32<0xb1>(v, -INFINITY));
+    v = fmaxf(v, dpp_f32<0x4e>(v, -INFINITY));
+    v = fmaxf(v, dpp_f32<0x114>(v, -INFINITY));
+    v = fmaxf(v, dpp_f32<0x118>(v, -INFINITY));
+    v = fmaxf(v, dpp_f32<0x142>(v, -INFINITY));
+    v = fmaxf(v, dpp_f32<0x143>(v, -INFINITY));
+    return lane63_f32(v);
+}
+__device__ __forceinline__ float wave_sum_f32(float v)
+{
+    v = v + dpp_f32<0xb1>(v, 0.f);
+    v = v + dpp_f32<0x4e>(v, 0.f);
+    v = v + dpp_f32<0x114>(v, 0.f);
+    v = v + dpp_f32<0x118>(v, 0.f);
+    v = v + dpp_f32<0x142>(v, 0.f);
+    v = v + dpp_f32<0x143>(v, 0.f);
+    return lane63_f32(v);
+}
+__device__ __forceinline__ uint32_t wave_or_u32(uint32_t v)
+{
+    v |= dpp_u32<0xb1>(v, 0u);
+    v |= dpp_u32<0x4e>(v, 0u);
+    v |= dpp_u32<0x114>(v, 0u);
+    v |= dpp_u32<0x118>(v, 0u);
+    v |= dpp_u32<0x142>(v, 0u);
+    v |= dpp_u32<0x143>(v, 0u);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ __forceinline__ uint64_t wave_or_u64(uint64_t v)
+{
+    return ((uint64_t)wave_or_u32((uint32_t)(v >> 32)) << 32) | wave_or_u32((uint32_t)v);
+}
+
+
 struct Acc {
     float m, s;       // log-sum-exp state: max and sum of exp(x - m)
     float best, sec;  // top-1 score and best score among the other entries
@@ -141,6 +198,41 @@ __device__ __forceinline__ Acc acc_sel(bool c, const Acc &x, const Acc &y)
     return r;
 }
 
+// Reduction of one state per lane whose log-sum-exp max is its top-1 score
+// (m == best, as the streaming fold leaves it) over the 64 lanes: the max;
+// each lane's sum rescaled to it and summed; the argmax as the smallest mask
+// among the lanes holding the max (read from the one lane holding it, else a
+// butterfly minimum); the second best as that max when two lanes hold it,
+// else the max over the other lanes' best and the holder's second.  Fixed
+// trees, so the result does not depend on scheduling; every lane returns it.
+__device__ __forceinline__ Acc acc_wave_reduce_one(const Acc &a)
+{
+    const float M = wave_max_f32(a.best);
+    const float s = wave_sum_f32((a.best == -INFINITY) ? 0.f : a.s * __expf(a.best - M));
+    const bool top = a.best == M;
+    const uint64_t tops = __ballot(top);
+    Acc r;
+    r.m = M;
+    r.s = s;
+    r.best = M;
+    if (__popcll(tops) == 1) {                               // uniform: one lane holds the max
+        const int w = __builtin_ctzll(tops);
+        r.bm = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(a.bm >> 32), w) << 32) |
+               (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)a.bm, w);
+        r.sec = wave_max_f32(top ? a.sec : a.best);
+    } else {                                                 // a tie: the smallest mask among the holders
+        uint64_t bm = top ? a.bm : ~0ull;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t o = (uint64_t)__shfl_xor((unsigned long long)bm, off, 64);
+            bm = o < bm ? o : bm;
+        }
+        r.bm = bm;
+        r.sec = M;
+    }
+    return r;
+}
+
 // Reduction of BT per-lane states over the 64 lanes of a wavefront, as a
 // reduce-scatter: while more than one state is left, lanes split by the next
 // high lane bit (32, 16, ...) keep one half of the states, receive the
@@ -206,13 +298,8 @@ __device__ __forceinline__ uint64_t wave_pred(const int32_t *__restrict__ ord, i
     uint64_t bit = inr ? (1ull << v) : 0ull;
     uint64_t here = __ballot(lane < n && v == node);
     int pos = here ? __builtin_ctzll(here) : 0;
-    uint64_t before = (lane < pos) ? bit : 0ull;
-    uint64_t all = bit;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        before |= (uint64_t)__shfl_xor((unsigned long long)before, off, 64);
-        all |= (uint64_t)__shfl_xor((unsigned long long)all, off, 64);
-    }
+    const uint64_t before = wave_or_u64((lane < pos) ? bit : 0ull);
+    const uint64_t all = wave_or_u64(bit);
     uint64_t full = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
     valid = (all == full) && (__ballot(lane < n && !inr) == 0ull);
     return valid ? before : 0ull;
@@ -259,6 +346,11 @@ struct ScoreArgs {
     const uint64_t *tsub;      // sub-tile summaries (with tand)
     const uint64_t *anchor;    // first mask of every 4 entries in slot space, or null
     int K;
+    // One order on the balanced schedule (else null): block x is (p << 16) | c of
+    // sched[x]; the node at position p has sched_c[p] chunks; rows have row_steps steps.
+    const uint32_t *sched;
+    const int32_t *sched_c;
+    int sched_blocks, row_steps;
 };
 
 // What one streaming block needs to know about its table and its orders.
@@ -328,7 +420,8 @@ __device__ __forceinline__ uint64_t to_nodes(uint64_t s, int node)
 // 6 bytes per entry read instead of 12.  NOSAT steps without the saturation
 // test where next_mask_nosat allows it.
 template <int BT, bool CM = false, bool NOSAT = false>
-__device__ __forceinline__ void score_block(const TabView &V, int node, int chunk, int group)
+__device__ __forceinline__ void score_block(const TabView &V, int node, int chunk, int group, int chunks,
+                                            int steps)
 {
     static_assert(!CM || BT == 1, "computed masks serve one order per block");
     __shared__ uint64_t s_npred[BT];
@@ -350,8 +443,8 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     // 16 sub-tile summaries still fill one 128-byte line.
     const int64_t row = (int64_t)node * V.S_pad;             // the node's first entry
     const int64_t trow = row >> 8;                            // and first tile
-    const int steps = V.chunk_entries / kEntriesPerStep;      // each wavefront owns local tiles wave + 4*i, i < steps
-    auto gtile = [&](int tl) -> int64_t { return ((chunk + (int64_t)(tl >> 2) * V.chunks) << 2) + (tl & 3); };
+    // each wavefront owns local tiles wave + 4*i, i < steps (the block's steps: chunk + i * chunks)
+    auto gtile = [&](int tl) -> int64_t { return ((chunk + (int64_t)(tl >> 2) * chunks) << 2) + (tl & 3); };
     // this wavefront's tile summaries, requested before the predecessor masks so the latencies overlap
     uint64_t tsum = 0, tsl = 0;
     if (V.tand && lane < steps) tsum = V.tand[trow + gtile(lane * 4 + wave)];
@@ -417,92 +510,84 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     }
     __syncthreads();
     const int nt = s_ntile[wave];
-    // Software pipeline over this wavefront's needed tiles: the loads of the
-    // next tile are in flight while the current one is folded.
-    int k = 0;
-    u64x2 n01 = {0ull, 0ull}, n23 = {0ull, 0ull};
-    f32x4 nsc = {0.f, 0.f, 0.f, 0.f};
-    uint32_t need_n = 0;
     // With one order per block, a lane reads its 4 entries only if the order
     // can use its 64-entry sub-tile; otherwise its masks read as ~0 (consistent
     // with nothing), so the fold is unchanged and the sub-tile's bytes are not
     // fetched.  (With several orders the union rarely skips a sub-tile and the
-    // test costs more than it saves.)  Bit i of `sub_need` tells whether this
-    // lane's sub-tile (lane / 16) of the wavefront's i-th step tile is needed;
-    // lane 4 i + s holds the summary of sub-tile s of that tile.
-    uint32_t sub_need = 0xffffffffu;
-    if (BT == 1 && V.tand) {
-        sub_need = 0u;
-        for (int i = 0; i < steps; ++i) {
-            const uint64_t sub = (uint64_t)__shfl((unsigned long long)tsl, i * 4 + (lane >> 4), 64);
-            sub_need |= ((sub & npred[0]) == 0ull) ? (1u << i) : 0u;
-        }
-    }
+    // test costs more than it saves.)  Lane 4 i + s holds the summary of
+    // sub-tile s of the wavefront's i-th step tile, so one ballot gives every
+    // lane its bits: bit 4 i + s of `sub_ok` (the same in all lanes).
+    uint64_t sub_ok = ~0ull;
+    if (BT == 1 && V.tand) sub_ok = __ballot(lane < 4 * steps && (tsl & npred[0]) == 0ull);
+    const int my_sub = lane >> 4;
     // This lane's 4-entry group of local tile tk, as an index into the node's
     // row of groups (below 2^30: rows hold fewer than 2^32 entries).
     auto group_of = [&](int tk) -> uint32_t {
-        return ((uint32_t)(chunk + (tk >> 2) * V.chunks) << 8) | ((uint32_t)(tk & 3) << 6) | (uint32_t)lane;
+        return ((uint32_t)(chunk + (tk >> 2) * chunks) << 8) | ((uint32_t)(tk & 3) << 6) | (uint32_t)lane;
     };
-    if (k < nt) {
-        const int tk = s_tile[wave][k];
-        const uint32_t q = group_of(tk);
-        need_n = s_tneed[wave][k];
-        n01 = (u64x2){CM ? dead : ~0ull, ~0ull};
-        n23 = (u64x2){~0ull, ~0ull};
-        if ((sub_need >> (tk >> 2)) & 1u) {
+    // Prefetch ring over this wavefront's needed tiles: while the tile in
+    // slot d is folded, the loads of the next D - 1 tiles are in flight; the
+    // slot is refilled (with the tile D places on) right after its fold, and
+    // the loop is unrolled by D so that every slot keeps its own registers.
+    constexpr int D = (BT == 1) ? 3 : 2;
+    u64x2 r01[D], r23[D];
+    f32x4 rsc[D];
+    uint32_t rneed[D];
+#define BNOS_ISSUE(d, kk)                                                                       \
+    if ((kk) < nt) {                                                                            \
+        const int tk_ = s_tile[wave][(kk)];                                                     \
+        const uint32_t q_ = group_of(tk_);                                                      \
+        rneed[d] = s_tneed[wave][(kk)];                                                         \
+        r01[d] = (u64x2){CM ? dead : ~0ull, ~0ull};                                             \
+        r23[d] = (u64x2){~0ull, ~0ull};                                                         \
+        if ((sub_ok >> ((tk_ & ~3) + my_sub)) & 1ull) {                                         \
+            if (CM) {                                                                           \
+                r01[d].x = __builtin_nontemporal_load(&ap[q_]);                                 \
+            } else {                                                                            \
+                r01[d] = __builtin_nontemporal_load(&mp[2 * q_]);                               \
+                r23[d] = __builtin_nontemporal_load(&mp[2 * q_ + 1]);                           \
+            }                                                                                   \
+            rsc[d] = __builtin_nontemporal_load(&sp[q_]);                                       \
+        }                                                                                       \
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        rsc[d] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        rneed[d] = 0u;
+        BNOS_ISSUE(d, d)
+    }
+    for (int k0 = 0; k0 < nt; k0 += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int k = k0 + d;
+            if (k >= nt) break;                              // uniform
+            uint64_t mk[4] = {r01[d].x, r01[d].y, r23[d].x, r23[d].y};
             if (CM) {
-                n01.x = __builtin_nontemporal_load(&ap[q]);
-            } else {
-                n01 = __builtin_nontemporal_load(&mp[2 * q]);
-                n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
+                mk[1] = NOSAT ? next_mask_nosat(mk[0], V.K) : next_mask(mk[0], V.K);
+                mk[2] = NOSAT ? next_mask_nosat(mk[1], V.K) : next_mask(mk[1], V.K);
+                mk[3] = NOSAT ? next_mask_nosat(mk[2], V.K) : next_mask(mk[2], V.K);
             }
-            nsc = __builtin_nontemporal_load(&sp[q]);
-        }
-    }
-    for (; k < nt; ++k) {
-        const u64x2 m01 = n01, m23 = n23;
-        const f32x4 sc = nsc;
-        const uint32_t need_c = need_n;
-        const int kn = k + 1;
-        if (kn < nt) {
-            const int tk = s_tile[wave][kn];
-            const uint32_t q = group_of(tk);
-            need_n = s_tneed[wave][kn];
-            n01 = (u64x2){CM ? dead : ~0ull, ~0ull};
-            n23 = (u64x2){~0ull, ~0ull};
-            if ((sub_need >> (tk >> 2)) & 1u) {
-                if (CM) {
-                    n01.x = __builtin_nontemporal_load(&ap[q]);
-                } else {
-                    n01 = __builtin_nontemporal_load(&mp[2 * q]);
-                    n23 = __builtin_nontemporal_load(&mp[2 * q + 1]);
+            const float x[4] = {rsc[d].x, rsc[d].y, rsc[d].z, rsc[d].w};
+            const uint32_t need_c = rneed[d];
+#pragma unroll
+            for (int j = 0; j < BT; ++j) {
+                if (!((need_c >> j) & 1u)) continue;         // uniform
+                const uint64_t np = CM ? npred_s : npred[j];
+                float xs[4];
+                bool any = false;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const bool ok = (mk[e] & np) == 0ull;
+                    xs[e] = ok ? x[e] : -INFINITY;
+                    any |= ok;
                 }
-                nsc = __builtin_nontemporal_load(&sp[q]);
+                if (__ballot(any) == 0ull) continue;         // uniform: nothing consistent in the wavefront
+                acc_fold4(a[j], xs, mk);
             }
-        }
-        uint64_t mk[4] = {m01.x, m01.y, m23.x, m23.y};
-        if (CM) {
-            mk[1] = NOSAT ? next_mask_nosat(mk[0], V.K) : next_mask(mk[0], V.K);
-            mk[2] = NOSAT ? next_mask_nosat(mk[1], V.K) : next_mask(mk[1], V.K);
-            mk[3] = NOSAT ? next_mask_nosat(mk[2], V.K) : next_mask(mk[2], V.K);
-        }
-        const float x[4] = {sc.x, sc.y, sc.z, sc.w};
-#pragma unroll
-        for (int j = 0; j < BT; ++j) {
-            if (!((need_c >> j) & 1u)) continue;             // uniform
-            const uint64_t np = CM ? npred_s : npred[j];
-            float xs[4];
-            bool any = false;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const bool ok = (mk[e] & np) == 0ull;
-                xs[e] = ok ? x[e] : -INFINITY;
-                any |= ok;
-            }
-            if (__ballot(any) == 0ull) continue;             // uniform: nothing consistent in the wavefront
-            acc_fold4(a[j], xs, mk);
+            BNOS_ISSUE(d, k + D)
         }
     }
+#undef BNOS_ISSUE
 #pragma unroll
     for (int j = 0; j < BT; ++j) acc_fold_finish(a[j]);
 
@@ -513,7 +598,7 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
 #pragma unroll
         for (int j = 0; j < BT; ++j) any |= a[j].m != -INFINITY;
         Acc r;
-        if (__ballot(any) != 0ull) r = acc_wave_reduce_scatter<BT>(a, lane);
+        if (__ballot(any) != 0ull) r = (BT == 1) ? acc_wave_reduce_one(a[0]) : acc_wave_reduce_scatter<BT>(a, lane);
         else acc_init(r);
         if ((lane & (64 / BT - 1)) == 0) {
             const int j = lane / (64 / BT);
@@ -655,6 +740,17 @@ template <int BT, bool CM = false, bool NOSAT = false>
 __global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
 {
     int x, y;
+    if (BT == 1 && A.sched) {
+        // one order, balanced schedule: block x is chunk c of sched_c[p] of the node at position p
+        if (!xcd_block(A.sched_blocks, x, y)) return;
+        const uint32_t e = A.sched[x];
+        const int p = (int)(e >> 16), c = (int)(e & 0xffffu);
+        const int C = A.sched_c[p];
+        const int v = A.orders[p];
+        const int node = (v >= 0 && v < A.n) ? v : p;
+        score_block<BT, CM, NOSAT>(view_of(A), node, c, 0, C, (A.row_steps - c + C - 1) / C);
+        return;
+    }
     if (!xcd_block((int64_t)A.n * A.chunks, x, y)) return;
     int node = x / A.chunks;
     const int chunk = x - node * A.chunks;
@@ -662,7 +758,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
         const int v = A.orders[(int64_t)y * A.n + (A.n - 1 - node)];
         node = (v >= 0 && v < A.n) ? v : node;
     }
-    score_block<BT, CM, NOSAT>(view_of(A), node, chunk, y);
+    score_block<BT, CM, NOSAT>(view_of(A), node, chunk, y, A.chunks, A.chunk_entries / kEntriesPerStep);
 }
 
 // Index of the segment holding x, for prefix bases base[0] = 0 < ... < base[T].
@@ -690,7 +786,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_multi(const TabView *__
     const int local = (int)((int64_t)x - blk_base[k]);
     const int node = local / V.chunks;
     const int chunk = local - node * V.chunks;
-    score_block<BT>(V, node, chunk, y);
+    score_block<BT>(V, node, chunk, y, V.chunks, V.chunk_entries / kEntriesPerStep);
 }
 
 // ------------------------------------------------------------------ gather scoring
@@ -744,8 +840,10 @@ struct MergeLds {
 // fixed tree (lower wave always the left operand).  The merged state of node
 // node_j is valid in lane j of wave 0.  All threads of the block must call it.
 __device__ __forceinline__ Acc merge_nodes(const Partial *__restrict__ base, int n, int chunks, int node_j,
-                                           MergeLds &L)
+                                           MergeLds &L, int nch_j = -1)
 {
+    // nch_j >= 0: this lane's node has only its first nch_j chunk slots (stride `chunks`)
+    const int lim = nch_j >= 0 ? nch_j : chunks;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     Acc a;
@@ -754,7 +852,7 @@ __device__ __forceinline__ Acc merge_nodes(const Partial *__restrict__ base, int
         const Partial *p = base + node_j;
         int c = wave;
         // four loads in flight per step
-        for (; c + 3 * kMergeWaves < chunks; c += 4 * kMergeWaves) {
+        for (; c + 3 * kMergeWaves < lim; c += 4 * kMergeWaves) {
             const Acc x0 = load_partial(p + (int64_t)c * n);
             const Acc x1 = load_partial(p + (int64_t)(c + kMergeWaves) * n);
             const Acc x2 = load_partial(p + (int64_t)(c + 2 * kMergeWaves) * n);
@@ -764,7 +862,7 @@ __device__ __forceinline__ Acc merge_nodes(const Partial *__restrict__ base, int
             acc_merge(a, x2);
             acc_merge(a, x3);
         }
-        for (; c < chunks; c += kMergeWaves) acc_merge(a, load_partial(p + (int64_t)c * n));
+        for (; c < lim; c += kMergeWaves) acc_merge(a, load_partial(p + (int64_t)c * n));
     }
     if (wave < kMergeWaves) {
         L.m[wave][lane] = a.m;
@@ -808,7 +906,18 @@ __device__ __forceinline__ void merge_block(const ScoreArgs &A, int b, MergeLds 
     // the order's entries are requested first and checked after the merge, so the
     // two loads overlap
     const int v = lane < n ? A.orders[(int64_t)b * n + lane] : -1;
-    const Acc r = merge_nodes(A.part + (int64_t)b * A.chunks * n, n, A.chunks, lane < n ? lane : -1, L);
+    int nch = -1;
+    if (A.sched) {
+        // the node's chunk count is that of its position (lane p holds the node at p)
+        __shared__ int s_pos[64];
+        if (threadIdx.x < 64) s_pos[threadIdx.x] = -1;
+        __syncthreads();
+        if (wave == 0 && lane < n && v >= 0 && v < n) s_pos[v] = lane;
+        __syncthreads();
+        const int pos = lane < n ? s_pos[lane] : -1;
+        nch = pos >= 0 ? A.sched_c[pos] : A.chunks;     // an invalid order scores NaN anyway
+    }
+    const Acc r = merge_nodes(A.part + (int64_t)b * A.chunks * n, n, A.chunks, lane < n ? lane : -1, L, nch);
     valid = order_valid(v, n, lane);
     lse_out = 0.0;
     max_out = 0.0;
@@ -835,5 +944,6 @@ ScoreArgs score_args(const TableT *t, const int32_t *orders, int B, double *lse,
 bnos_status launch_stream(TableT *t, const ScoreArgs &A, hipStream_t st, int bt, bool allow_timing = true);
 bnos_status launch_gather(TableT *t, ScoreArgs &A, hipStream_t st, bool allow_timing = true);
 bnos_status launch_merge(const ScoreArgs &A, hipStream_t st);
+bnos_status build_schedule(TableT *t, int target);
 
 }  // namespace bnos
