@@ -753,7 +753,7 @@ def main():
         o = torch.from_numpy(datagen.random_orders(n, Bq, seed=900 + Bq)).to(dev)
         cs, bt, g, ms = table.autotune(o, reps=20 if Bq < 64 else 3, stream=stream)
         tuned[str(Bq)] = {"gather": bool(g), "chunk_steps": cs, "orders_per_block": bt, "tune_ms_per_launch": ms}
-        print(f"# autotune B={Bq}: " + ("gather pass" if g else ("balanced schedule, 1 order/block" if cs == 0 else f"chunk {cs}x1024 entries, {bt} orders/block")) +
+        print(f"# autotune B={Bq}: " + ("gather pass" if g else f"chunk {cs}x1024 entries, {bt} orders/block") +
               f", {ms * 1e3:.1f} us", file=sys.stderr, flush=True)
     if args.chunk_steps:
         tuned = {"fixed_chunk_steps": args.chunk_steps}

@@ -55,13 +55,6 @@ struct TableT {
     bool tile_skip = true;
     uint64_t *d_anchor = nullptr;   // [n * S_pad / 4]: slot-space mask of every 4th entry
     bool computed_masks = true;     // one-order blocks compute masks from the anchors
-    // Balanced schedule of a one-order launch: the node at position p gets
-    // sched_c[p] blocks (chunk c of sched_c[p]: the row's steps c, c + C, ...),
-    // about equal in expected needed tiles; d_sched lists the blocks as
-    // (p << 16) | c, the last positions (most predecessors) first.
-    uint32_t *d_sched = nullptr;    // [sched_blocks]
-    int32_t *d_sched_c = nullptr;   // [n]
-    int sched_blocks = 0, sched_max = 0;
 
     // order-scoring workspace: per (order, node, chunk) partial reductions
     void *d_part = nullptr;
@@ -99,10 +92,6 @@ struct TableT {
         return B >= 8 ? pad_steps * 1024 : chunk_entries;
     }
     int chunks_for(int B) const { return (int)(S_pad / chunk_entries_for(B)); }
-    // One order per launch without a fixed chunk length takes the balanced schedule.
-    bool sched_for(int B) const { return B == 1 && tuned_cs[0] == 0 && sched_blocks > 0; }
-    // partial slots per order of a streaming launch of B orders
-    int slots_for(int B) const { return sched_for(B) ? sched_max : chunks_for(B); }
     // Chain sweeps of C chains have their own launch shape (bnos_chains_autotune /
     // bnos_chains_set_launch) per chain-count bucket; 0 = the scoring shape of a
     // batch of C orders, except that the orders per block follow pick_bt.
@@ -120,7 +109,6 @@ struct TableT {
     {
         int c = chunks_for(B) > n ? chunks_for(B) : n;
         if (chain_chunks_for(B) > c) c = chain_chunks_for(B);
-        if (B == 1 && sched_max > c) c = sched_max;
         return (int64_t)B * n * c * (int64_t)sizeof(Partial);
     }
     bool gather_for(int B) const { return K <= 4 && tuned_gather[bucket(B)] != 0; }
@@ -129,8 +117,6 @@ struct TableT {
 constexpr uint32_t kMagic = 0xB0A5C0DEu;
 
 void set_error(const std::string &msg);
-// the balanced one-order schedule of a built table, over about `target` blocks (score.hip)
-bnos_status build_schedule(TableT *t, int target);
 bool handle_live(const TableT *t);
 void register_handle(TableT *t);
 void unregister_handle(TableT *t);

@@ -47,7 +47,7 @@ int64_t TableT::device_bytes() const
     return (int64_t)n * S_pad * (int64_t)(sizeof(uint64_t) + sizeof(float)) + (int64_t)n * N_pad +
            (int64_t)n * (int64_t)(sizeof(int32_t) + n * sizeof(double) + 5 * sizeof(double)) + 64 * 8 * 8 +
            part_bytes + (int64_t)n * (S_pad / 256) * 8 + (int64_t)n * (S_pad / 64) * 8 +
-           (int64_t)n * (S_pad / 4) * 8 + (int64_t)sched_blocks * 4 + (int64_t)n * 4;
+           (int64_t)n * (S_pad / 4) * 8;
 }
 
 // ------------------------------------------------------------------ device helpers
@@ -684,8 +684,6 @@ static void free_device(TableT *t)
     hipFree(t->d_tsub);
     hipFree(t->d_anchor);
     hipFree(t->d_part);
-    hipFree(t->d_sched);
-    hipFree(t->d_sched_c);
     for (auto e : t->ev_start) hipEventDestroy(e);
     for (auto e : t->ev_stop) hipEventDestroy(e);
 }
@@ -929,16 +927,6 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     hipFree(d_den);
     hipFree(d_lut);
 #undef CK
-    {
-        // balanced schedule of one-order launches: about one round of resident blocks (8 per CU)
-        int cus = 256, dev = 0;
-        if (hipGetDevice(&dev) == hipSuccess) {
-            int v = 0;
-            if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
-        }
-        const bnos_status ss = build_schedule(t, cus * 8);
-        if (ss != BNOS_OK) return fail(ss);
-    }
     t->magic = kMagic;
     register_handle(t);
     *out = reinterpret_cast<bnos_table>(t);

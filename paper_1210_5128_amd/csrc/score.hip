@@ -216,12 +216,8 @@ ScoreArgs score_args(const TableT *t, const int32_t *orders, int B, double *lse,
     A.masks = t->d_masks;
     A.scores = t->d_scores;
     A.S_pad = t->S_pad;
-    A.chunks = t->slots_for(B);
+    A.chunks = t->chunks_for(B);
     A.chunk_entries = t->chunk_entries_for(B);
-    A.sched = t->sched_for(B) ? t->d_sched : nullptr;
-    A.sched_c = t->d_sched_c;
-    A.sched_blocks = t->sched_blocks;
-    A.row_steps = (int)(t->S_pad / kEntriesPerStep);
     A.orders = orders;
     A.B = B;
     A.n = t->n;
@@ -273,8 +269,7 @@ bnos_status launch_stream(TableT *t, const ScoreArgs &A, hipStream_t st, int bt,
     if (allow_timing && t->timing && t->timing_seen++ % t->timing_every == 0) {
         if ((s = next_events(t, e0, e1, (A.B + bt - 1) / bt)) != BNOS_OK) return s;
     }
-    const int nbx = A.sched ? A.sched_blocks : t->n * A.chunks;
-    if (A.sched) bt = 1;                     // the balanced schedule serves one order
+    const int nbx = t->n * A.chunks;
     if (bt == 8) launch_bt<8>(A, nbx, st, e0, e1);
     else if (bt == 4) launch_bt<4>(A, nbx, st, e0, e1);
     else if (bt == 2) launch_bt<2>(A, nbx, st, e0, e1);
@@ -289,7 +284,6 @@ bnos_status launch_gather(TableT *t, ScoreArgs &A, hipStream_t st, bool allow_ti
 {
     bnos_status s;
     A.chunks = t->n;
-    A.sched = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (allow_timing && t->timing && t->timing_seen++ % t->timing_every == 0) {
         if ((s = next_events(t, e0, e1, 0)) != BNOS_OK) return s;
@@ -320,65 +314,6 @@ static bnos_status score_impl(TableT *t, const int32_t *orders, int B, double *l
     if (s != BNOS_OK) return s;
     hipLaunchKernelGGL(k_merge, dim3(B), dim3(kMergeWaves * 64), 0, st, A);
     BNOS_HIP(hipGetLastError());
-    return BNOS_OK;
-}
-
-// Balanced schedule of a one-order launch.  A tile is needed at a node with p
-// predecessors iff its AND of masks (k members) lies in the predecessor set,
-// which for a uniformly random order has probability prod_{i<k} (p - i) / (n - 1 - i);
-// every row lists the same slot-space masks, so one row's tile ANDs give the
-// expected needed tiles T_p of every node at position p.  Position p gets
-// C_p = T_p / W blocks (W = the tiles per block that spreads all positions over
-// `target` blocks), at least enough for 16 steps per block and at most one step
-// each; blocks are listed from the last position down, the heaviest first.
-bnos_status build_schedule(TableT *t, int target)
-{
-    const int n = t->n;
-    const int64_t R = t->S_pad / kEntriesPerStep;          // 1024-entry steps per row
-    const int64_t tiles = t->S_pad / 256;
-    std::vector<uint64_t> tand((size_t)tiles);
-    BNOS_HIP(hipMemcpy(tand.data(), t->d_tand, sizeof(uint64_t) * (size_t)tiles, hipMemcpyDeviceToHost));
-    std::vector<double> hist(65, 0.0);
-    for (uint64_t a : tand) hist[__builtin_popcountll(a)] += 1.0;
-    std::vector<double> T(n, 0.0);
-    double total = 0.0;
-    for (int p = 0; p < n; ++p) {
-        for (int k = 0; k <= 64 && k <= p; ++k) {
-            if (hist[k] == 0.0) continue;
-            double pr = 1.0;
-            for (int i = 0; i < k; ++i) pr *= (double)(p - i) / (double)(n - 1 - i);
-            T[p] += hist[k] * pr;
-        }
-        total += T[p];
-    }
-    const int64_t cmin = (R + kMaxStepsPerChunk - 1) / kMaxStepsPerChunk;
-    const double W = total > 0.0 ? total / (double)target : 1.0;
-    std::vector<int32_t> C(n);
-    int64_t blocks = 0;
-    int cmax = 0;
-    for (int p = 0; p < n; ++p) {
-        int64_t c = (int64_t)std::ceil(T[p] / (W > 1e-9 ? W : 1e-9));
-        c = c < cmin ? cmin : (c > R ? R : c);
-        C[p] = (int32_t)c;
-        blocks += c;
-        cmax = (int)c > cmax ? (int)c : cmax;
-    }
-    if (blocks > (1 << 24) || R > 0xffff) { t->sched_blocks = 0; return BNOS_OK; }   // plain chunks then
-    std::vector<uint32_t> map((size_t)blocks);
-    size_t x = 0;
-    for (int p = n - 1; p >= 0; --p)
-        for (int c = 0; c < C[p]; ++c) map[x++] = ((uint32_t)p << 16) | (uint32_t)c;
-    hipFree(t->d_sched);
-    hipFree(t->d_sched_c);
-    t->d_sched = nullptr;
-    t->d_sched_c = nullptr;
-    t->sched_blocks = 0;
-    BNOS_HIP(hipMalloc((void **)&t->d_sched, sizeof(uint32_t) * map.size()));
-    BNOS_HIP(hipMalloc((void **)&t->d_sched_c, sizeof(int32_t) * (size_t)n));
-    BNOS_HIP(hipMemcpy(t->d_sched, map.data(), sizeof(uint32_t) * map.size(), hipMemcpyHostToDevice));
-    BNOS_HIP(hipMemcpy(t->d_sched_c, C.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
-    t->sched_blocks = (int)blocks;
-    t->sched_max = cmax;
     return BNOS_OK;
 }
 
@@ -475,9 +410,6 @@ extern "C" bnos_status bnos_table_count_tiles(bnos_table h, const int32_t *order
     BNOS_HIP(hipSetDevice(t->device));
     ScoreArgs A = score_args(t, orders, B, nullptr, nullptr, nullptr, nullptr, nullptr);
     A.tand = t->d_tand;
-    // the same tiles are read whatever the decomposition: count them over uniform chunks
-    A.sched = nullptr;
-    A.chunks = t->chunks_for(B);
     const int bt = pick_bt(t, B);
     const int nbx = t->n * A.chunks;
     const int64_t blocks = (int64_t)nbx * ((B + bt - 1) / bt);
@@ -555,9 +487,7 @@ extern "C" bnos_status bnos_table_autotune(bnos_table h, const int32_t *orders, 
     double best_ms = 1e300;
     int best_cs = t->chunk_entries / kEntriesPerStep, best_bt = pick_bt(t, B);
     bnos_status s = BNOS_OK;
-    // chunk lengths 1 .. pad_steps, and for one order first the balanced schedule (cs = 0)
-    const int cs0 = (B == 1 && t->sched_blocks > 0) ? 0 : 1;
-    for (int cs = cs0; cs <= t->pad_steps && e == hipSuccess && s == BNOS_OK; cs = cs ? cs << 1 : 1) {
+    for (int cs = 1; cs <= t->pad_steps && e == hipSuccess && s == BNOS_OK; cs <<= 1) {
         t->tuned_cs[bk] = cs;
         if ((s = ensure_workspace(t, B)) != BNOS_OK) break;
         for (int bt = 1; bt <= 8 && bt <= B && s == BNOS_OK; bt <<= 1) {
@@ -698,7 +628,7 @@ extern "C" bnos_status bnos_score_orders_noalloc(bnos_table h, const int32_t *or
     if (B < 1 || B > (1 << 20)) { set_error("B outside [1, 2^20]"); return BNOS_E_RANGE; }
     if (!orders || !lse || !maxs || !best) { set_error("NULL argument"); return BNOS_E_INVALID; }
     // partials [B][slots][n]: one slot per chunk, or per top member + the empty set in the gather pass
-    const int64_t slots = t->gather_for(B) ? t->n : t->slots_for(B);
+    const int64_t slots = t->gather_for(B) ? t->n : t->chunks_for(B);
     const int64_t need = (int64_t)B * slots * t->n * (int64_t)sizeof(Partial);
     if (need > (int64_t)kNoAllocScratchBytes) {
         set_error("B = " + std::to_string(B) + " orders need " + std::to_string(need) +

@@ -127,7 +127,8 @@ constexpr float kScoreFloor = -1.0e38f;   // below every score; keeps best * log
 
 __device__ __forceinline__ float fold_shift(float best) { return fmaxf(best, kScoreFloor) * kLog2e; }
 
-__device__ __forceinline__ void acc_fold4(Acc &a, const float (&x)[4], const uint64_t (&mk)[4])
+// t: the caller keeps t == fold_shift(a.best) (initially fold_shift(-inf)).
+__device__ __forceinline__ void acc_fold4(Acc &a, float &t, const float (&x)[4], const uint64_t (&mk)[4])
 {
 #pragma clang fp contract(off)     // t_old - t_new must subtract the two rounded shifts
     const float b = fmaxf(fmaxf(x[0], x[1]), fmaxf(x[2], x[3]));
@@ -137,12 +138,13 @@ __device__ __forceinline__ void acc_fold4(Acc &a, const float (&x)[4], const uin
         float o = -INFINITY;
 #pragma unroll
         for (int e = 0; e < 4; ++e) o = (e != i) ? fmaxf(o, x[e]) : o;
-        a.s *= __builtin_amdgcn_exp2f(fold_shift(a.best) - b * kLog2e);   // 0 when nothing was held
+        const float tn = b * kLog2e;
+        a.s *= __builtin_amdgcn_exp2f(t - tn);               // 0 when nothing was held
+        t = tn;
         a.sec = fmaxf(a.best, o);
         a.best = b;
         a.bm = i == 0 ? mk[0] : (i == 1 ? mk[1] : (i == 2 ? mk[2] : mk[3]));
     }
-    const float t = fold_shift(a.best);
     const float e0 = __builtin_amdgcn_exp2f(fmaf(x[0], kLog2e, -t)), e1 = __builtin_amdgcn_exp2f(fmaf(x[1], kLog2e, -t));
     const float e2 = __builtin_amdgcn_exp2f(fmaf(x[2], kLog2e, -t)), e3 = __builtin_amdgcn_exp2f(fmaf(x[3], kLog2e, -t));
     a.s += (e0 + e1) + (e2 + e3);
@@ -346,11 +348,6 @@ struct ScoreArgs {
     const uint64_t *tsub;      // sub-tile summaries (with tand)
     const uint64_t *anchor;    // first mask of every 4 entries in slot space, or null
     int K;
-    // One order on the balanced schedule (else null): block x is (p << 16) | c of
-    // sched[x]; the node at position p has sched_c[p] chunks; rows have row_steps steps.
-    const uint32_t *sched;
-    const int32_t *sched_c;
-    int sched_blocks, row_steps;
 };
 
 // What one streaming block needs to know about its table and its orders.
@@ -446,11 +443,15 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     // each wavefront owns local tiles wave + 4*i, i < steps (the block's steps: chunk + i * chunks)
     auto gtile = [&](int tl) -> int64_t { return ((chunk + (int64_t)(tl >> 2) * chunks) << 2) + (tl & 3); };
     // this wavefront's tile summaries, requested before the predecessor masks so the latencies overlap
-    uint64_t tsum = 0, tsl = 0;
+    uint64_t tsum = 0;
     if (V.tand && lane < steps) tsum = V.tand[trow + gtile(lane * 4 + wave)];
-    // sub-tile summaries (one order per block): lane 4i + s holds sub-tile s of this wavefront's tile i
-    if (BT == 1 && V.tand && lane < 4 * steps)
-        tsl = V.tsub[(trow + gtile((lane >> 2) * 4 + wave)) * 4 + (lane & 3)];
+    // sub-tile summaries (one order per block): lane i holds the 4 of this wavefront's tile i
+    u64x2 tsl01 = {0ull, 0ull}, tsl23 = {0ull, 0ull};
+    if (BT == 1 && V.tand && lane < steps) {
+        const u64x2 *tp = reinterpret_cast<const u64x2 *>(V.tsub + (trow + gtile(lane * 4 + wave)) * 4);
+        tsl01 = tp[0];
+        tsl23 = tp[1];
+    }
 
     for (int j = wave; j < BT; j += kScoreThreads / 64) {
         uint64_t np = ~0ull;   // no order in this slot: nothing is consistent
@@ -469,10 +470,12 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     __syncthreads();
     uint64_t npred[BT];
     Acc a[BT];
+    float tt[BT];        // fold_shift(a[j].best), kept by acc_fold4
 #pragma unroll
     for (int j = 0; j < BT; ++j) {
         npred[j] = uniform_u64(s_npred[j]);
         acc_init(a[j]);
+        tt[j] = fold_shift(-INFINITY);
     }
 
     const u64x2 *mp = reinterpret_cast<const u64x2 *>(V.masks + row);
@@ -503,8 +506,8 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         const uint64_t bal = __ballot(m != 0u);
         if (m != 0u) {
             const int pos = __popcll(bal & ((1ull << lane) - 1ull));
-            s_tile[wave][pos] = lane * 4 + wave;             // local index
-            s_tneed[wave][pos] = m;
+            s_tile[wave][pos] = (int)gtile(lane * 4 + wave);  // the tile's index in the row
+            s_tneed[wave][pos] = m | ((uint32_t)lane << 8);   // the orders that need it, and its step
         }
         if (lane == 0) s_ntile[wave] = __popcll(bal);
     }
@@ -514,17 +517,22 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     // can use its 64-entry sub-tile; otherwise its masks read as ~0 (consistent
     // with nothing), so the fold is unchanged and the sub-tile's bytes are not
     // fetched.  (With several orders the union rarely skips a sub-tile and the
-    // test costs more than it saves.)  Lane 4 i + s holds the summary of
-    // sub-tile s of the wavefront's i-th step tile, so one ballot gives every
-    // lane its bits: bit 4 i + s of `sub_ok` (the same in all lanes).
-    uint64_t sub_ok = ~0ull;
-    if (BT == 1 && V.tand) sub_ok = __ballot(lane < 4 * steps && (tsl & npred[0]) == 0ull);
-    const int my_sub = lane >> 4;
-    // This lane's 4-entry group of local tile tk, as an index into the node's
-    // row of groups (below 2^30: rows hold fewer than 2^32 entries).
-    auto group_of = [&](int tk) -> uint32_t {
-        return ((uint32_t)(chunk + (tk >> 2) * chunks) << 8) | ((uint32_t)(tk & 3) << 6) | (uint32_t)lane;
-    };
+    // test costs more than it saves.)  Lane i holds the summaries of the
+    // wavefront's i-th step tile, so four ballots give, for each sub-tile s,
+    // the tiles whose sub-tile s is needed; a lane reads sub-tile lane / 16 of
+    // every tile, so it keeps that ballot: bit i of `my_ok`.
+    uint64_t my_ok = ~0ull;
+    if (BT == 1 && V.tand) {
+        const uint64_t np0 = npred[0];
+        const uint64_t b0 = __ballot(lane < steps && (tsl01.x & np0) == 0ull);
+        const uint64_t b1 = __ballot(lane < steps && (tsl01.y & np0) == 0ull);
+        const uint64_t b2 = __ballot(lane < steps && (tsl23.x & np0) == 0ull);
+        const uint64_t b3 = __ballot(lane < steps && (tsl23.y & np0) == 0ull);
+        const int my_sub = lane >> 4;
+        my_ok = my_sub == 0 ? b0 : (my_sub == 1 ? b1 : (my_sub == 2 ? b2 : b3));
+    }
+    // This lane's 4-entry group of the tile with row index gt, as an index into
+    // the node's row of groups (below 2^30: rows hold fewer than 2^32 entries).
     // Prefetch ring over this wavefront's needed tiles: while the tile in
     // slot d is folded, the loads of the next D - 1 tiles are in flight; the
     // slot is refilled (with the tile D places on) right after its fold, and
@@ -535,12 +543,12 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     uint32_t rneed[D];
 #define BNOS_ISSUE(d, kk)                                                                       \
     if ((kk) < nt) {                                                                            \
-        const int tk_ = s_tile[wave][(kk)];                                                     \
-        const uint32_t q_ = group_of(tk_);                                                      \
-        rneed[d] = s_tneed[wave][(kk)];                                                         \
+        const uint32_t q_ = ((uint32_t)s_tile[wave][(kk)] << 6) | (uint32_t)lane;              \
+        const uint32_t nd_ = s_tneed[wave][(kk)];                                               \
+        rneed[d] = nd_ & 0xffu;                                                                 \
         r01[d] = (u64x2){CM ? dead : ~0ull, ~0ull};                                             \
         r23[d] = (u64x2){~0ull, ~0ull};                                                         \
-        if ((sub_ok >> ((tk_ & ~3) + my_sub)) & 1ull) {                                         \
+        if ((my_ok >> (nd_ >> 8)) & 1ull) {                                                     \
             if (CM) {                                                                           \
                 r01[d].x = __builtin_nontemporal_load(&ap[q_]);                                 \
             } else {                                                                            \
@@ -582,7 +590,12 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
                     any |= ok;
                 }
                 if (__ballot(any) == 0ull) continue;         // uniform: nothing consistent in the wavefront
-                acc_fold4(a[j], xs, mk);
+                if (BT == 1) {
+                    acc_fold4(a[j], tt[j], xs, mk);
+                } else {                                     // registers: recompute the shift
+                    float t = fold_shift(a[j].best);
+                    acc_fold4(a[j], t, xs, mk);
+                }
             }
             BNOS_ISSUE(d, k + D)
         }
@@ -740,17 +753,6 @@ template <int BT, bool CM = false, bool NOSAT = false>
 __global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
 {
     int x, y;
-    if (BT == 1 && A.sched) {
-        // one order, balanced schedule: block x is chunk c of sched_c[p] of the node at position p
-        if (!xcd_block(A.sched_blocks, x, y)) return;
-        const uint32_t e = A.sched[x];
-        const int p = (int)(e >> 16), c = (int)(e & 0xffffu);
-        const int C = A.sched_c[p];
-        const int v = A.orders[p];
-        const int node = (v >= 0 && v < A.n) ? v : p;
-        score_block<BT, CM, NOSAT>(view_of(A), node, c, 0, C, (A.row_steps - c + C - 1) / C);
-        return;
-    }
     if (!xcd_block((int64_t)A.n * A.chunks, x, y)) return;
     int node = x / A.chunks;
     const int chunk = x - node * A.chunks;
@@ -840,10 +842,8 @@ struct MergeLds {
 // fixed tree (lower wave always the left operand).  The merged state of node
 // node_j is valid in lane j of wave 0.  All threads of the block must call it.
 __device__ __forceinline__ Acc merge_nodes(const Partial *__restrict__ base, int n, int chunks, int node_j,
-                                           MergeLds &L, int nch_j = -1)
+                                           MergeLds &L)
 {
-    // nch_j >= 0: this lane's node has only its first nch_j chunk slots (stride `chunks`)
-    const int lim = nch_j >= 0 ? nch_j : chunks;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     Acc a;
@@ -852,7 +852,7 @@ __device__ __forceinline__ Acc merge_nodes(const Partial *__restrict__ base, int
         const Partial *p = base + node_j;
         int c = wave;
         // four loads in flight per step
-        for (; c + 3 * kMergeWaves < lim; c += 4 * kMergeWaves) {
+        for (; c + 3 * kMergeWaves < chunks; c += 4 * kMergeWaves) {
             const Acc x0 = load_partial(p + (int64_t)c * n);
             const Acc x1 = load_partial(p + (int64_t)(c + kMergeWaves) * n);
             const Acc x2 = load_partial(p + (int64_t)(c + 2 * kMergeWaves) * n);
@@ -862,7 +862,7 @@ __device__ __forceinline__ Acc merge_nodes(const Partial *__restrict__ base, int
             acc_merge(a, x2);
             acc_merge(a, x3);
         }
-        for (; c < lim; c += kMergeWaves) acc_merge(a, load_partial(p + (int64_t)c * n));
+        for (; c < chunks; c += kMergeWaves) acc_merge(a, load_partial(p + (int64_t)c * n));
     }
     if (wave < kMergeWaves) {
         L.m[wave][lane] = a.m;
@@ -906,18 +906,7 @@ __device__ __forceinline__ void merge_block(const ScoreArgs &A, int b, MergeLds 
     // the order's entries are requested first and checked after the merge, so the
     // two loads overlap
     const int v = lane < n ? A.orders[(int64_t)b * n + lane] : -1;
-    int nch = -1;
-    if (A.sched) {
-        // the node's chunk count is that of its position (lane p holds the node at p)
-        __shared__ int s_pos[64];
-        if (threadIdx.x < 64) s_pos[threadIdx.x] = -1;
-        __syncthreads();
-        if (wave == 0 && lane < n && v >= 0 && v < n) s_pos[v] = lane;
-        __syncthreads();
-        const int pos = lane < n ? s_pos[lane] : -1;
-        nch = pos >= 0 ? A.sched_c[pos] : A.chunks;     // an invalid order scores NaN anyway
-    }
-    const Acc r = merge_nodes(A.part + (int64_t)b * A.chunks * n, n, A.chunks, lane < n ? lane : -1, L, nch);
+    const Acc r = merge_nodes(A.part + (int64_t)b * A.chunks * n, n, A.chunks, lane < n ? lane : -1, L);
     valid = order_valid(v, n, lane);
     lse_out = 0.0;
     max_out = 0.0;
@@ -944,6 +933,5 @@ ScoreArgs score_args(const TableT *t, const int32_t *orders, int B, double *lse,
 bnos_status launch_stream(TableT *t, const ScoreArgs &A, hipStream_t st, int bt, bool allow_timing = true);
 bnos_status launch_gather(TableT *t, ScoreArgs &A, hipStream_t st, bool allow_timing = true);
 bnos_status launch_merge(const ScoreArgs &A, hipStream_t st);
-bnos_status build_schedule(TableT *t, int target);
 
 }  // namespace bnos
