@@ -243,3 +243,69 @@ def test_trained_network_gains_over_uniform_swaps(bnos):
     assert res["learned"]["ess"] > 1.05 * res["uniform"]["ess"], res
     m.free()
     t.free()
+
+
+def test_network_trained_across_datasets(bnos):
+    # one network trained on the accepted moves of two datasets of different size
+    # (n=20 and n=28): the loss on each harvest falls below that of uniform pairs,
+    # and the network then drives exact chains on a third, unseen size (n=4)
+    sets = [datagen.WORKLOADS["prior20"], datagen.Workload("x28", 28, 1500, (2, 3), 3, 4, 31, None)]
+    C, iters, cap = 64, 4000, 512
+    feats, pairs = [], []
+    for k, w in enumerate(sets):
+        net, prior = datagen.make(w)
+        t = bnos.build_score_table(net.data, net.arities, w.K, prior=prior)
+        st = t.new_chain_state(C, 1, trace_every=0, harvest_cap=cap)
+        t.run_chains(st, iters, 40 + k, trace_every=0)
+        cnt = st["harvest_count"].cpu().numpy()
+        assert cnt.min() > 0
+        feats.append(torch.cat([st["harvest_feats"][c, :int(min(cnt[c], cap))] for c in range(C)]))
+        pairs.append(torch.cat([st["harvest_pairs"][c, :int(min(cnt[c], cap))] for c in range(C)]))
+        t.free()
+    m = bnos.Mlp()
+    m.set_params(datagen.mlp_params(9, scale=0.5).astype(np.float32))
+    m.fit_norm(torch.cat([f.reshape(-1, 8) for f in feats]).contiguous())
+    g = torch.empty(N_PARAM, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def losses():
+        out = []
+        for f, p in zip(feats, pairs):
+            m.grad(f, p, g, loss)
+            out.append(loss.item())
+        return out
+
+    before = losses()
+    for ep in range(10):
+        for k in range(len(sets)):
+            m.train(feats[k], pairs[k], epochs=1, batch=512, lr=2e-3, seed=100 * ep + k)
+    after = losses()
+    for w, b, a in zip(sets, before, after):
+        uniform_loss = np.log(w.n * (w.n - 1) / 2)
+        assert a < b, (w.name, b, a)
+        assert a < uniform_loss - 0.05, (w.name, a, uniform_loss)
+    # exactness on an unseen size: the visiting frequencies of the q-corrected
+    # chains match the exact order posterior
+    n, K = 4, 3
+    arities = [2, 3, 2, 2]
+    rng = np.random.default_rng(21)
+    data = np.stack([rng.integers(0, a, size=10) for a in arities], axis=1).astype(np.int8)
+    t = bnos.build_score_table(data, arities, K)
+    orc = oracle.build_table(data, arities, K)
+    orders = list(itertools.permutations(range(n)))
+    sc = np.array([oracle.score_order(orc, K, o)[0] for o in orders])
+    post = np.exp(sc - sc.max())
+    post /= post.sum()
+    C2 = 32768
+    st = t.new_chain_state(C2, 300, trace_every=300)
+    t.run_chains(st, 300, seed=77, mlp=m, eps=0.1, trace_every=300)
+    fin = st["orders"].cpu().numpy()
+    idx = {o: k for k, o in enumerate(orders)}
+    freq = np.zeros(len(orders))
+    for row in fin:
+        freq[idx[tuple(int(v) for v in row)]] += 1
+    freq /= C2
+    tv = 0.5 * np.abs(freq - post).sum()
+    assert tv < 0.03, tv
+    m.free()
+    t.free()
