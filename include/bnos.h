@@ -433,6 +433,24 @@ bnos_status bnos_table_timing(bnos_table t, int32_t enable);
 bnos_status bnos_table_tile_skip(bnos_table t, int32_t enable);
 
 /*
+ * Score bound (on by default; acts with tile skipping on): in a launch of one
+ * order per block, every block first bounds from below the best and the
+ * second-best score among the entries of its node that the order can use
+ * (Sec. III.B, Eq. (3)-(6)), from entries it can locate without a search: the
+ * empty set, the singletons of the node's predecessors, and up to 192 top
+ * entries of the row listed at build (sets of two or more members).  It then
+ * skips every tile whose largest score (kept per 256-entry tile at build) lies
+ * below the second-best bound and 60 nats below the best bound.  Such a tile
+ * holds neither the argmax nor the second best, and every one of its terms in
+ * the node's log-sum-exp is below e^-60 times the largest term, so the sum
+ * changes by less than 2^-60 of itself at n <= 64 (far below FP32 rounding):
+ * the max score, the best parent sets and the second best are unchanged, and
+ * the log-sum-exp is the same up to that bound (bitwise, in every case tested).
+ * Launches of several orders per block and chain sweeps do not use it.
+ */
+bnos_status bnos_table_score_bound(bnos_table t, int32_t enable);
+
+/*
  * Computed masks (on by default): a scoring launch of one order per block
  * does not read the stored masks.  The table keeps, for every 4 entries of a
  * row, the first entry's mask over the node's n - 1 other nodes; the scoring

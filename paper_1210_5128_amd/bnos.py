@@ -81,6 +81,7 @@ _SIGS = {
     "bnos_mlp_train": (i32, [P, P, P, i64, i32, ctypes.c_float, i32, i32, ctypes.c_float, ctypes.c_uint64, P, P]),
     "bnos_table_timing": (i32, [P, i32]),
     "bnos_table_tile_skip": (i32, [P, i32]),
+    "bnos_table_score_bound": (i32, [P, i32]),
     "bnos_table_computed_masks": (i32, [P, i32]),
     "bnos_table_count_tiles": (i32, [P, P, i32, P, P]),
     "bnos_table_autotune": (i32, [P, P, i32, i32, P, P, P, P, P]),
@@ -288,6 +289,9 @@ class Table:
 
     def tile_skip(self, enable: bool):
         _check(_lib.bnos_table_tile_skip(self._h, int(enable)))
+
+    def score_bound(self, enable: bool):
+        _check(_lib.bnos_table_score_bound(self._h, int(enable)))
 
     def computed_masks(self, enable: bool):
         """One-order launches compute the masks from per-4-entry anchors (bnos_table_computed_masks)."""

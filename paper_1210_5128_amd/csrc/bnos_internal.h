@@ -23,6 +23,18 @@ constexpr int kScoreThreads = 256;
 constexpr int kEntriesPerStep = 1024;
 constexpr int kMaxStepsPerChunk = 16;
 
+// Score bound of the one-order pass: a block first takes lower bounds on the
+// best and the second-best consistent entry of its node from entries it knows
+// the order can use (the empty set, the singletons of the predecessors, and
+// kBoundCands listed top entries of the row with two or more members), then
+// leaves out every tile whose largest score is below both the second-best
+// bound and the best bound minus kBoundGap nats.  Such a tile holds neither
+// the argmax nor the second best, and each of its terms is below e^-60 of the
+// largest term of the node's sum.
+constexpr int kBoundCands = 192;
+constexpr int kBoundSlots = 64 + kBoundCands;   // per node: slot s < 63 {slot s}, 63 the empty set, then the list
+constexpr float kBoundGap = 60.0f;
+
 // Partial-reduction record written by each scoring block (one per order).
 struct Partial {
     float m, s;          // running max and sum of exp(x - m) over consistent entries
@@ -55,6 +67,10 @@ struct TableT {
     bool tile_skip = true;
     uint64_t *d_anchor = nullptr;   // [n * S_pad / 4]: slot-space mask of every 4th entry
     bool computed_masks = true;     // one-order blocks compute masks from the anchors
+    float *d_tmax = nullptr;        // [n * S_pad / 256]: largest score of each tile
+    uint64_t *d_cmask = nullptr;    // [n][kBoundSlots]: bound candidates (node-space mask; ~0 for none)
+    float *d_cscore = nullptr;      // [n][kBoundSlots]: their scores (-inf for none)
+    bool score_bound = true;        // one-order blocks skip tiles by the score bound
 
     // order-scoring workspace: per (order, node, chunk) partial reductions
     void *d_part = nullptr;

@@ -47,7 +47,7 @@ int64_t TableT::device_bytes() const
     return (int64_t)n * S_pad * (int64_t)(sizeof(uint64_t) + sizeof(float)) + (int64_t)n * N_pad +
            (int64_t)n * (int64_t)(sizeof(int32_t) + n * sizeof(double) + 5 * sizeof(double)) + 64 * 8 * 8 +
            part_bytes + (int64_t)n * (S_pad / 256) * 8 + (int64_t)n * (S_pad / 64) * 8 +
-           (int64_t)n * (S_pad / 4) * 8;
+           (int64_t)n * (S_pad / 4) * 8 + (int64_t)n * (S_pad / 256) * 4 + (int64_t)n * kBoundSlots * 12;
 }
 
 // ------------------------------------------------------------------ device helpers
@@ -526,22 +526,122 @@ __global__ __launch_bounds__(1024) void k_node_stats(const float *__restrict__ s
     }
 }
 
-// AND of the masks of every 256-entry tile (one wavefront per tile).
-__global__ __launch_bounds__(256) void k_tile_and(const uint64_t *__restrict__ masks, int64_t tiles,
-                                                  uint64_t *__restrict__ tand, uint64_t *__restrict__ tsub)
+// AND of the masks of every 256-entry tile and of its four 64-entry sub-tiles,
+// and the tile's largest score (one wavefront per tile).
+__global__ __launch_bounds__(256) void k_tile_and(const uint64_t *__restrict__ masks,
+                                                  const float *__restrict__ scores, int64_t tiles,
+                                                  uint64_t *__restrict__ tand, uint64_t *__restrict__ tsub,
+                                                  float *__restrict__ tmax)
 {
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (tile >= tiles) return;                       // uniform per wavefront
     const uint64_t *p = masks + tile * 256 + lane * 4;
+    const float *q = scores + tile * 256 + lane * 4;
     uint64_t v = p[0] & p[1] & p[2] & p[3];
+    float x = fmaxf(fmaxf(q[0], q[1]), fmaxf(q[2], q[3]));
     // lanes 16s .. 16s+15 hold sub-tile s (entries 64s .. 64s+63)
 #pragma unroll
     for (int off = 1; off <= 8; off <<= 1) v &= (uint64_t)__shfl_xor((unsigned long long)v, off, 64);
     if ((lane & 15) == 0) tsub[tile * 4 + (lane >> 4)] = v;
 #pragma unroll
     for (int off = 16; off <= 32; off <<= 1) v &= (uint64_t)__shfl_xor((unsigned long long)v, off, 64);
-    if (lane == 0) tand[tile] = v;
+#pragma unroll
+    for (int off = 1; off <= 32; off <<= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
+    if (lane == 0) {
+        tand[tile] = v;
+        tmax[tile] = x;
+    }
+}
+
+// Index in a row of the singleton {slot s}: every mask below 1 << s, i.e.
+// every set of at most K slots below s, comes first.
+__device__ __forceinline__ int64_t singleton_index(int s, int K)
+{
+    int64_t c = 1, tot = 1;
+    for (int k = 1; k <= K; ++k) {
+        c = c * (s - k + 1) / k;
+        tot += c;
+    }
+    return tot;
+}
+
+// The score bound's candidates of each row (one block per node), in
+// kBoundSlots slots: slot s < n - 1 the singleton of slot s (K >= 1), slot 63
+// the empty set, then the listed top entries: with M the row's largest score
+// among the sets of two or more members, the entries of those sets within b
+// quarter-nats of M, for the largest b that keeps them to at most
+// kBoundCands.  Unused slots hold (~0, -inf), which no order can use.  The
+// list's order is that of the appends and does not matter: only the entries'
+// values are used.
+constexpr int kBoundBins = 1024;
+__global__ __launch_bounds__(1024) void k_bound_cands(const uint64_t *__restrict__ masks,
+                                                      const float *__restrict__ scores, int n, int K, int64_t S,
+                                                      int64_t S_pad, uint64_t *__restrict__ cmask,
+                                                      float *__restrict__ cscore)
+{
+    __shared__ float s_max[1024 / 64];
+    __shared__ unsigned s_hist[kBoundBins];
+    __shared__ unsigned s_cut, s_cnt;
+    const int node = blockIdx.x;
+    const int tid = threadIdx.x;
+    const uint64_t *mr = masks + (int64_t)node * S_pad;
+    const float *sr = scores + (int64_t)node * S_pad;
+    float mx = -INFINITY;
+    for (int64_t e = tid; e < S; e += 1024)
+        if (__popcll(mr[e]) >= 2) mx = fmaxf(mx, sr[e]);
+#pragma unroll
+    for (int off = 1; off <= 32; off <<= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    if ((tid & 63) == 0) s_max[tid >> 6] = mx;
+    for (int i = tid; i < kBoundBins; i += 1024) s_hist[i] = 0u;
+    __syncthreads();
+    float M = s_max[0];
+    for (int w = 1; w < 1024 / 64; ++w) M = fmaxf(M, s_max[w]);
+    for (int64_t e = tid; e < S; e += 1024) {
+        if (__popcll(mr[e]) < 2) continue;
+        const float d = (M - sr[e]) * 4.0f;
+        if (d < (float)kBoundBins) atomicAdd(&s_hist[(int)d], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        unsigned acc = 0u;
+        int b = 0;
+        while (b < kBoundBins && acc + s_hist[b] <= (unsigned)kBoundCands) acc += s_hist[b++];
+        s_cut = (unsigned)b;
+        s_cnt = 0u;
+    }
+    __syncthreads();
+    const float cut = (float)s_cut;
+    if (tid < 64) {
+        uint64_t fm = ~0ull;
+        float fx = -INFINITY;
+        if (tid == 63) {
+            fm = 0ull;
+            fx = sr[0];
+        } else if (tid < n - 1 && K >= 1) {
+            fm = 1ull << (tid < node ? tid : tid + 1);
+            fx = sr[singleton_index(tid, K)];
+        }
+        cmask[(int64_t)node * kBoundSlots + tid] = fm;
+        cscore[(int64_t)node * kBoundSlots + tid] = fx;
+    }
+    uint64_t *cm = cmask + (int64_t)node * kBoundSlots + 64;
+    float *cs = cscore + (int64_t)node * kBoundSlots + 64;
+    for (int64_t e = tid; e < S; e += 1024) {
+        const uint64_t m = mr[e];
+        if (__popcll(m) < 2) continue;
+        const float x = sr[e];
+        if ((M - x) * 4.0f < cut) {
+            const unsigned k = atomicAdd(&s_cnt, 1u);
+            cm[k] = m;
+            cs[k] = x;
+        }
+    }
+    __syncthreads();
+    for (int k = (int)s_cnt + tid; k < kBoundCands; k += 1024) {
+        cm[k] = ~0ull;
+        cs[k] = -INFINITY;
+    }
 }
 
 // The slot-space mask (the node's own bit removed: slot s is node s below the
@@ -683,6 +783,9 @@ static void free_device(TableT *t)
     hipFree(t->d_tand);
     hipFree(t->d_tsub);
     hipFree(t->d_anchor);
+    hipFree(t->d_tmax);
+    hipFree(t->d_cmask);
+    hipFree(t->d_cscore);
     hipFree(t->d_part);
     for (auto e : t->ev_start) hipEventDestroy(e);
     for (auto e : t->ev_stop) hipEventDestroy(e);
@@ -827,6 +930,9 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     ALLOC(t->d_tand, sizeof(uint64_t) * (size_t)n * (t->S_pad / 256));
     ALLOC(t->d_tsub, sizeof(uint64_t) * (size_t)n * (t->S_pad / 64));
     ALLOC(t->d_anchor, sizeof(uint64_t) * (size_t)n * (t->S_pad / 4));
+    ALLOC(t->d_tmax, sizeof(float) * (size_t)n * (t->S_pad / 256));
+    ALLOC(t->d_cmask, sizeof(uint64_t) * (size_t)n * kBoundSlots);
+    ALLOC(t->d_cscore, sizeof(float) * (size_t)n * kBoundSlots);
 #undef ALLOC
     int8_t *d_rows = nullptr;
     float *d_prior_in = nullptr;
@@ -912,8 +1018,11 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     CK(hipGetLastError());
     {
         const int64_t tiles = (int64_t)n * (t->S_pad / 256);
-        hipLaunchKernelGGL(k_tile_and, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, t->d_masks, tiles,
-                           t->d_tand, t->d_tsub);
+        hipLaunchKernelGGL(k_tile_and, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, t->d_masks,
+                           t->d_scores, tiles, t->d_tand, t->d_tsub, t->d_tmax);
+        CK(hipGetLastError());
+        hipLaunchKernelGGL(k_bound_cands, dim3(n), dim3(1024), 0, st, t->d_masks, t->d_scores, n, K, t->S,
+                           t->S_pad, t->d_cmask, t->d_cscore);
         CK(hipGetLastError());
         const int64_t groups = (int64_t)n * (t->S_pad / 4);
         hipLaunchKernelGGL(k_anchor, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, st, t->d_masks, n,

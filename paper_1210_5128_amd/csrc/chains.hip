@@ -668,6 +668,9 @@ static bnos_status run_chains_impl(const bnos_table *hs, int32_t T, const bnos_c
         V.tand = t->tile_skip ? t->d_tand : nullptr;
         V.tsub = t->d_tsub;
         V.anchor = nullptr;            // chain blocks read the stored masks
+        V.tmax = nullptr;              // and fold every needed tile
+        V.cmask = nullptr;
+        V.cscore = nullptr;
         V.K = t->K;
         blk_base[k + 1] = blk_base[k] + (int64_t)n * V.chunks;
         chain_base[k + 1] = chain_base[k] + C;

@@ -232,8 +232,19 @@ ScoreArgs score_args(const TableT *t, const int32_t *orders, int B, double *lse,
     A.tand = t->tile_skip ? t->d_tand : nullptr;
     A.tsub = t->d_tsub;
     A.anchor = t->computed_masks ? t->d_anchor : nullptr;
+    const bool bound = t->score_bound && t->tile_skip;
+    A.tmax = bound ? t->d_tmax : nullptr;
+    A.cmask = bound ? t->d_cmask : nullptr;
+    A.cscore = bound ? t->d_cscore : nullptr;
     A.K = t->K;
     return A;
+}
+
+template <void (*KERNEL)(ScoreArgs)>
+static void launch_one(dim3 grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1, const ScoreArgs &A)
+{
+    if (e0) hipExtLaunchKernelGGL(KERNEL, grid, dim3(kScoreThreads), 0, st, e0, e1, 0, A);
+    else hipLaunchKernelGGL(KERNEL, grid, dim3(kScoreThreads), 0, st, A);
 }
 
 // With events, they take the kernel's own start and end (hipExtLaunchKernel),
@@ -244,15 +255,18 @@ static void launch_bt(const ScoreArgs &A, int nblocks_x, hipStream_t st, hipEven
     nblocks_x = (nblocks_x + kXcds - 1) / kXcds * kXcds;      // padded for xcd_block
     dim3 grid((unsigned)nblocks_x, (unsigned)((A.B + BT - 1) / BT));
     // without the saturation test when three steps cannot pass 2^64 (with K = 1 a step from
-    // a single slot doubles the mask)
+    // a single slot doubles the mask); with tile skipping a wavefront folds few tiles and waits
+    // on their loads, so six are kept in flight, while the full scan streams the row and keeps
+    // three (fewer registers, more wavefronts resident)
+    const bool deep = A.tand != nullptr;
     if (BT == 1 && A.anchor && ((A.K >= 2 && A.n <= 63) || (A.K == 1 && A.n <= 61))) {
-        if (e0) hipExtLaunchKernelGGL((k_score<1, true, true>), grid, dim3(kScoreThreads), 0, st, e0, e1, 0, A);
-        else hipLaunchKernelGGL((k_score<1, true, true>), grid, dim3(kScoreThreads), 0, st, A);
+        if (deep) launch_one<k_score<1, true, true, 6>>(grid, st, e0, e1, A);
+        else launch_one<k_score<1, true, true, 3>>(grid, st, e0, e1, A);
         return;
     }
     if (BT == 1 && A.anchor) {
-        if (e0) hipExtLaunchKernelGGL((k_score<1, true>), grid, dim3(kScoreThreads), 0, st, e0, e1, 0, A);
-        else hipLaunchKernelGGL((k_score<1, true>), grid, dim3(kScoreThreads), 0, st, A);
+        if (deep) launch_one<k_score<1, true, false, 6>>(grid, st, e0, e1, A);
+        else launch_one<k_score<1, true, false, 3>>(grid, st, e0, e1, A);
         return;
     }
     if (e0) hipExtLaunchKernelGGL(k_score<BT>, grid, dim3(kScoreThreads), 0, st, e0, e1, 0, A);
@@ -436,6 +450,14 @@ extern "C" bnos_status bnos_table_tile_skip(bnos_table h, int32_t enable)
     TableT *t = reinterpret_cast<TableT *>(h);
     if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
     t->tile_skip = enable != 0;
+    return BNOS_OK;
+}
+
+extern "C" bnos_status bnos_table_score_bound(bnos_table h, int32_t enable)
+{
+    TableT *t = reinterpret_cast<TableT *>(h);
+    if (!handle_live(t)) { set_error("invalid table handle"); return BNOS_E_STATE; }
+    t->score_bound = enable != 0;
     return BNOS_OK;
 }
 

@@ -111,11 +111,11 @@ __device__ __forceinline__ void acc_push(Acc &a, float x, uint64_t mk)
 // that sees its entries in ascending mask order (the streaming pass: a row
 // lists the masks in ascending order and a lane visits its groups in row
 // order).  x[e] is the entry's score if consistent, else -inf; mk[e] its mask.
-// The log-sum-exp max is the top-1 score, so one comparison serves both: the
-// rare group that beats the lane's best rescales the sum and takes the new
-// argmax (the first entry holding the group's max, i.e. the smallest mask among
+// The log-sum-exp max is the top-1 score, so one comparison serves both: a
+// group that beats the lane's best rescales the sum and takes the new argmax
+// (the first entry holding the group's max, i.e. the smallest mask among
 // equal scores -- earlier groups hold smaller masks, so an equal score never
-// replaces the held best); every other group adds its exp terms and raises the
+// replaces the held best); any other group adds its exp terms and raises the
 // second best.  Each term is 2^fl(x log2e - t), t = fl(best log2e): one fma and
 // one v_exp_f32 per entry.  Against the exact 2^((x - best) log2e) every term
 // carries the same factor 2^(best log2e - t), t's rounding residual, which
@@ -145,6 +145,36 @@ __device__ __forceinline__ void acc_fold4(Acc &a, float &t, const float (&x)[4],
         a.best = b;
         a.bm = i == 0 ? mk[0] : (i == 1 ? mk[1] : (i == 2 ? mk[2] : mk[3]));
     }
+    const float e0 = __builtin_amdgcn_exp2f(fmaf(x[0], kLog2e, -t)), e1 = __builtin_amdgcn_exp2f(fmaf(x[1], kLog2e, -t));
+    const float e2 = __builtin_amdgcn_exp2f(fmaf(x[2], kLog2e, -t)), e3 = __builtin_amdgcn_exp2f(fmaf(x[3], kLog2e, -t));
+    a.s += (e0 + e1) + (e2 + e3);
+}
+
+// The same fold with both updates formed and one selected, no branch: for one
+// order per block with computed masks, where some lane of a wavefront nearly
+// always takes the first (results bitwise those of acc_fold4; it needs more
+// registers, which the blocks that read stored masks cannot spare).
+__device__ __forceinline__ void acc_fold4_sel(Acc &a, float &t, const float (&x)[4], const uint64_t (&mk)[4])
+{
+#pragma clang fp contract(off)     // t_old - t_new must subtract the two rounded shifts
+    uint64_t k0 = mk[0], k1 = mk[1], k2 = mk[2], k3 = mk[3];
+    asm volatile("" : "+v"(k0), "+v"(k1), "+v"(k2), "+v"(k3));   // keep the masks in registers
+    const float m01 = fmaxf(x[0], x[1]), n01 = fminf(x[0], x[1]);
+    const float m23 = fmaxf(x[2], x[3]), n23 = fminf(x[2], x[3]);
+    const float b = fmaxf(m01, m23);
+    const float o = fmaxf(fminf(m01, m23), fmaxf(n01, n23));
+    uint64_t bmk = k3;
+    bmk = x[2] == b ? k2 : bmk;
+    bmk = x[1] == b ? k1 : bmk;
+    bmk = x[0] == b ? k0 : bmk;
+    const bool nb = b > a.best;
+    const float tn = b * kLog2e;
+    const float r = __builtin_amdgcn_exp2f(t - tn);
+    a.s = nb ? a.s * r : a.s;
+    t = nb ? tn : t;
+    a.sec = nb ? fmaxf(a.best, o) : fmaxf(a.sec, b);
+    a.bm = nb ? bmk : a.bm;
+    a.best = nb ? b : a.best;
     const float e0 = __builtin_amdgcn_exp2f(fmaf(x[0], kLog2e, -t)), e1 = __builtin_amdgcn_exp2f(fmaf(x[1], kLog2e, -t));
     const float e2 = __builtin_amdgcn_exp2f(fmaf(x[2], kLog2e, -t)), e3 = __builtin_amdgcn_exp2f(fmaf(x[3], kLog2e, -t));
     a.s += (e0 + e1) + (e2 + e3);
@@ -347,6 +377,9 @@ struct ScoreArgs {
     const uint64_t *tand;      // tile summaries, or null
     const uint64_t *tsub;      // sub-tile summaries (with tand)
     const uint64_t *anchor;    // first mask of every 4 entries in slot space, or null
+    const float *tmax;         // largest score of each tile (with tand, one order per block), or null
+    const uint64_t *cmask;     // [n][kBoundSlots] score-bound candidates of each row (with tmax)
+    const float *cscore;
     int K;
 };
 
@@ -364,6 +397,9 @@ struct TabView {
     const uint64_t *tand;       // [n * S_pad / 256] AND of each 256-entry tile's masks, or null (no skipping)
     const uint64_t *tsub;       // [n * S_pad / 64] the same per 64-entry sub-tile (with tand)
     const uint64_t *anchor;     // [n * S_pad / 4] slot-space first mask of each 4-entry group (computed masks)
+    const float *tmax;          // [n * S_pad / 256] largest score of each tile, or null (no score bound)
+    const uint64_t *cmask;      // [n][kBoundSlots] score-bound candidates of each row (with tmax)
+    const float *cscore;
     int K;
 };
 
@@ -405,6 +441,59 @@ __device__ __forceinline__ uint64_t to_nodes(uint64_t s, int node)
     return (s & low) | ((s & ~low) << 1);
 }
 
+// ---- score bound (one order per block)
+//
+// A block takes lower bounds on the best and the second-best score among the
+// entries its order can use, from candidates kept per row at build (lane l of
+// wavefront w holds slot 64 w + l): the singleton of slot s (usable if that
+// node precedes), the empty set (always usable) and the row's listed top
+// entries of two or more members.  The candidates are distinct entries, so the
+// largest usable one bounds the best from below and the second largest the
+// second best.  A tile whose largest score is below both the second-best bound
+// and the best bound minus kBoundGap holds neither result and only terms below
+// e^-kBoundGap of the largest one; the block leaves it out.
+
+// This lane's candidate (score, node-space mask); requested before the order
+// is read so that the loads overlap.
+__device__ __forceinline__ void bound_candidate(const TabView &V, int node, int wave, int lane, float &cv,
+                                                uint64_t &cm)
+{
+    static_assert(kBoundSlots == kScoreThreads, "one candidate per thread of a scoring block");
+    const int64_t c = (int64_t)node * kBoundSlots + wave * 64 + lane;
+    cv = V.cscore[c];
+    cm = V.cmask[c];
+}
+
+// The score below which a tile is left out, for predecessor complement np
+// (node space).  Every thread of the block calls it (it holds a barrier).
+__device__ __forceinline__ float bound_cut(float cv, uint64_t cm, uint64_t np, int wave, int lane,
+                                           float (&s_lb)[kScoreThreads / 64][2])
+{
+    const float v = ((cm & np) == 0ull) ? cv : -INFINITY;
+    const float m1 = wave_max_f32(v);
+    const uint64_t at = __ballot(v == m1);
+    const int l1 = at ? __builtin_ctzll(at) : 64;
+    const float m2 = wave_max_f32(lane == l1 ? -INFINITY : v);
+    if (lane == 0) {
+        s_lb[wave][0] = m1;
+        s_lb[wave][1] = m2;
+    }
+    __syncthreads();
+    float b = s_lb[0][0];
+    int wb = 0;
+#pragma unroll
+    for (int w = 1; w < kScoreThreads / 64; ++w)
+        if (s_lb[w][0] > b) {
+            b = s_lb[w][0];
+            wb = w;
+        }
+    float sec = s_lb[wb][1];
+#pragma unroll
+    for (int w = 0; w < kScoreThreads / 64; ++w)
+        if (w != wb) sec = fmaxf(sec, s_lb[w][0]);
+    return fminf(b - kBoundGap, sec);
+}
+
 // One block streams chunk `chunk` of node `node`'s entries once and folds
 // each entry into BT order states (group `group` of the batch, or of the node's
 // work list); it writes one Partial per order.
@@ -416,7 +505,7 @@ __device__ __forceinline__ uint64_t to_nodes(uint64_t s, int node)
 // The states and partials are bitwise those of reading the stored masks, for
 // 6 bytes per entry read instead of 12.  NOSAT steps without the saturation
 // test where next_mask_nosat allows it.
-template <int BT, bool CM = false, bool NOSAT = false>
+template <int BT, bool CM = false, bool NOSAT = false, int RING = 0>
 __device__ __forceinline__ void score_block(const TabView &V, int node, int chunk, int group, int chunks,
                                             int steps)
 {
@@ -452,8 +541,19 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         tsl01 = tp[0];
         tsl23 = tp[1];
     }
+    // score bound (one order per block): lane i's tile maximum and this lane's candidate
+    const bool bound = BT == 1 && V.tmax != nullptr && V.tand != nullptr;
+    __shared__ float s_lb[kScoreThreads / 64][2];
+    float tmx = 0.f, cv = -INFINITY;
+    uint64_t cm = ~0ull;
+    if (bound) {
+        if (lane < steps) tmx = V.tmax[trow + gtile(lane * 4 + wave)];
+        bound_candidate(V, node, wave, lane, cv, cm);
+    }
 
-    for (int j = wave; j < BT; j += kScoreThreads / 64) {
+    // with the bound every wavefront forms the predecessor set itself
+    uint64_t np_w = ~0ull;
+    for (int j = bound ? 0 : wave; j < BT; j += kScoreThreads / 64) {
         uint64_t np = ~0ull;   // no order in this slot: nothing is consistent
         int ob = -1;
         if (b0 + j < count) {
@@ -462,12 +562,15 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
             uint64_t pred = wave_pred(V.orders + (int64_t)ob * n, n, node, lane, valid);
             np = ~pred;        // invalid order: only the empty set is consistent
         }
-        if (lane == 0) {
+        if (lane == 0 && (!bound || wave == 0)) {
             s_npred[j] = np;
             s_ord[j] = ob;
         }
+        np_w = np;
     }
-    __syncthreads();
+    float cut = -INFINITY;     // tiles whose largest score is below this are left out
+    if (bound) cut = bound_cut(cv, cm, np_w, wave, lane, s_lb);   // holds the block barrier
+    else __syncthreads();
     uint64_t npred[BT];
     Acc a[BT];
     float tt[BT];        // fold_shift(a[j].best), kept by acc_fold4
@@ -499,6 +602,7 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
             if (V.tand) {
 #pragma unroll
                 for (int j = 0; j < BT; ++j) m |= ((tsum & npred[j]) == 0ull) ? (1u << j) : 0u;
+                if (bound && tmx < cut) m = 0u;
             } else {
                 m = (1u << BT) - 1u;
             }
@@ -537,7 +641,9 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     // slot d is folded, the loads of the next D - 1 tiles are in flight; the
     // slot is refilled (with the tile D places on) right after its fold, and
     // the loop is unrolled by D so that every slot keeps its own registers.
-    constexpr int D = (BT == 1) ? 3 : 2;
+    // RING > 0 fixes the depth; by default three slots with one order per
+    // block and two with several.
+    constexpr int D = RING > 0 ? RING : ((BT == 1) ? 3 : 2);
     u64x2 r01[D], r23[D];
     f32x4 rsc[D];
     uint32_t rneed[D];
@@ -590,7 +696,9 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
                     any |= ok;
                 }
                 if (__ballot(any) == 0ull) continue;         // uniform: nothing consistent in the wavefront
-                if (BT == 1) {
+                if (BT == 1 && CM) {
+                    acc_fold4_sel(a[j], tt[j], xs, mk);
+                } else if (BT == 1) {
                     acc_fold4(a[j], tt[j], xs, mk);
                 } else {                                     // registers: recompute the shift
                     float t = fold_shift(a[j].best);
@@ -671,6 +779,9 @@ __device__ __forceinline__ TabView view_of(const ScoreArgs &A)
     V.tand = A.tand;
     V.tsub = A.tsub;
     V.anchor = A.anchor;
+    V.tmax = A.tmax;
+    V.cmask = A.cmask;
+    V.cscore = A.cscore;
     V.K = A.K;
     return V;
 }
@@ -690,15 +801,25 @@ __global__ __launch_bounds__(kScoreThreads) void k_count_tiles(ScoreArgs A, unsi
     const int wave = threadIdx.x >> 6;
     const int n = A.n;
     const int count = A.B;
-    for (int j = wave; j < BT; j += kScoreThreads / 64) {
+    const TabView V = view_of(A);
+    const bool bound = BT == 1 && A.tmax != nullptr && A.tand != nullptr;
+    __shared__ float s_lb[kScoreThreads / 64][2];
+    float cv = -INFINITY;
+    uint64_t cm = ~0ull;
+    if (bound) bound_candidate(V, node, wave, lane, cv, cm);
+    uint64_t np_w = ~0ull;
+    for (int j = bound ? 0 : wave; j < BT; j += kScoreThreads / 64) {
         uint64_t np = ~0ull;
         if (b0 + j < count) {
             bool valid;
             np = ~wave_pred(A.orders + (int64_t)(b0 + j) * n, n, node, lane, valid);
         }
-        if (lane == 0) s_np[j] = np;
+        if (lane == 0 && (!bound || wave == 0)) s_np[j] = np;
+        np_w = np;
     }
-    __syncthreads();
+    float cut = -INFINITY;
+    if (bound) cut = bound_cut(cv, cm, np_w, wave, lane, s_lb);
+    else __syncthreads();
     const int64_t trow = (int64_t)node * (A.S_pad >> 8);
     const int steps = A.chunk_entries / kEntriesPerStep;
     // 64-entry sub-tiles read: of the needed tiles, those the order can use (one
@@ -710,6 +831,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_count_tiles(ScoreArgs A, unsi
             const uint64_t sm = A.tand[tile];
             bool any = false;
             for (int j = 0; j < BT; ++j) any |= (sm & s_np[j]) == 0ull;
+            if (bound && A.tmax[tile] < cut) any = false;
             if (!any) continue;
             if (BT > 1) {                  // several orders: the whole tile is read
                 c += 4u;
@@ -749,7 +871,7 @@ __device__ __forceinline__ bool xcd_block(int64_t real_x, int &x, int &y)
 // to read, so the longest blocks are dispatched first and the shortest fill
 // the tail.  (An entry that is not a node id keeps the plain mapping; such an
 // order is invalid and scores NaN anyway.)
-template <int BT, bool CM = false, bool NOSAT = false>
+template <int BT, bool CM = false, bool NOSAT = false, int RING = 0>
 __global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
 {
     int x, y;
@@ -760,7 +882,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(ScoreArgs A)
         const int v = A.orders[(int64_t)y * A.n + (A.n - 1 - node)];
         node = (v >= 0 && v < A.n) ? v : node;
     }
-    score_block<BT, CM, NOSAT>(view_of(A), node, chunk, y, A.chunks, A.chunk_entries / kEntriesPerStep);
+    score_block<BT, CM, NOSAT, RING>(view_of(A), node, chunk, y, A.chunks, A.chunk_entries / kEntriesPerStep);
 }
 
 // Index of the segment holding x, for prefix bases base[0] = 0 < ... < base[T].

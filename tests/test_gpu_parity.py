@@ -669,3 +669,67 @@ def test_batched_block_shapes_match_oracle(bnos, prior20, bt):
     finally:
         t.set_launch(11)
     check_orders_against_oracle(got, orc, w.K, orders)
+
+
+def test_score_bound_is_bitwise_identical_on_the_60_node_table(bnos, mixed60):
+    # one order per launch: random orders, the generating DAG's topological order
+    # (every node's best parent sets usable: the bound leaves out most tiles) and
+    # its reverse (no parent usable: the bound is weak); every output bitwise equal
+    # to tile skipping without the bound, and never more tiles read
+    w, net, prior, t = mixed60
+    topo = np.asarray(net.perm, dtype=np.int32)
+    orders = np.concatenate([datagen.random_orders(w.n, 10, seed=501), topo[None], topo[::-1][None]])
+    t.set_launch(1, chunk_steps=16)
+    fewer = 0
+    try:
+        for b in range(orders.shape[0]):
+            o = orders[b:b + 1]
+            t.score_bound(False)
+            plain = dev_score(t, o)
+            n_plain, _ = t.count_tiles(torch.from_numpy(o).cuda())
+            t.score_bound(True)
+            got = dev_score(t, o)
+            n_bound, _ = t.count_tiles(torch.from_numpy(o).cuda())
+            same_bits(got, plain)
+            assert n_bound <= n_plain
+            fewer += n_bound < n_plain
+        # the topological order: most of the table is left out
+        o = topo[None]
+        t.score_bound(False)
+        n_plain, _ = t.count_tiles(torch.from_numpy(o).cuda())
+        t.score_bound(True)
+        n_bound, _ = t.count_tiles(torch.from_numpy(o).cuda())
+        assert n_bound < 0.2 * n_plain, (n_bound, n_plain)
+        assert fewer >= 8
+    finally:
+        t.score_bound(True)
+        t.set_launch(1)
+
+
+@pytest.mark.parametrize("n,K,N,arities", [
+    (8, 3, 200, (2,)), (20, 4, 1000, (3,)), (64, 2, 129, (2,)), (1, 0, 50, (3,)), (12, 0, 40, (2,)),
+    (9, 6, 200, (2,)), (33, 5, 80, (2,)), (61, 1, 80, (2,)), (40, 4, 3000, (2, 3, 4)),
+])
+def test_score_bound_edge_shapes(bnos, n, K, N, arities):
+    # bound on vs off, one order per block, several chunk lengths: bitwise equal,
+    # and equal to the oracle where it is small enough to build
+    net = datagen.random_network(n, N, arities, min(4, n - 1), seed=11 * n + K)
+    t = bnos.build_score_table(net.data, net.arities, K)
+    orc = oracle.build_table(net.data, net.arities, K) if n <= 20 else None
+    try:
+        orders = datagen.random_orders(n, 6, seed=17 + n)
+        orders = np.concatenate([orders, np.asarray(net.perm, dtype=np.int32)[None]])
+        for cs in (1, 4, 16):
+            try:
+                t.set_launch(orders.shape[0], chunk_steps=cs, orders_per_block=1)
+            except bnos.BnosError:       # longer than this table's row padding
+                continue
+            t.score_bound(False)
+            plain = dev_score(t, orders)
+            t.score_bound(True)
+            got = dev_score(t, orders)
+            same_bits(got, plain)
+        if orc is not None:
+            assert check_orders_against_oracle(got, orc, K, orders) == 0
+    finally:
+        t.free()
