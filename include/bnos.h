@@ -433,9 +433,10 @@ bnos_status bnos_table_timing(bnos_table t, int32_t enable);
 bnos_status bnos_table_tile_skip(bnos_table t, int32_t enable);
 
 /*
- * Score bound (on by default; acts with tile skipping on): in a launch of one
- * order per block, every block first bounds from below the best and the
- * second-best score among the entries of its node that the order can use
+ * Score bound (on by default; acts with tile skipping on): every scoring block
+ * (order scoring and chain sweeps) first bounds from below, for each of its
+ * orders, the best and the second-best score among the entries of its node
+ * that the order can use
  * (Sec. III.B, Eq. (3)-(6)), from entries it can locate without a search: the
  * empty set, the singletons of the node's predecessors, and up to 192 top
  * entries of the row listed at build (sets of two or more members).  It then
@@ -446,7 +447,8 @@ bnos_status bnos_table_tile_skip(bnos_table t, int32_t enable);
  * changes by less than 2^-60 of itself at n <= 64 (far below FP32 rounding):
  * the max score, the best parent sets and the second best are unchanged, and
  * the log-sum-exp is the same up to that bound (bitwise, in every case tested).
- * Launches of several orders per block and chain sweeps do not use it.
+ * A block of several orders reads a tile if any of its orders needs it, and
+ * each order folds only the tiles it needs.
  */
 bnos_status bnos_table_score_bound(bnos_table t, int32_t enable);
 

@@ -23,14 +23,14 @@ constexpr int kScoreThreads = 256;
 constexpr int kEntriesPerStep = 1024;
 constexpr int kMaxStepsPerChunk = 16;
 
-// Score bound of the one-order pass: a block first takes lower bounds on the
-// best and the second-best consistent entry of its node from entries it knows
-// the order can use (the empty set, the singletons of the predecessors, and
-// kBoundCands listed top entries of the row with two or more members), then
-// leaves out every tile whose largest score is below both the second-best
-// bound and the best bound minus kBoundGap nats.  Such a tile holds neither
-// the argmax nor the second best, and each of its terms is below e^-60 of the
-// largest term of the node's sum.
+// Score bound of the streaming pass: a block first takes, for each of its
+// orders, lower bounds on the best and the second-best consistent entry of its
+// node from entries it knows the order can use (the empty set, the singletons
+// of the predecessors, and kBoundCands listed top entries of the row with two
+// or more members), then leaves out for that order every tile whose largest
+// score is below both the second-best bound and the best bound minus
+// kBoundGap nats.  Such a tile holds neither the argmax nor the second best,
+// and each of its terms is below e^-60 of the largest term of the node's sum.
 constexpr int kBoundCands = 192;
 constexpr int kBoundSlots = 64 + kBoundCands;   // per node: slot s < 63 {slot s}, 63 the empty set, then the list
 constexpr float kBoundGap = 60.0f;

@@ -668,9 +668,10 @@ static bnos_status run_chains_impl(const bnos_table *hs, int32_t T, const bnos_c
         V.tand = t->tile_skip ? t->d_tand : nullptr;
         V.tsub = t->d_tsub;
         V.anchor = nullptr;            // chain blocks read the stored masks
-        V.tmax = nullptr;              // and fold every needed tile
-        V.cmask = nullptr;
-        V.cscore = nullptr;
+        const bool bound = t->score_bound && t->tile_skip;
+        V.tmax = bound ? t->d_tmax : nullptr;
+        V.cmask = bound ? t->d_cmask : nullptr;
+        V.cscore = bound ? t->d_cscore : nullptr;
         V.K = t->K;
         blk_base[k + 1] = blk_base[k] + (int64_t)n * V.chunks;
         chain_base[k + 1] = chain_base[k] + C;

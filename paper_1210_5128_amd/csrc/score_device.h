@@ -494,6 +494,44 @@ __device__ __forceinline__ float bound_cut(float cv, uint64_t cm, uint64_t np, i
     return fminf(b - kBoundGap, sec);
 }
 
+// The same for the BT orders of a several-order block, after the barrier that
+// published their predecessor complements: every wavefront takes each order's
+// top two usable candidates among its own, and a second barrier combines them.
+template <int BT>
+__device__ __forceinline__ void bound_cuts(float cv, uint64_t cm, const uint64_t (&npred)[BT], int wave, int lane,
+                                           float (&s_lbm)[kScoreThreads / 64][BT][2], float (&cut)[BT])
+{
+#pragma unroll
+    for (int j = 0; j < BT; ++j) {
+        const float v = ((cm & npred[j]) == 0ull) ? cv : -INFINITY;
+        const float m1 = wave_max_f32(v);
+        const uint64_t at = __ballot(v == m1);
+        const int l1 = at ? __builtin_ctzll(at) : 64;
+        const float m2 = wave_max_f32(lane == l1 ? -INFINITY : v);
+        if (lane == 0) {
+            s_lbm[wave][j][0] = m1;
+            s_lbm[wave][j][1] = m2;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < BT; ++j) {
+        float b = s_lbm[0][j][0];
+        int wb = 0;
+#pragma unroll
+        for (int w = 1; w < kScoreThreads / 64; ++w)
+            if (s_lbm[w][j][0] > b) {
+                b = s_lbm[w][j][0];
+                wb = w;
+            }
+        float sec = s_lbm[wb][j][1];
+#pragma unroll
+        for (int w = 0; w < kScoreThreads / 64; ++w)
+            if (w != wb) sec = fmaxf(sec, s_lbm[w][j][0]);
+        cut[j] = fminf(b - kBoundGap, sec);
+    }
+}
+
 // One block streams chunk `chunk` of node `node`'s entries once and folds
 // each entry into BT order states (group `group` of the batch, or of the node's
 // work list); it writes one Partial per order.
@@ -541,9 +579,10 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         tsl01 = tp[0];
         tsl23 = tp[1];
     }
-    // score bound (one order per block): lane i's tile maximum and this lane's candidate
-    const bool bound = BT == 1 && V.tmax != nullptr && V.tand != nullptr;
+    // score bound: lane i's tile maximum and this lane's candidate
+    const bool bound = V.tmax != nullptr && V.tand != nullptr;
     __shared__ float s_lb[kScoreThreads / 64][2];
+    __shared__ float s_lbm[kScoreThreads / 64][BT][2];
     float tmx = 0.f, cv = -INFINITY;
     uint64_t cm = ~0ull;
     if (bound) {
@@ -551,9 +590,10 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         bound_candidate(V, node, wave, lane, cv, cm);
     }
 
-    // with the bound every wavefront forms the predecessor set itself
+    // with the bound and one order, every wavefront forms the predecessor set itself
+    const bool own = BT == 1 && bound;
     uint64_t np_w = ~0ull;
-    for (int j = bound ? 0 : wave; j < BT; j += kScoreThreads / 64) {
+    for (int j = own ? 0 : wave; j < BT; j += kScoreThreads / 64) {
         uint64_t np = ~0ull;   // no order in this slot: nothing is consistent
         int ob = -1;
         if (b0 + j < count) {
@@ -562,14 +602,17 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
             uint64_t pred = wave_pred(V.orders + (int64_t)ob * n, n, node, lane, valid);
             np = ~pred;        // invalid order: only the empty set is consistent
         }
-        if (lane == 0 && (!bound || wave == 0)) {
+        if (lane == 0 && (!own || wave == 0)) {
             s_npred[j] = np;
             s_ord[j] = ob;
         }
         np_w = np;
     }
-    float cut = -INFINITY;     // tiles whose largest score is below this are left out
-    if (bound) cut = bound_cut(cv, cm, np_w, wave, lane, s_lb);   // holds the block barrier
+    // tiles whose largest score is below cut[j] are left out for order j
+    float cut[BT];
+#pragma unroll
+    for (int j = 0; j < BT; ++j) cut[j] = -INFINITY;
+    if (own) cut[0] = bound_cut(cv, cm, np_w, wave, lane, s_lb);   // holds the block barrier
     else __syncthreads();
     uint64_t npred[BT];
     Acc a[BT];
@@ -580,6 +623,7 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         acc_init(a[j]);
         tt[j] = fold_shift(-INFINITY);
     }
+    if (BT > 1 && bound) bound_cuts<BT>(cv, cm, npred, wave, lane, s_lbm, cut);   // a second barrier
 
     const u64x2 *mp = reinterpret_cast<const u64x2 *>(V.masks + row);
     const f32x4 *sp = reinterpret_cast<const f32x4 *>(V.scores + row);
@@ -601,8 +645,8 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         if (lane < steps) {
             if (V.tand) {
 #pragma unroll
-                for (int j = 0; j < BT; ++j) m |= ((tsum & npred[j]) == 0ull) ? (1u << j) : 0u;
-                if (bound && tmx < cut) m = 0u;
+                for (int j = 0; j < BT; ++j)
+                    m |= ((tsum & npred[j]) == 0ull && !(bound && tmx < cut[j])) ? (1u << j) : 0u;
             } else {
                 m = (1u << BT) - 1u;
             }
@@ -802,24 +846,32 @@ __global__ __launch_bounds__(kScoreThreads) void k_count_tiles(ScoreArgs A, unsi
     const int n = A.n;
     const int count = A.B;
     const TabView V = view_of(A);
-    const bool bound = BT == 1 && A.tmax != nullptr && A.tand != nullptr;
+    const bool bound = A.tmax != nullptr && A.tand != nullptr;
+    const bool own = BT == 1 && bound;
     __shared__ float s_lb[kScoreThreads / 64][2];
+    __shared__ float s_lbm[kScoreThreads / 64][BT][2];
     float cv = -INFINITY;
     uint64_t cm = ~0ull;
     if (bound) bound_candidate(V, node, wave, lane, cv, cm);
     uint64_t np_w = ~0ull;
-    for (int j = bound ? 0 : wave; j < BT; j += kScoreThreads / 64) {
+    for (int j = own ? 0 : wave; j < BT; j += kScoreThreads / 64) {
         uint64_t np = ~0ull;
         if (b0 + j < count) {
             bool valid;
             np = ~wave_pred(A.orders + (int64_t)(b0 + j) * n, n, node, lane, valid);
         }
-        if (lane == 0 && (!bound || wave == 0)) s_np[j] = np;
+        if (lane == 0 && (!own || wave == 0)) s_np[j] = np;
         np_w = np;
     }
-    float cut = -INFINITY;
-    if (bound) cut = bound_cut(cv, cm, np_w, wave, lane, s_lb);
+    float cut[BT];
+    for (int j = 0; j < BT; ++j) cut[j] = -INFINITY;
+    if (own) cut[0] = bound_cut(cv, cm, np_w, wave, lane, s_lb);
     else __syncthreads();
+    if (BT > 1 && bound) {
+        uint64_t np_all[BT];
+        for (int j = 0; j < BT; ++j) np_all[j] = s_np[j];
+        bound_cuts<BT>(cv, cm, np_all, wave, lane, s_lbm, cut);
+    }
     const int64_t trow = (int64_t)node * (A.S_pad >> 8);
     const int steps = A.chunk_entries / kEntriesPerStep;
     // 64-entry sub-tiles read: of the needed tiles, those the order can use (one
@@ -829,9 +881,9 @@ __global__ __launch_bounds__(kScoreThreads) void k_count_tiles(ScoreArgs A, unsi
         for (int it = 0; it < steps; ++it) {
             const int64_t tile = trow + ((chunk + (int64_t)it * A.chunks) << 2) + wave;   // as in score_block
             const uint64_t sm = A.tand[tile];
+            const float tm = bound ? A.tmax[tile] : 0.f;
             bool any = false;
-            for (int j = 0; j < BT; ++j) any |= (sm & s_np[j]) == 0ull;
-            if (bound && A.tmax[tile] < cut) any = false;
+            for (int j = 0; j < BT; ++j) any |= (sm & s_np[j]) == 0ull && !(bound && tm < cut[j]);
             if (!any) continue;
             if (BT > 1) {                  // several orders: the whole tile is read
                 c += 4u;

@@ -403,3 +403,29 @@ def test_chain_sweep_autotune_picks_a_shape_and_keeps_the_chain(bnos, prior20):
     assert np.array_equal(a["orders"], b["orders"])
     assert np.array_equal(a["best_graphs"], b["best_graphs"])
     np.testing.assert_allclose(a["trace"], b["trace"], rtol=REL)
+
+
+@pytest.mark.parametrize("bt", [1, 4, 8])
+def test_score_bound_leaves_chain_sweeps_unchanged(bnos, bt):
+    # 128 chains x 150 iterations on the 40-node table with and without the score
+    # bound, for several chains per block: the same decisions, orders, best graphs
+    # and (bitwise) the same traced scores
+    w = datagen.WORKLOADS["mixed40"]
+    net, prior = datagen.make(w)
+    t = bnos.build_score_table(net.data, net.arities, w.K, prior=prior)
+    C, iters = 128, 150
+    runs = []
+    try:
+        t.chains_set_launch(C, 0, bt)
+        for on in (False, True):
+            t.score_bound(on)
+            st = t.new_chain_state(C, iters, trace_every=1, flags=True)
+            t.run_chains(st, iters, seed=31)
+            torch.cuda.synchronize()
+            runs.append({k: v.cpu().numpy() for k, v in st.items() if v is not None})
+    finally:
+        t.score_bound(True)
+        t.free()
+    a, b = runs
+    for k in ("accept_flags", "orders", "best_graphs", "best_scores", "accepted", "scores", "trace"):
+        assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), k

@@ -733,3 +733,26 @@ def test_score_bound_edge_shapes(bnos, n, K, N, arities):
             assert check_orders_against_oracle(got, orc, K, orders) == 0
     finally:
         t.free()
+
+
+@pytest.mark.parametrize("bt", [2, 4, 8])
+def test_score_bound_several_orders_per_block(bnos, mixed60, bt):
+    # a block of several orders reads a tile if any of its orders needs it and each
+    # order folds only its own: bitwise the same as without the bound, fewer tiles
+    w, net, prior, t = mixed60
+    B = 16
+    orders = datagen.random_orders(w.n, B, seed=700 + bt)
+    orders[3] = np.asarray(net.perm, dtype=np.int32)
+    t.set_launch(B, orders_per_block=bt)
+    try:
+        t.score_bound(False)
+        plain = dev_score(t, orders)
+        n_plain, _ = t.count_tiles(torch.from_numpy(orders).cuda())
+        t.score_bound(True)
+        got = dev_score(t, orders)
+        n_bound, _ = t.count_tiles(torch.from_numpy(orders).cuda())
+        same_bits(got, plain)
+        assert n_bound < n_plain, (n_bound, n_plain)
+    finally:
+        t.score_bound(True)
+        t.set_launch(B)
