@@ -750,7 +750,7 @@ def main():
             per_launch += passes * (per_pass * 8 + (per_pass // 4) * 4 + n * 256 * 12)
         return tl * 64 * eb + per_launch
 
-    def timed(Bq, steps, warmup, skip=True, tables=None, seed_base=5):
+    def timed(Bq, steps, warmup, skip=True, tables=None, seed_base=5, computed=None):
         """Time `steps` scoring launches of Bq random orders each, rotating over `tables`
         (launch s uses tables[s % len]); the kernel time comes from HIP events on every
         7th launch of each table (every launch for batches), and the algorithmic bytes
@@ -794,7 +794,8 @@ def main():
         passes_per_launch = k_passes / k_launches
         # bytes per entry: a one-order block with computed masks reads the score and a quarter
         # of an 8-byte anchor mask (6 B); otherwise mask + score (12 B)
-        eb = 6 if (args.computed_masks and passes_per_launch == Bq) else 12
+        computed_now = bool(args.computed_masks) if computed is None else computed
+        eb = 6 if (computed_now and passes_per_launch == Bq) else 12
         cache = {}
         alg_tot, tiles_tot, per_pass = 0.0, 0, 1
         for s_ in timed_s:
@@ -842,7 +843,7 @@ def main():
         # the stored-mask full scan: 12 B x n x S = 352 MB per launch at n = 60, more than the
         # 256 MB Infinity Cache holds, so every launch streams from HBM
         table.computed_masks(False)
-        rs = timed(B, extra_steps, args.warmup, skip=False)
+        rs = timed(B, extra_steps, args.warmup, skip=False, computed=False)
         table.computed_masks(bool(args.computed_masks))
         print(f"# stored-mask full scan: {rs['kernel_avg_ms'] * 1e3:.1f} us per launch, {rs['gbs']:.0f} GB/s",
               file=sys.stderr, flush=True)
