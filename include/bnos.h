@@ -68,7 +68,10 @@ typedef struct {
                               families (i, U \ {i}); 1: one histogram per family.  Same table, bit
                               for bit; 0 counts about (K+1) times fewer samples.  (0 falls back to 1
                               when the lnGamma lookup of the build would exceed 256 MB.) */
-    int32_t reserved[5];   /* must be zero */
+    int32_t data_on_device; /* 0: data is a host array; 1: data is a DEVICE pointer (int8 [N][n],
+                              row-major, ready on `stream`); its states are then checked on the
+                              device, and an out-of-range state is BNOS_E_INVALID as for host data */
+    int32_t reserved[4];   /* must be zero */
 } bnos_build_opts;         /* all-zero = defaults */
 
 /*
@@ -88,6 +91,10 @@ typedef struct {
  *              has completed on it.
  *   out        receives the handle; free with bnos_table_free.
  * The library copies what it needs and keeps no caller pointer.
+ * Memory cap: if the environment variable BNOS_MAX_DEVICE_BYTES holds a positive
+ * integer, a build whose table would hold more device bytes than that (the
+ * bnos_table_info figure, before any scoring workspace) returns BNOS_E_NOMEM
+ * with a message, before it touches the device.
  * Table layout (device): for node i, entries e = 0..S-1 with
  * S = sum_{j<=K} C(n-1, j) hold (uint64 parent mask, float score); the
  * entries are the parent sets of size <= K over the other n-1 nodes, listed

@@ -39,7 +39,8 @@ i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 
 class BuildOpts(ctypes.Structure):
     _fields_ = [("log_gamma", ctypes.c_double), ("prior_mode", ctypes.c_int32), ("chunk_steps", ctypes.c_int32),
-                ("count_mode", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("count_mode", ctypes.c_int32), ("data_on_device", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class ChainCfg(ctypes.Structure):
@@ -454,10 +455,18 @@ def run_chains_multi(tables, states, iterations: int, seed: int, target: int = 0
 
 def build_score_table(data, arities, K: int, ess: float = 1.0, prior=None, prior_mode: int = 0,
                       log_gamma: float = 0.0, chunk_steps: int = 0, count_mode: int = 0, stream=None) -> Table:
-    """Build the local-score table (host inputs; see bnos_build_score_table)."""
-    data = np.ascontiguousarray(data, dtype=np.int8)
-    if data.ndim != 2:
-        raise ValueError("data must be [N][n]")
+    """Build the local-score table (see bnos_build_score_table).  `data` is a host
+    array, or a DEVICE int8 torch tensor [N][n] (row-major), passed as a device
+    pointer; the other inputs are host arrays."""
+    on_dev = hasattr(data, "is_cuda") and data.is_cuda
+    if on_dev:
+        import torch
+        if data.dtype != torch.int8 or data.dim() != 2 or not data.is_contiguous():
+            raise ValueError("device data must be a contiguous int8 tensor [N][n]")
+    else:
+        data = np.ascontiguousarray(data, dtype=np.int8)
+        if data.ndim != 2:
+            raise ValueError("data must be [N][n]")
     N, n = data.shape
     ar = np.ascontiguousarray(arities, dtype=np.int32)
     pr = None if prior is None else np.ascontiguousarray(prior, dtype=np.float32)
@@ -466,9 +475,11 @@ def build_score_table(data, arities, K: int, ess: float = 1.0, prior=None, prior
     opts.prior_mode = prior_mode
     opts.chunk_steps = chunk_steps
     opts.count_mode = count_mode
+    opts.data_on_device = 1 if on_dev else 0
     h = ctypes.c_void_p()
     st = ctypes.c_void_p(0) if stream is None else _stream(stream)
-    _check(_lib.bnos_build_score_table(_ptr(data) if N else None, N, n, _ptr(ar), K, ess,
+    dptr = (_dptr(data) if on_dev else _ptr(data)) if N else None
+    _check(_lib.bnos_build_score_table(dptr, N, n, _ptr(ar), K, ess,
                                        None if pr is None else _ptr(pr), ctypes.byref(opts), st,
                                        ctypes.byref(h)))
     return Table(h.value, n, K)

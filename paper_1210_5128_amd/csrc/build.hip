@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <set>
@@ -175,6 +176,22 @@ __global__ void k_ingest(const int8_t *__restrict__ src, int64_t N, int n, int64
         int v = (int)(g - t * n);
         dst[(int64_t)v * N_pad + t] = (uint8_t)src[g];
     }
+}
+
+// Device-resident input: counts the states outside [0, arity) (the host input
+// is checked on the host instead).
+__global__ void k_check_states(const int8_t *__restrict__ src, int64_t N, int n, const int32_t *__restrict__ ar,
+                               unsigned *__restrict__ bad)
+{
+    const int64_t total = N * n;
+    unsigned c = 0;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int x = src[g];
+        const int v = (int)(g % n);
+        c += (x < 0 || x >= ar[v]) ? 1u : 0u;
+    }
+    if (c) atomicAdd(bad, c);
 }
 
 // Prior term in nats per (child i, parent m): ln(10) * 100 * (R - 0.5)^3 (Eq. (10),
@@ -814,14 +831,16 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     bnos_build_opts o;
     std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
-    for (int r = 0; r < 5; ++r)
+    for (int r = 0; r < 4; ++r)
         if (o.reserved[r] != 0) { set_error("opts.reserved must be zero"); return BNOS_E_INVALID; }
+    if (o.data_on_device != 0 && o.data_on_device != 1) { set_error("data_on_device must be 0 or 1"); return BNOS_E_INVALID; }
+    const bool dev_data = o.data_on_device == 1;
     if (o.prior_mode != 0 && o.prior_mode != 1) { set_error("prior_mode must be 0 or 1"); return BNOS_E_INVALID; }
     if (o.count_mode != 0 && o.count_mode != 1) { set_error("count_mode must be 0 or 1"); return BNOS_E_INVALID; }
     if (!std::isfinite(o.log_gamma)) { set_error("log_gamma must be finite"); return BNOS_E_INVALID; }
     for (int v = 0; v < n; ++v)
         if (arities[v] < 1 || arities[v] > 255) { set_error("arity outside [1, 255]"); return BNOS_E_RANGE; }
-    for (int64_t t = 0; t < N; ++t)
+    for (int64_t t = 0; t < (dev_data ? 0 : N); ++t)        // device data: checked on the device
         for (int v = 0; v < n; ++v) {
             int x = data[t * n + v];
             if (x < 0 || x >= arities[v]) {
@@ -876,6 +895,17 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
         while (P < kMaxStepsPerChunk && (P < node_steps || P < st)) P <<= 1;
         t->pad_steps = P;
         t->S_pad = ((node_steps + P - 1) / P) * P * kEntriesPerStep;
+        if (const char *cap_s = std::getenv("BNOS_MAX_DEVICE_BYTES")) {
+            const long long cap = std::atoll(cap_s);
+            if (cap > 0 && t->device_bytes() > cap) {
+                char buf[160];
+                std::snprintf(buf, sizeof buf, "table needs %lld device bytes, above BNOS_MAX_DEVICE_BYTES = %lld",
+                              (long long)t->device_bytes(), cap);
+                set_error(buf);
+                delete t;
+                return BNOS_E_NOMEM;
+            }
+        }
         if (st == 0) {
             // automatic: the length that best fills whole rounds of resident blocks
             // (8 blocks of 256 threads per compute unit) for a single-order pass
@@ -948,17 +978,39 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
         hipFree(d_lut_row); hipFree(d_den); hipFree(d_lut);                               \
         return fail(BNOS_E_DEVICE);                                                       \
     }
-    if (N > 0) CK(hipMalloc((void **)&d_rows, (size_t)N * n));
+    if (N > 0 && !dev_data) CK(hipMalloc((void **)&d_rows, (size_t)N * n));
     if (prior) CK(hipMalloc((void **)&d_prior_in, sizeof(float) * n * n));
     CK(hipMemsetAsync(t->d_data, 0, (size_t)n * t->N_pad, st));
-    if (N > 0) CK(hipMemcpyAsync(d_rows, data, (size_t)N * n, hipMemcpyHostToDevice, st));
+    if (N > 0 && !dev_data) CK(hipMemcpyAsync(d_rows, data, (size_t)N * n, hipMemcpyHostToDevice, st));
     if (prior) CK(hipMemcpyAsync(d_prior_in, prior, sizeof(float) * n * n, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(t->d_ar, arities, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(t->d_nsets, nsets.data(), sizeof(int64_t) * 64 * 8, hipMemcpyHostToDevice, st));
     if (N > 0) {
         int64_t tot = N * n;
         int blocks = (int)std::min<int64_t>((tot + 255) / 256, 1 << 16);
-        hipLaunchKernelGGL(k_ingest, dim3(blocks), dim3(256), 0, st, d_rows, N, n, t->N_pad, t->d_data);
+        if (dev_data) {                          // the caller's device rows: check their states first
+            unsigned *d_bad = nullptr;
+            unsigned bad = 0;
+            CK(hipMalloc((void **)&d_bad, sizeof(unsigned)));
+            hipError_t e2 = hipMemsetAsync(d_bad, 0, sizeof(unsigned), st);
+            if (e2 == hipSuccess) {
+                hipLaunchKernelGGL(k_check_states, dim3(blocks), dim3(256), 0, st, data, N, n, t->d_ar, d_bad);
+                e2 = hipGetLastError();
+            }
+            if (e2 == hipSuccess) e2 = hipMemcpyAsync(&bad, d_bad, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+            if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
+            hipFree(d_bad);
+            CK(e2);
+            if (bad) {
+                char buf[128];
+                std::snprintf(buf, sizeof buf, "%u states of the device data are outside their node's arity", bad);
+                set_error(buf);
+                hipFree(d_prior_in);
+                return fail(BNOS_E_INVALID);
+            }
+        }
+        hipLaunchKernelGGL(k_ingest, dim3(blocks), dim3(256), 0, st, dev_data ? data : d_rows, N, n, t->N_pad,
+                           t->d_data);
         CK(hipGetLastError());
     }
     hipLaunchKernelGGL(k_prior, dim3((n * n + 255) / 256), dim3(256), 0, st, d_prior_in, n, o.prior_mode,

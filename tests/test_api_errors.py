@@ -86,3 +86,31 @@ def test_stale_handles_are_rejected():
     assert B._lib.bnos_mlp_set_params(ctypes.c_void_p(0x7654320), None, None, None) == B.E_STATE
     B._lib.bnos_table_free(ctypes.c_void_p(0x1234560))     # a no-op, not a crash
     B._lib.bnos_mlp_free(ctypes.c_void_p(0x7654320))
+
+
+def test_device_byte_cap_is_checked_before_the_device(monkeypatch):
+    # BNOS_MAX_DEVICE_BYTES: a build whose table would need more device memory
+    # returns E_NOMEM with a message, before any device call (so on the CPU too)
+    d = np.zeros((50, 12), dtype=np.int8)
+    monkeypatch.setenv("BNOS_MAX_DEVICE_BYTES", "4096")
+    assert status_of(lambda: build(d, [2] * 12, 3)) == B.E_NOMEM
+    msg = B._lib.bnos_last_error().decode()
+    assert "BNOS_MAX_DEVICE_BYTES" in msg and "4096" in msg
+    monkeypatch.setenv("BNOS_MAX_DEVICE_BYTES", "0")       # 0 or unset: no cap; argument checks still come first
+    assert status_of(lambda: build(d, [2] * 12, 12)) == B.E_RANGE
+
+
+def test_build_options_reject_unknown_values():
+    d = np.zeros((6, 3), dtype=np.int8)
+    opts = B.BuildOpts()
+    opts.data_on_device = 2
+    h = ctypes.c_void_p()
+    ar = np.array([2, 2, 2], np.int32)
+    st = B._lib.bnos_build_score_table(B._ptr(d), 6, 3, B._ptr(ar), 1, 1.0, None, ctypes.byref(opts), None,
+                                       ctypes.byref(h))
+    assert st == B.E_INVALID
+    opts.data_on_device = 0
+    opts.reserved[3] = 1
+    st = B._lib.bnos_build_score_table(B._ptr(d), 6, 3, B._ptr(ar), 1, 1.0, None, ctypes.byref(opts), None,
+                                       ctypes.byref(h))
+    assert st == B.E_INVALID

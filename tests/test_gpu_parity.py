@@ -756,3 +756,26 @@ def test_score_bound_several_orders_per_block(bnos, mixed60, bt):
     finally:
         t.score_bound(True)
         t.set_launch(B)
+
+
+def test_build_from_device_data_matches_host_data(bnos):
+    # the same rows handed over as a device tensor give the same table, bit for
+    # bit; an out-of-range state in device data is rejected like host data
+    w = datagen.WORKLOADS["prior20"]
+    net, prior = datagen.make(w)
+    th = bnos.build_score_table(net.data, net.arities, w.K, prior=prior)
+    dd = torch.from_numpy(np.ascontiguousarray(net.data, dtype=np.int8)).cuda()
+    td = bnos.build_score_table(dd, net.arities, w.K, prior=prior)
+    try:
+        for v in (0, 7, w.n - 1):
+            mh, sh = th.export(v)
+            md, sd = td.export(v)
+            assert np.array_equal(mh, md) and np.array_equal(sh.view(np.uint32), sd.view(np.uint32))
+        bad = dd.clone()
+        bad[5, 3] = int(net.arities[3])
+        with pytest.raises(bnos.BnosError) as e:
+            bnos.build_score_table(bad, net.arities, w.K)
+        assert e.value.status == bnos.E_INVALID
+    finally:
+        th.free()
+        td.free()
