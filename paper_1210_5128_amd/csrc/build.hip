@@ -242,9 +242,19 @@ __device__ __forceinline__ int64_t rank_ascending(uint64_t m, int bits, int K, c
 // cell index (the last member fastest).
 struct Subset {
     int u[kMaxK + 1], r[kMaxK + 1], stride[kMaxK + 1];
+    uint32_t magic[kMaxK + 1];   // floor(2^32 / r) + 1: quotients by r of cell indices (< 2^14) by multiply-high
     int j;        // members
     int cells;    // product of the members' arities
 };
+
+// q = x / r and x - q r for 0 <= x < 2^14 and 1 <= r <= 255: with m = floor(2^32/r) + 1,
+// x m / 2^32 exceeds x / r by less than x / 2^32 < 2^-18, too little to carry a
+// fraction of at most (r - 1) / r past the next integer.
+__device__ __forceinline__ void divmod_small(int x, int r, uint32_t magic, int &q, int &rem)
+{
+    q = (r == 1) ? x : (int)__umulhi((uint32_t)x, magic);
+    rem = x - q * r;
+}
 
 __device__ __forceinline__ Subset decode_subset(uint64_t U, const int32_t *__restrict__ ar)
 {
@@ -261,6 +271,7 @@ __device__ __forceinline__ Subset decode_subset(uint64_t U, const int32_t *__res
             S.r[t] = ar[S.u[t]];
             S.j = t + 1;
         }
+        S.magic[t] = S.r[t] > 1 ? (uint32_t)(0x100000000ull / (uint64_t)S.r[t]) + 1u : 0u;
     }
     int cells = 1;
 #pragma unroll
@@ -275,25 +286,41 @@ __device__ __forceinline__ Subset decode_subset(uint64_t U, const int32_t *__res
 // Joint histogram of U's variables over the N samples into hist[0 .. cells)
 // (one wavefront, its private LDS region); each lane takes 4 consecutive
 // samples per step from 32-bit loads of the column-major data.
+// (J = the number of members, a constant of the instance.)
+template <int J>
+__device__ __forceinline__ void joint_histogram_j(const uint8_t *__restrict__ data, int64_t N, int64_t N_pad,
+                                                  const Subset &S, uint32_t *hist, int lane)
+{
+    const uint32_t *col[J];
+#pragma unroll
+    for (int t = 0; t < J; ++t) col[t] = reinterpret_cast<const uint32_t *>(data + (int64_t)S.u[t] * N_pad);
+    for (int64_t base = (int64_t)lane * 4; base < N; base += 256) {
+        uint32_t x[J];
+#pragma unroll
+        for (int t = 0; t < J; ++t) x[t] = col[t][base >> 2];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            int cell = 0;
+#pragma unroll
+            for (int t = 0; t < J; ++t) cell += S.stride[t] * (int)((x[t] >> (8 * b)) & 0xffu);
+            if (base + b < N) atomicAdd(&hist[cell], 1u);
+        }
+    }
+}
+
 __device__ __forceinline__ void joint_histogram(const uint8_t *__restrict__ data, int64_t N, int64_t N_pad,
                                                 const Subset &S, uint32_t *hist, int lane)
 {
     for (int c = lane; c < S.cells; c += 64) hist[c] = 0u;
     wave_lds_sync();
-    const uint32_t *col[kMaxK + 1];
-#pragma unroll
-    for (int t = 0; t <= kMaxK; ++t) col[t] = reinterpret_cast<const uint32_t *>(data + (int64_t)S.u[t] * N_pad);
-    for (int64_t base = (int64_t)lane * 4; base < N; base += 256) {
-        uint32_t x[kMaxK + 1];
-#pragma unroll
-        for (int t = 0; t <= kMaxK; ++t) x[t] = (t < S.j) ? col[t][base >> 2] : 0u;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            int cell = 0;
-#pragma unroll
-            for (int t = 0; t <= kMaxK; ++t) cell += S.stride[t] * (int)((x[t] >> (8 * b)) & 0xffu);
-            if (base + b < N) atomicAdd(&hist[cell], 1u);
-        }
+    switch (S.j) {                 // uniform: one subset per wavefront
+    case 1: joint_histogram_j<1>(data, N, N_pad, S, hist, lane); break;
+    case 2: joint_histogram_j<2>(data, N, N_pad, S, hist, lane); break;
+    case 3: joint_histogram_j<3>(data, N, N_pad, S, hist, lane); break;
+    case 4: joint_histogram_j<4>(data, N, N_pad, S, hist, lane); break;
+    case 5: joint_histogram_j<5>(data, N, N_pad, S, hist, lane); break;
+    case 6: joint_histogram_j<6>(data, N, N_pad, S, hist, lane); break;
+    default: joint_histogram_j<kMaxK + 1>(data, N, N_pad, S, hist, lane); break;
     }
     wave_lds_sync();
 }
@@ -324,8 +351,10 @@ __device__ __forceinline__ int family_base(const Subset &S, int c, int k)
 #pragma unroll
     for (int t = kMaxK; t >= 0; --t) {
         if (t < S.j && t != c) {
-            J += (rest % S.r[t]) * S.stride[t];
-            rest /= S.r[t];
+            int q, d;
+            divmod_small(rest, S.r[t], S.magic[t], q, d);
+            J += d * S.stride[t];
+            rest = q;
         }
     }
     return J;
