@@ -464,6 +464,14 @@ __device__ __forceinline__ void bound_candidate(const TabView &V, int node, int 
     cm = V.cmask[c];
 }
 
+// b - kBoundGap, or -inf where FP32 cannot hold that gap below b (|b| of order
+// 2^31 and above, where the rounded difference could come out closer to b).
+__device__ __forceinline__ float gap_below(float b)
+{
+    const float g = b - kBoundGap;
+    return (b - g >= kBoundGap) ? g : -INFINITY;
+}
+
 // The score below which a tile is left out, for predecessor complement np
 // (node space).  Every thread of the block calls it (it holds a barrier).
 __device__ __forceinline__ float bound_cut(float cv, uint64_t cm, uint64_t np, int wave, int lane,
@@ -491,7 +499,7 @@ __device__ __forceinline__ float bound_cut(float cv, uint64_t cm, uint64_t np, i
 #pragma unroll
     for (int w = 0; w < kScoreThreads / 64; ++w)
         if (w != wb) sec = fmaxf(sec, s_lb[w][0]);
-    return fminf(b - kBoundGap, sec);
+    return fminf(gap_below(b), sec);
 }
 
 // The same for the BT orders of a several-order block, after the barrier that
@@ -528,7 +536,7 @@ __device__ __forceinline__ void bound_cuts(float cv, uint64_t cm, const uint64_t
 #pragma unroll
         for (int w = 0; w < kScoreThreads / 64; ++w)
             if (w != wb) sec = fmaxf(sec, s_lbm[w][j][0]);
-        cut[j] = fminf(b - kBoundGap, sec);
+        cut[j] = fminf(gap_below(b), sec);
     }
 }
 
