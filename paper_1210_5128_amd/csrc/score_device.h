@@ -743,11 +743,14 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
                 bool any = false;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const bool ok = (mk[e] & np) == 0ull;
+                    // an entry below the order's cut is left out like the tiles below it (it is
+                    // neither result and its term is below e^-60 of the largest); cut[j] = -inf
+                    // without the bound
+                    const bool ok = (mk[e] & np) == 0ull && !(x[e] < cut[j]);
                     xs[e] = ok ? x[e] : -INFINITY;
                     any |= ok;
                 }
-                if (__ballot(any) == 0ull) continue;         // uniform: nothing consistent in the wavefront
+                if (__ballot(any) == 0ull) continue;         // uniform: nothing to fold in the wavefront
                 if (BT == 1 && CM) {
                     acc_fold4_sel(a[j], tt[j], xs, mk);
                 } else if (BT == 1) {
