@@ -377,7 +377,7 @@ struct ScoreArgs {
     const uint64_t *tand;      // tile summaries, or null
     const uint64_t *tsub;      // sub-tile summaries (with tand)
     const uint64_t *anchor;    // first mask of every 4 entries in slot space, or null
-    const float *tmax;         // largest score of each tile (with tand, one order per block), or null
+    const float *tmax;         // largest score of each tile (with tand: the score bound), or null
     const uint64_t *cmask;     // [n][kBoundSlots] score-bound candidates of each row (with tmax)
     const float *cscore;
     int K;
@@ -441,17 +441,19 @@ __device__ __forceinline__ uint64_t to_nodes(uint64_t s, int node)
     return (s & low) | ((s & ~low) << 1);
 }
 
-// ---- score bound (one order per block)
+// ---- score bound
 //
-// A block takes lower bounds on the best and the second-best score among the
-// entries its order can use, from candidates kept per row at build (lane l of
-// wavefront w holds slot 64 w + l): the singleton of slot s (usable if that
-// node precedes), the empty set (always usable) and the row's listed top
-// entries of two or more members.  The candidates are distinct entries, so the
-// largest usable one bounds the best from below and the second largest the
-// second best.  A tile whose largest score is below both the second-best bound
-// and the best bound minus kBoundGap holds neither result and only terms below
-// e^-kBoundGap of the largest one; the block leaves it out.
+// For each of its orders, a block takes lower bounds on the best and the
+// second-best score among the entries the order can use, from candidates kept
+// per row at build (lane l of wavefront w holds slot 64 w + l): the singleton
+// of slot s (usable if that node precedes), the empty set (always usable) and
+// the row's listed top entries of two or more members.  The candidates are
+// distinct entries, so the largest usable one bounds the best from below and
+// the second largest the second best.  A tile whose largest score is below
+// both the second-best bound and the best bound minus kBoundGap holds neither
+// result and only terms below e^-kBoundGap of the largest one; the block
+// leaves it out for that order (and reads it only if another order needs it),
+// and inside a kept tile an entry below the cut counts as unusable.
 
 // This lane's candidate (score, node-space mask); requested before the order
 // is read so that the loads overlap.
