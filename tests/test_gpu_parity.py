@@ -779,3 +779,31 @@ def test_build_from_device_data_matches_host_data(bnos):
     finally:
         th.free()
         td.free()
+
+
+@pytest.mark.parametrize("log_gamma,prior_mode", [(-8.0, 0), (3.0, 0), (0.0, 1)])
+def test_score_bound_with_structure_penalty_and_priors(bnos, log_gamma, prior_mode):
+    # the bound's candidates and tile maxima follow the stored scores whatever shifts
+    # them: a structure penalty per parent (either sign) or the paper's R-form prior
+    # with strong entries; bound on vs off bitwise, and against the oracle
+    w = datagen.WORKLOADS["prior20"]
+    net, prior = datagen.make(w)
+    if prior_mode == 1:
+        prior = np.clip((1.0 + prior) / 2.0, 0.0, 1.0).astype(np.float32)
+        prior[np.abs(prior - 0.5) > 0.3] = 1.0          # a few confident edges
+    t = bnos.build_score_table(net.data, net.arities, w.K, prior=prior, prior_mode=prior_mode,
+                               log_gamma=log_gamma)
+    orc = oracle.build_table(net.data, net.arities, w.K, prior=prior, prior_mode=prior_mode,
+                             log_gamma=log_gamma)
+    try:
+        orders = np.concatenate([datagen.random_orders(w.n, 6, seed=41),
+                                 np.asarray(net.perm, dtype=np.int32)[None]])
+        t.set_launch(orders.shape[0], orders_per_block=1)
+        t.score_bound(False)
+        plain = dev_score(t, orders)
+        t.score_bound(True)
+        got = dev_score(t, orders)
+        same_bits(got, plain)
+        assert check_orders_against_oracle(got, orc, w.K, orders) == 0
+    finally:
+        t.free()
