@@ -202,14 +202,16 @@ bnos_status bnos_score_orders(bnos_table t, const int32_t *orders, int32_t B, do
  * For callers that cannot allocate device memory -- code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc: the same
  * scoring as bnos_score_orders (same arguments, kernels and results, bit for
- * bit), with the chunk partials in a fixed device array of 16 MiB that the
- * library holds on each GPU it runs on until the process ends, instead of
- * the table's workspace.  It never calls hipMalloc or hipFree; the first call
- * on a device only looks up that array's address (make it before any capture).
- * Limit: B orders need B * n * slots * 24 bytes, slots = the launch's chunks
- * per row (n for the gather pass); above 16 MiB the call returns
- * BNOS_E_RANGE before any device work (at n = 60, K = 4, in the default
- * shape for 8+ orders, 30 chunks per row: up to 388 orders in one call).  Every call on a GPU, for any table, uses that GPU's one array:
+ * bit), with the chunk partials and the per-(order, node) score-bound cuts
+ * in a fixed device array of 16 MiB that the library holds on each GPU it
+ * runs on until the process ends, instead of the table's workspace.  It never
+ * calls hipMalloc or hipFree; the first call on a device only looks up that
+ * array's address (make it before any capture).
+ * Limit: B orders need B * n * slots * 24 bytes (rounded up to 256) plus
+ * B * n * 4, slots = the launch's chunks per row (n for the gather pass);
+ * above 16 MiB the call returns BNOS_E_RANGE before any device work (at
+ * n = 60, K = 4, in the default shape for 8+ orders, 30 chunks per row: up to
+ * 386 orders in one call).  Every call on a GPU, for any table, uses that GPU's one array:
  * calls that may overlap on one GPU (streams, host threads) race and must be
  * serialised by the caller.  Nothing needs clearing between calls.
  */

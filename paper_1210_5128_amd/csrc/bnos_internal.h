@@ -121,12 +121,15 @@ struct TableT {
     int chain_chunks_for(int C) const { return (int)(S_pad / chain_chunk_entries_for(C)); }
     // partials of one launch: [B][chunks][n], with n slots per order in gather mode; a chain
     // sweep of B chains writes [B][chain chunks][n]
-    int64_t workspace_bytes_for(int B) const
+    int64_t partial_bytes_for(int B) const
     {
         int c = chunks_for(B) > n ? chunks_for(B) : n;
         if (chain_chunks_for(B) > c) c = chain_chunks_for(B);
         return (int64_t)B * n * c * (int64_t)sizeof(Partial);
     }
+    // the partials, then (256-byte aligned) each order's score-bound cut per node
+    int64_t cuts_offset_for(int B) const { return (partial_bytes_for(B) + 255) & ~(int64_t)255; }
+    int64_t workspace_bytes_for(int B) const { return cuts_offset_for(B) + (int64_t)B * n * (int64_t)sizeof(float); }
     bool gather_for(int B) const { return K <= 4 && tuned_gather[bucket(B)] != 0; }
 };
 

@@ -75,6 +75,7 @@ struct ChainView {
     int32_t *wl_count;         // [n] chains listing each node in their window
     int32_t *wl_list;          // [n][C]
     uint8_t *ppos;             // [C][n] position of each node in the order being scored
+    float *cuts;               // [C][n] score-bound cut of each window node of the proposal, or null
     double *trace;             // [C][trace_len] or null
     int trace_every;
     int64_t trace_len;
@@ -221,6 +222,34 @@ __global__ __launch_bounds__(kListThreads) void k_worklist(const ChainView *__re
         }
         __syncthreads();
     }
+}
+
+// Score bound of the proposals: one wavefront per (chain, node) pair over all
+// tables (pair g: node g mod the total node count, chain g div it) computes the
+// cut of the chain's proposal for that node when the node is in the chain's
+// window, so that the scoring blocks read it instead of each computing it.
+__global__ __launch_bounds__(kScoreThreads) void k_chain_cuts(const TabView *__restrict__ tviews,
+                                                              const ChainView *__restrict__ views,
+                                                              const int64_t *__restrict__ node_base, int T,
+                                                              int C)
+{
+    const int64_t g = (int64_t)blockIdx.x * (kScoreThreads / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t nodes = node_base[T];
+    if (g >= nodes * C) return;                              // uniform per wavefront
+    const int c = (int)(g / nodes);
+    const int64_t gn = g - (int64_t)c * nodes;
+    const int k = find_segment(node_base, T, gn);
+    const ChainView &H = views[k];
+    const int node = (int)(gn - node_base[k]);
+    if (!H.cuts || !((H.wmask[c] >> node) & 1ull)) return;  // uniform
+    const int n = H.n;
+    const uint8_t *pp = H.ppos + (int64_t)c * n;
+    const int pv = pp[node];
+    const int pu = pp[lane < n ? lane : n - 1];              // every lane loads (no branch)
+    const uint64_t pred = __ballot(lane < n && pu < pv);
+    const float cut = wave_bound_cut(tviews[k], node, ~pred, lane);
+    if (lane == 0) H.cuts[(int64_t)c * n + node] = cut;
 }
 
 // Offer graph g (lane i holds node i's parent mask) with max score M to chain
@@ -587,6 +616,7 @@ static bnos_status run_chains_impl(const bnos_table *hs, int32_t T, const bnos_c
         bytes += cn * 24 + (size_t)C * 16 + cn * 4 + n * C * 4 + n * 4 + 256;   // caches, windows, lists
         bytes += cn * 8 + cn * 4 + (size_t)C * 8 + (size_t)C * 8 + 256;         // second best, logits, q, pair
         bytes += cn + 256;                                                       // node positions
+        bytes += cn * 4 + 256;                                                   // score-bound cuts
         bytes = (bytes + 255) & ~(size_t)255;
     }
     char *ws = nullptr;
@@ -625,7 +655,10 @@ static bnos_status run_chains_impl(const bnos_table *hs, int32_t T, const bnos_c
         H.lq_fwd = reinterpret_cast<double *>(p);       p += (size_t)C * 8;
         H.cur_logit = reinterpret_cast<float *>(p);     p += cn * 4;
         H.pend = reinterpret_cast<int32_t *>(p);       p += (size_t)C * 8;
-        H.ppos = reinterpret_cast<uint8_t *>(p);
+        H.ppos = reinterpret_cast<uint8_t *>(p);       p += cn;
+        p = ws + ((size_t)(p - ws + 255) & ~(size_t)255);
+        const bool bound = t->score_bound && t->tile_skip;
+        H.cuts = bound ? reinterpret_cast<float *>(p) : nullptr;
         H.nstat = t->d_nstat;
         H.proposal = cfg->proposal;
         H.eps = cfg->eps > 0.f ? (double)cfg->eps : 0.5;
@@ -668,10 +701,10 @@ static bnos_status run_chains_impl(const bnos_table *hs, int32_t T, const bnos_c
         V.tand = t->tile_skip ? t->d_tand : nullptr;
         V.tsub = t->d_tsub;
         V.anchor = nullptr;            // chain blocks read the stored masks
-        const bool bound = t->score_bound && t->tile_skip;
         V.tmax = bound ? t->d_tmax : nullptr;
         V.cmask = bound ? t->d_cmask : nullptr;
         V.cscore = bound ? t->d_cscore : nullptr;
+        V.cuts = H.cuts;               // computed by k_chain_cuts before each scoring launch
         V.K = t->K;
         blk_base[k + 1] = blk_base[k] + (int64_t)n * V.chunks;
         chain_base[k + 1] = chain_base[k] + C;
@@ -709,10 +742,17 @@ static bnos_status run_chains_impl(const bnos_table *hs, int32_t T, const bnos_c
     const int bt = (tb_bt > 0 && tb_bt <= C) ? tb_bt : pick_bt(tabs[0], C);
     const unsigned groups = (unsigned)((max_groups_c + bt - 1) / bt);
     const unsigned total_chains = (unsigned)chain_base[T];
+    bool any_bound = false;
+    for (int k = 0; k < T; ++k) any_bound = any_bound || cv[k].cuts != nullptr;
     hipLaunchKernelGGL(k_chain_init, dim3(total_chains), dim3(64), 0, us, d_cv, d_chain, T);
     CK(hipGetLastError());
     auto one_step = [&](hipStream_t q) -> hipError_t {
         hipLaunchKernelGGL(k_worklist, dim3((unsigned)node_base[T]), dim3(kListThreads), 0, q, d_cv, d_node, T);
+        if (any_bound) {
+            const int64_t pairs = node_base[T] * (int64_t)C;
+            hipLaunchKernelGGL(k_chain_cuts, dim3((unsigned)((pairs + kScoreThreads / 64 - 1) / (kScoreThreads / 64))),
+                               dim3(kScoreThreads), 0, q, d_tv, d_cv, d_node, T, C);
+        }
         dim3 grid((unsigned)((blk_base[T] + kXcds - 1) / kXcds * kXcds), groups);   // padded for xcd_block
         if (bt == 8) hipLaunchKernelGGL(k_score_multi<8>, grid, dim3(kScoreThreads), 0, q, d_tv, d_blk, T);
         else if (bt == 4) hipLaunchKernelGGL(k_score_multi<4>, grid, dim3(kScoreThreads), 0, q, d_tv, d_blk, T);

@@ -29,6 +29,23 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_merge(ScoreArgs A)
     }
 }
 
+// The cut of every (order, node) pair of a several-order launch, one wavefront
+// per pair, written to A.cut_ws[order][node] before the scoring launch: the
+// scoring blocks then read their orders' cuts instead of each recomputing them
+// (a node's row is streamed by many blocks).
+__global__ __launch_bounds__(kScoreThreads) void k_bound_pre(ScoreArgs A)
+{
+    const int64_t g = (int64_t)blockIdx.x * (kScoreThreads / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int n = A.n;
+    if (g >= (int64_t)A.B * n) return;            // uniform per wavefront
+    const int b = (int)(g / n), node = (int)(g - (int64_t)b * n);
+    bool valid;
+    const uint64_t np = ~wave_pred(A.orders + (int64_t)b * n, n, node, lane, valid);
+    const float c = wave_bound_cut(view_of(A), node, np, lane);
+    if (lane == 0) A.cut_ws[g] = c;
+}
+
 // Gather pass: see the comment at kGatherMaxK (score_device.h).
 __global__ __launch_bounds__(kScoreThreads) void k_gather(ScoreArgs A, const int64_t *__restrict__ nsets, int K)
 {
@@ -236,6 +253,9 @@ ScoreArgs score_args(const TableT *t, const int32_t *orders, int B, double *lse,
     A.tmax = bound ? t->d_tmax : nullptr;
     A.cmask = bound ? t->d_cmask : nullptr;
     A.cscore = bound ? t->d_cscore : nullptr;
+    A.cuts = nullptr;
+    A.cut_ws = t->d_part ? reinterpret_cast<float *>(static_cast<char *>(t->d_part) + t->cuts_offset_for(B))
+                         : nullptr;
     A.K = t->K;
     return A;
 }
@@ -284,10 +304,18 @@ bnos_status launch_stream(TableT *t, const ScoreArgs &A, hipStream_t st, int bt,
         if ((s = next_events(t, e0, e1, (A.B + bt - 1) / bt)) != BNOS_OK) return s;
     }
     const int nbx = t->n * A.chunks;
-    if (bt == 8) launch_bt<8>(A, nbx, st, e0, e1);
-    else if (bt == 4) launch_bt<4>(A, nbx, st, e0, e1);
-    else if (bt == 2) launch_bt<2>(A, nbx, st, e0, e1);
-    else launch_bt<1>(A, nbx, st, e0, e1);
+    ScoreArgs A2 = A;
+    if (bt > 1 && A.tmax && A.tand && A.cut_ws) {
+        // every (order, node) cut once, before the blocks that stream the node's row
+        const int64_t pairs = (int64_t)A.B * A.n;
+        hipLaunchKernelGGL(k_bound_pre, dim3((unsigned)((pairs + kScoreThreads / 64 - 1) / (kScoreThreads / 64))),
+                           dim3(kScoreThreads), 0, st, A);
+        A2.cuts = A.cut_ws;
+    }
+    if (bt == 8) launch_bt<8>(A2, nbx, st, e0, e1);
+    else if (bt == 4) launch_bt<4>(A2, nbx, st, e0, e1);
+    else if (bt == 2) launch_bt<2>(A2, nbx, st, e0, e1);
+    else launch_bt<1>(A2, nbx, st, e0, e1);
     BNOS_HIP(hipGetLastError());
     return BNOS_OK;
 }
@@ -650,11 +678,14 @@ extern "C" bnos_status bnos_score_orders_noalloc(bnos_table h, const int32_t *or
     if (B < 1 || B > (1 << 20)) { set_error("B outside [1, 2^20]"); return BNOS_E_RANGE; }
     if (!orders || !lse || !maxs || !best) { set_error("NULL argument"); return BNOS_E_INVALID; }
     // partials [B][slots][n]: one slot per chunk, or per top member + the empty set in the gather pass
+    // and after them (256-byte aligned) each order's score-bound cut per node
     const int64_t slots = t->gather_for(B) ? t->n : t->chunks_for(B);
-    const int64_t need = (int64_t)B * slots * t->n * (int64_t)sizeof(Partial);
+    const int64_t part_bytes = (int64_t)B * slots * t->n * (int64_t)sizeof(Partial);
+    const int64_t cuts_off = (part_bytes + 255) & ~(int64_t)255;
+    const int64_t need = cuts_off + (int64_t)B * t->n * (int64_t)sizeof(float);
     if (need > (int64_t)kNoAllocScratchBytes) {
         set_error("B = " + std::to_string(B) + " orders need " + std::to_string(need) +
-                  " bytes of scoring partials, above the fixed " + std::to_string(kNoAllocScratchBytes) +
+                  " bytes of scoring partials and cuts, above the fixed " + std::to_string(kNoAllocScratchBytes) +
                   "-byte scratch array of the allocation-free call");
         return BNOS_E_RANGE;
     }
@@ -665,6 +696,7 @@ extern "C" bnos_status bnos_score_orders_noalloc(bnos_table h, const int32_t *or
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     ScoreArgs A = score_args(t, orders, B, lse, maxs, best, node_lse, node_second);
     A.part = reinterpret_cast<Partial *>(part);
+    A.cut_ws = reinterpret_cast<float *>(static_cast<char *>(part) + cuts_off);
     if (t->gather_for(B)) s = launch_gather(t, A, st, false);
     else s = launch_stream(t, A, st, 0, false);
     if (s != BNOS_OK) return s;

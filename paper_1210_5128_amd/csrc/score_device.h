@@ -380,6 +380,8 @@ struct ScoreArgs {
     const float *tmax;         // largest score of each tile (with tand: the score bound), or null
     const uint64_t *cmask;     // [n][kBoundSlots] score-bound candidates of each row (with tmax)
     const float *cscore;
+    const float *cuts;         // [B][n] each order's cut per node, computed before the launch, or null
+    float *cut_ws;             // [B][n] workspace for those cuts (several-order launches)
     int K;
 };
 
@@ -400,6 +402,8 @@ struct TabView {
     const float *tmax;          // [n * S_pad / 256] largest score of each tile, or null (no score bound)
     const uint64_t *cmask;      // [n][kBoundSlots] score-bound candidates of each row (with tmax)
     const float *cscore;
+    const float *cuts;          // [orders][n] each order's (chain's) cut per node, computed by an
+                                // earlier launch, or null (the block computes it)
     int K;
 };
 
@@ -504,6 +508,29 @@ __device__ __forceinline__ float bound_cut(float cv, uint64_t cm, uint64_t np, i
     return fminf(gap_below(b), sec);
 }
 
+// The cut of one (order, node) pair computed by one wavefront alone (lane l
+// holds candidates l, l + 64, l + 128, l + 192), for launches that compute
+// every pair's cut before the scoring launch: the same candidates and the same
+// top two, so the same value as bound_cut.
+__device__ __forceinline__ float wave_bound_cut(const TabView &V, int node, uint64_t np, int lane)
+{
+    float t1 = -INFINITY, t2 = -INFINITY;      // this lane's top two usable candidates
+#pragma unroll
+    for (int i = 0; i < kBoundSlots / 64; ++i) {
+        const uint32_t c = (uint32_t)node * kBoundSlots + (uint32_t)(i * 64 + lane);   // < 2^14
+        const uint64_t cm = V.cmask[c];
+        const float cs = V.cscore[c];
+        const float x = ((cm & np) == 0ull) ? cs : -INFINITY;
+        t2 = fmaxf(t2, fminf(t1, x));
+        t1 = fmaxf(t1, x);
+    }
+    const float m1 = wave_max_f32(t1);
+    const uint64_t at = __ballot(t1 == m1);
+    const int l1 = at ? __builtin_ctzll(at) : 64;
+    const float m2 = wave_max_f32(lane == l1 ? t2 : t1);
+    return fminf(gap_below(m1), m2);
+}
+
 // The same for the BT orders of a several-order block, after the barrier that
 // published their predecessor complements: every wavefront takes each order's
 // top two usable candidates among its own, and a second barrier combines them.
@@ -589,19 +616,21 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         tsl01 = tp[0];
         tsl23 = tp[1];
     }
-    // score bound: lane i's tile maximum and this lane's candidate
+    // score bound: lane i's tile maximum and this lane's candidate (unless the
+    // cuts were computed before the launch)
     const bool bound = V.tmax != nullptr && V.tand != nullptr;
+    const bool pre = bound && V.cuts != nullptr;
     __shared__ float s_lb[kScoreThreads / 64][2];
     __shared__ float s_lbm[kScoreThreads / 64][BT][2];
     float tmx = 0.f, cv = -INFINITY;
     uint64_t cm = ~0ull;
     if (bound) {
         if (lane < steps) tmx = V.tmax[trow + gtile(lane * 4 + wave)];
-        bound_candidate(V, node, wave, lane, cv, cm);
+        if (!pre) bound_candidate(V, node, wave, lane, cv, cm);
     }
 
-    // with the bound and one order, every wavefront forms the predecessor set itself
-    const bool own = BT == 1 && bound;
+    // with the bound computed here and one order, every wavefront forms the predecessor set itself
+    const bool own = BT == 1 && bound && !pre;
     uint64_t np_w = ~0ull;
     for (int j = own ? 0 : wave; j < BT; j += kScoreThreads / 64) {
         uint64_t np = ~0ull;   // no order in this slot: nothing is consistent
@@ -633,7 +662,15 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
         acc_init(a[j]);
         tt[j] = fold_shift(-INFINITY);
     }
-    if (BT > 1 && bound) bound_cuts<BT>(cv, cm, npred, wave, lane, s_lbm, cut);   // a second barrier
+    if (pre) {
+#pragma unroll
+        for (int j = 0; j < BT; ++j) {
+            const int ob = s_ord[j];
+            cut[j] = ob >= 0 ? V.cuts[(int64_t)ob * n + node] : -INFINITY;
+        }
+    } else if (BT > 1 && bound) {
+        bound_cuts<BT>(cv, cm, npred, wave, lane, s_lbm, cut);   // a second barrier
+    }
 
     const u64x2 *mp = reinterpret_cast<const u64x2 *>(V.masks + row);
     const f32x4 *sp = reinterpret_cast<const f32x4 *>(V.scores + row);
@@ -839,6 +876,7 @@ __device__ __forceinline__ TabView view_of(const ScoreArgs &A)
     V.tmax = A.tmax;
     V.cmask = A.cmask;
     V.cscore = A.cscore;
+    V.cuts = A.cuts;
     V.K = A.K;
     return V;
 }
