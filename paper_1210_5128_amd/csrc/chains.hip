@@ -160,14 +160,14 @@ __global__ __launch_bounds__(64) void k_chain_init(const ChainView *__restrict__
 // entry of a chain lies in leaves that chain's state unchanged.
 constexpr int kListThreads = 1024;
 constexpr int kPosBins = 8;
-__global__ __launch_bounds__(kListThreads) void k_worklist(const ChainView *__restrict__ views,
-                                                           const int64_t *__restrict__ node_base, int T)
+__device__ __forceinline__ void worklist_block(const ChainView *__restrict__ views,
+                                               const int64_t *__restrict__ node_base, int T, int64_t blk)
 {
     __shared__ int s_cnt[kPosBins][kListThreads / 64];   // per bin, chains listed by each wave
     __shared__ int s_run[kPosBins];                       // per bin, list position reached
-    const int k = find_segment(node_base, T, (int64_t)blockIdx.x);
+    const int k = find_segment(node_base, T, blk);
     const ChainView &H = views[k];
-    const int node = (int)((int64_t)blockIdx.x - node_base[k]);
+    const int node = (int)(blk - node_base[k]);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     // the bin of chain c for this node, or -1 if its window does not hold the node
@@ -224,17 +224,15 @@ __global__ __launch_bounds__(kListThreads) void k_worklist(const ChainView *__re
     }
 }
 
-// Score bound of the proposals: one wavefront per (chain, node) pair over all
-// tables (pair g: node g mod the total node count, chain g div it) computes the
-// cut of the chain's proposal for that node when the node is in the chain's
-// window, so that the scoring blocks read it instead of each computing it.
-__global__ __launch_bounds__(kScoreThreads) void k_chain_cuts(const TabView *__restrict__ tviews,
-                                                              const ChainView *__restrict__ views,
-                                                              const int64_t *__restrict__ node_base, int T,
-                                                              int C)
+// Score bound of the proposals: the wavefront of (chain, node) pair g over all
+// tables (node g mod the total node count, chain g div it) computes the cut of
+// the chain's proposal for that node when the node is in the chain's window, so
+// that the scoring blocks read it instead of each computing it.
+__device__ __forceinline__ void chain_cut_wave(const TabView *__restrict__ tviews,
+                                               const ChainView *__restrict__ views,
+                                               const int64_t *__restrict__ node_base, int T, int C, int64_t g,
+                                               int lane)
 {
-    const int64_t g = (int64_t)blockIdx.x * (kScoreThreads / 64) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
     const int64_t nodes = node_base[T];
     if (g >= nodes * C) return;                              // uniform per wavefront
     const int c = (int)(g / nodes);
@@ -250,6 +248,23 @@ __global__ __launch_bounds__(kScoreThreads) void k_chain_cuts(const TabView *__r
     const uint64_t pred = __ballot(lane < n && pu < pv);
     const float cut = wave_bound_cut(tviews[k], node, ~pred, lane);
     if (lane == 0) H.cuts[(int64_t)c * n + node] = cut;
+}
+
+// One launch per iteration before the scoring: blocks below the total node count
+// build the work lists (a block per (table, node)); with the score bound, the
+// blocks after them compute the cuts (16 (chain, node) pairs per block, one per
+// wavefront).  Both parts only read the chains' windows and positions, which
+// the previous iteration's k_chain_step wrote, so they run side by side instead
+// of as two launches.
+__global__ __launch_bounds__(kListThreads) void k_worklist(const TabView *__restrict__ tviews,
+                                                           const ChainView *__restrict__ views,
+                                                           const int64_t *__restrict__ node_base, int T, int C)
+{
+    const int64_t nodes = node_base[T];
+    const int64_t blk = blockIdx.x;
+    if (blk < nodes) worklist_block(views, node_base, T, blk);   // uniform per block
+    else chain_cut_wave(tviews, views, node_base, T, C, (blk - nodes) * (kListThreads / 64) + (threadIdx.x >> 6),
+                        threadIdx.x & 63);
 }
 
 // Offer graph g (lane i holds node i's parent mask) with max score M to chain
@@ -704,7 +719,7 @@ static bnos_status run_chains_impl(const bnos_table *hs, int32_t T, const bnos_c
         V.tmax = bound ? t->d_tmax : nullptr;
         V.cmask = bound ? t->d_cmask : nullptr;
         V.cscore = bound ? t->d_cscore : nullptr;
-        V.cuts = H.cuts;               // computed by k_chain_cuts before each scoring launch
+        V.cuts = H.cuts;               // computed by k_worklist before each scoring launch
         V.K = t->K;
         blk_base[k + 1] = blk_base[k] + (int64_t)n * V.chunks;
         chain_base[k + 1] = chain_base[k] + C;
@@ -744,15 +759,13 @@ static bnos_status run_chains_impl(const bnos_table *hs, int32_t T, const bnos_c
     const unsigned total_chains = (unsigned)chain_base[T];
     bool any_bound = false;
     for (int k = 0; k < T; ++k) any_bound = any_bound || cv[k].cuts != nullptr;
+    // blocks of k_worklist that compute the score-bound cuts after the list blocks
+    const int64_t cut_blocks = any_bound ? (node_base[T] * (int64_t)C + kListThreads / 64 - 1) / (kListThreads / 64) : 0;
     hipLaunchKernelGGL(k_chain_init, dim3(total_chains), dim3(64), 0, us, d_cv, d_chain, T);
     CK(hipGetLastError());
     auto one_step = [&](hipStream_t q) -> hipError_t {
-        hipLaunchKernelGGL(k_worklist, dim3((unsigned)node_base[T]), dim3(kListThreads), 0, q, d_cv, d_node, T);
-        if (any_bound) {
-            const int64_t pairs = node_base[T] * (int64_t)C;
-            hipLaunchKernelGGL(k_chain_cuts, dim3((unsigned)((pairs + kScoreThreads / 64 - 1) / (kScoreThreads / 64))),
-                               dim3(kScoreThreads), 0, q, d_tv, d_cv, d_node, T, C);
-        }
+        hipLaunchKernelGGL(k_worklist, dim3((unsigned)(node_base[T] + cut_blocks)), dim3(kListThreads), 0, q, d_tv, d_cv,
+                           d_node, T, C);
         dim3 grid((unsigned)((blk_base[T] + kXcds - 1) / kXcds * kXcds), groups);   // padded for xcd_block
         if (bt == 8) hipLaunchKernelGGL(k_score_multi<8>, grid, dim3(kScoreThreads), 0, q, d_tv, d_blk, T);
         else if (bt == 4) hipLaunchKernelGGL(k_score_multi<4>, grid, dim3(kScoreThreads), 0, q, d_tv, d_blk, T);
