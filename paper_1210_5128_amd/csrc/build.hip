@@ -242,18 +242,18 @@ __device__ __forceinline__ int64_t rank_ascending(uint64_t m, int bits, int K, c
 // cell index (the last member fastest).
 struct Subset {
     int u[kMaxK + 1], r[kMaxK + 1], stride[kMaxK + 1];
-    uint32_t magic[kMaxK + 1];   // floor(2^32 / r) + 1: quotients by r of cell indices (< 2^14) by multiply-high
+    uint32_t magic[kMaxK + 1];   // floor(2^32 / r) + 1: quotients by r of cell indices (<= 2^14) by multiply-high
     int j;        // members
     int cells;    // product of the members' arities
 };
 
-// q = x / r and x - q r for 0 <= x < 2^14 and 1 <= r <= 255: with m = floor(2^32/r) + 1,
-// x m / 2^32 exceeds x / r by less than x / 2^32 < 2^-18, too little to carry a
-// fraction of at most (r - 1) / r past the next integer.
+// q = x / r and x - q r for 0 <= x <= 2^14 and 1 <= r <= 255: with m = floor(2^32/r) + 1,
+// x m / 2^32 exceeds x / r by less than x / 2^32 <= 2^-18, too little to carry a
+// fraction of at most (r - 1) / r past the next integer.  q r <= x fits a 24-bit multiply.
 __device__ __forceinline__ void divmod_small(int x, int r, uint32_t magic, int &q, int &rem)
 {
     q = (r == 1) ? x : (int)__umulhi((uint32_t)x, magic);
-    rem = x - q * r;
+    rem = x - (int)__umul24((uint32_t)q, (uint32_t)r);
 }
 
 __device__ __forceinline__ Subset decode_subset(uint64_t U, const int32_t *__restrict__ ar)
@@ -285,26 +285,46 @@ __device__ __forceinline__ Subset decode_subset(uint64_t U, const int32_t *__res
 
 // Joint histogram of U's variables over the N samples into hist[0 .. cells)
 // (one wavefront, its private LDS region); each lane takes 4 consecutive
-// samples per step from 32-bit loads of the column-major data.
+// samples per step from 32-bit loads of the column-major data.  A cell's byte
+// offset is the sum of each member's state times its stride in bytes: states
+// are below 256 and cells number at most 2^14, so every product and the sum
+// fit 24-bit multiplies.  Whole 256-sample steps need no per-sample check;
+// only the last, partial step tests each sample against N.
 // (J = the number of members, a constant of the instance.)
 template <int J>
 __device__ __forceinline__ void joint_histogram_j(const uint8_t *__restrict__ data, int64_t N, int64_t N_pad,
                                                   const Subset &S, uint32_t *hist, int lane)
 {
     const uint32_t *col[J];
+    uint32_t st4[J];
 #pragma unroll
-    for (int t = 0; t < J; ++t) col[t] = reinterpret_cast<const uint32_t *>(data + (int64_t)S.u[t] * N_pad);
-    for (int64_t base = (int64_t)lane * 4; base < N; base += 256) {
+    for (int t = 0; t < J; ++t) {
+        col[t] = reinterpret_cast<const uint32_t *>(data + (int64_t)S.u[t] * N_pad);
+        st4[t] = (uint32_t)S.stride[t] * 4u;
+    }
+    char *hb = reinterpret_cast<char *>(hist);
+    auto offset_of = [&](const uint32_t (&x)[J], int b) -> uint32_t {
+        uint32_t off = 0;
+#pragma unroll
+        for (int t = 0; t < J; ++t) off += __umul24((x[t] >> (8 * b)) & 0xffu, st4[t]);
+        return off;
+    };
+    const int64_t whole = N & ~(int64_t)255;
+    for (int64_t base = (int64_t)lane * 4; base < whole; base += 256) {
         uint32_t x[J];
 #pragma unroll
         for (int t = 0; t < J; ++t) x[t] = col[t][base >> 2];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            int cell = 0;
+        for (int b = 0; b < 4; ++b) atomicAdd(reinterpret_cast<uint32_t *>(hb + offset_of(x, b)), 1u);
+    }
+    const int64_t base = whole + (int64_t)lane * 4;
+    if (base < N) {
+        uint32_t x[J];
 #pragma unroll
-            for (int t = 0; t < J; ++t) cell += S.stride[t] * (int)((x[t] >> (8 * b)) & 0xffu);
-            if (base + b < N) atomicAdd(&hist[cell], 1u);
-        }
+        for (int t = 0; t < J; ++t) x[t] = col[t][base >> 2];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if (base + b < N) atomicAdd(reinterpret_cast<uint32_t *>(hb + offset_of(x, b)), 1u);
     }
 }
 
@@ -325,20 +345,25 @@ __device__ __forceinline__ void joint_histogram(const uint8_t *__restrict__ data
     wave_lds_sync();
 }
 
-// Member c of U as the child of the family (u_c, U \ {u_c}): its id, arity and
-// digit stride, selected without indexing the arrays by c.
-__device__ __forceinline__ void subset_member(const Subset &S, int c, int &node, int &ri, int &sci)
+// Member c of U as the child of the family (u_c, U \ {u_c}): its id, arity,
+// digit stride and the family's number of parent configurations (the cells
+// divided by the arity), selected without indexing the arrays by c.
+__device__ __forceinline__ void subset_member(const Subset &S, int c, int &node, int &ri, int &sci, int &q)
 {
     node = 0;
     ri = 1;
     sci = 1;
+    uint32_t mag = 0;
 #pragma unroll
     for (int t = 0; t <= kMaxK; ++t)
         if (t == c) {
             node = S.u[t];
             ri = S.r[t];
             sci = S.stride[t];
+            mag = S.magic[t];
         }
+    int rem;
+    divmod_small(S.cells, ri, mag, q, rem);
 }
 
 // Joint cell of parent configuration k of the family whose child is member c,
@@ -353,7 +378,7 @@ __device__ __forceinline__ int family_base(const Subset &S, int c, int k)
         if (t < S.j && t != c) {
             int q, d;
             divmod_small(rest, S.r[t], S.magic[t], q, d);
-            J += d * S.stride[t];
+            J += (int)__umul24((uint32_t)d, (uint32_t)S.stride[t]);
             rest = q;
         }
     }
@@ -378,7 +403,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_build_joint(
     const double *__restrict__ lut, uint64_t *__restrict__ masks, float *__restrict__ scores)
 {
     extern __shared__ uint32_t lds_hist[];
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: the subset's decode stays scalar
     const int lane = threadIdx.x & 63;
     uint32_t *hist = lds_hist + wave * cells_cap;
     for (int64_t g = (int64_t)blockIdx.x * WAVES + wave; g < n_subsets; g += (int64_t)gridDim.x * WAVES) {
@@ -388,9 +413,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_build_joint(
         joint_histogram(data, N, N_pad, Sb, hist, lane);
         // one family per member
         for (int c = 0; c < j; ++c) {
-            int node, ri, sci;
-            subset_member(Sb, c, node, ri, sci);
-            const int q = cells / ri;
+            int node, ri, sci, q;
+            subset_member(Sb, c, node, ri, sci, q);
             const double *L_ijk = lut + (int64_t)lut_row[cells] * (N + 1);
             const double *L_ik = lut + (int64_t)lut_row[q] * (N + 1);
             double acc = 0.0;
@@ -399,7 +423,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_build_joint(
                 uint32_t nik = 0;
                 double part = 0.0;
                 for (int x = 0; x < ri; ++x) {
-                    const uint32_t cnt = hist[J + x * sci];
+                    const uint32_t cnt = hist[J + (int)__umul24((uint32_t)x, (uint32_t)sci)];
                     nik += cnt;
                     if (cnt) part += L_ijk[cnt];
                 }
@@ -739,7 +763,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_counts_joint(
     const int64_t *__restrict__ qoff, int cells_cap, uint32_t *__restrict__ out)
 {
     extern __shared__ uint32_t lds_hist[];
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: the subset's decode stays scalar
     const int lane = threadIdx.x & 63;
     uint32_t *hist = lds_hist + wave * cells_cap;
     for (int qi = blockIdx.x * WAVES + wave; qi < Q; qi += gridDim.x * WAVES) {
@@ -748,12 +772,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_counts_joint(
         const Subset Sb = decode_subset(U, ar);
         joint_histogram(data, N, N_pad, Sb, hist, lane);
         const int c = __popcll(U & ((1ull << child) - 1ull));       // the child's place among U's members
-        int node, ri, sci;
-        subset_member(Sb, c, node, ri, sci);
-        const int q = Sb.cells / ri;
+        int node, ri, sci, q;
+        subset_member(Sb, c, node, ri, sci, q);
         for (int k = lane; k < q; k += 64) {
             const int J = family_base(Sb, c, k);
-            for (int x = 0; x < ri; ++x) out[qoff[qi] + (int64_t)k * ri + x] = hist[J + x * sci];
+            for (int x = 0; x < ri; ++x)
+                out[qoff[qi] + (int64_t)k * ri + x] = hist[J + (int)__umul24((uint32_t)x, (uint32_t)sci)];
         }
         wave_lds_sync();
     }
