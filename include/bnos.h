@@ -372,7 +372,11 @@ bnos_status bnos_run_chains(bnos_table t, const bnos_chain_cfg *cfg, bnos_chain_
  * cfg->chains chains whose RNG stream ids are chain_offset + k*chains + c,
  * and its own state states[k] (sized by tables[k]'s n).  Each chain's
  * trajectory is the one bnos_run_chains gives it with that chain id.
- * T is 1..4096; a table may appear once.
+ * T is 1..4096; a table may appear once.  With the score bound on, the
+ * per-iteration launch that lists each node's chains also holds one
+ * wavefront per (chain, node) pair; a call whose pairs (summed over the
+ * tables) exceed that launch's 2^32 work-items returns BNOS_E_RANGE before
+ * any kernel runs.
  */
 bnos_status bnos_run_chains_multi(const bnos_table *tables, int32_t T, const bnos_chain_cfg *cfg,
                                   bnos_chain_state *states, void *stream);

@@ -761,6 +761,11 @@ static bnos_status run_chains_impl(const bnos_table *hs, int32_t T, const bnos_c
     for (int k = 0; k < T; ++k) any_bound = any_bound || cv[k].cuts != nullptr;
     // blocks of k_worklist that compute the score-bound cuts after the list blocks
     const int64_t cut_blocks = any_bound ? (node_base[T] * (int64_t)C + kListThreads / 64 - 1) / (kListThreads / 64) : 0;
+    if ((node_base[T] + cut_blocks) * kListThreads > (int64_t)UINT32_MAX) {
+        set_error("too many (chain, node) pairs for one launch: lower the chains or the tables per call");
+        cleanup();
+        return BNOS_E_RANGE;
+    }
     hipLaunchKernelGGL(k_chain_init, dim3(total_chains), dim3(64), 0, us, d_cv, d_chain, T);
     CK(hipGetLastError());
     auto one_step = [&](hipStream_t q) -> hipError_t {
