@@ -334,7 +334,21 @@ __global__ __launch_bounds__(kStepWaves * 64) void k_chain_step(const TabView *_
     const uint64_t wm = H.wmask[c];
     const bool learned = H.proposal == 1;
     const bool harvest = H.hv_feat != nullptr;
+    // wave 0's reads of the chain's cached values and counters, requested before
+    // the merge so that their latency overlaps it (only this block reads or
+    // writes chain c's rows)
+    double l0 = 0.0, m0 = 0.0, s0 = 0.0, score0 = 0.0, best0 = 0.0;
+    int64_t t0 = 0, nacc0 = 0;
     if (wave == 0) {
+        if (lane < n) {
+            l0 = H.node_l[row + lane];
+            m0 = H.node_m[row + lane];
+            s0 = H.node_sec[row + lane];
+        }
+        t0 = H.t[c];
+        score0 = H.score[c];
+        best0 = H.best_score[c];
+        nacc0 = H.accepted[c];
         const bool in = lane < n && ((wm >> lane) & 1ull);
         const uint64_t bal = __ballot(in);
         if (in) s_nodes[__popcll(bal & ((1ull << lane) - 1ull))] = lane;
@@ -364,8 +378,8 @@ __global__ __launch_bounds__(kStepWaves * 64) void k_chain_step(const TabView *_
         if (tid < n) {
             const int i = tid;
             const bool in = (wm >> i) & 1ull;
-            const double best = in ? s_b[i] : H.node_m[row + i];
-            const double sec = in ? s_s[i] : H.node_sec[row + i];
+            const double best = in ? s_b[i] : m0;   // tid < n: wave 0, lane i
+            const double sec = in ? s_s[i] : s0;
             float *f = s_feat + i * kF;
             f[0] = (float)s_posp[i] / (float)n;
             f[1] = (float)best;
@@ -379,13 +393,13 @@ __global__ __launch_bounds__(kStepWaves * 64) void k_chain_step(const TabView *_
     if (wave != 0) return;
 
     const bool in = lane < n && ((wm >> lane) & 1ull);
-    const double li = lane < n ? (in ? s_l[lane] : H.node_l[row + lane]) : 0.0;
-    const double mi = lane < n ? (in ? s_b[lane] : H.node_m[row + lane]) : 0.0;
-    const double si = lane < n ? (in ? s_s[lane] : H.node_sec[row + lane]) : 0.0;
+    const double li = lane < n ? (in ? s_l[lane] : l0) : 0.0;
+    const double mi = lane < n ? (in ? s_b[lane] : m0) : 0.0;
+    const double si = lane < n ? (in ? s_s[lane] : s0) : 0.0;
     const double L = wave_sum_f64(li, lane);
     const double M = wave_sum_f64(mi, lane);
     const uint64_t chain = (uint64_t)(H.chain0 + c);
-    const int64_t t = H.t[c];
+    const int64_t t = t0;
     const double nv = H.target ? M : L;
     int acc = 0, imp = 0, slot = -1;
     if (lane == 0) {
@@ -398,14 +412,14 @@ __global__ __launch_bounds__(kStepWaves * 64) void k_chain_step(const TabView *_
                 if (H.trace) H.trace[(int64_t)c * H.trace_len] = nv;
             }
         } else {
-            double ratio = nv - H.score[c];
+            double ratio = nv - score0;
             if (learned) ratio += pair_logq_dev(s_mlp.logit, n, H.pend[2 * c], H.pend[2 * c + 1], H.eps) - H.lq_fwd[c];
             const double u = rng_unit_open(rng_draw(H.seed, chain, 3, (uint64_t)t));
             acc = log(u) < ratio;
             if (acc) {
                 H.score[c] = nv;
-                H.accepted[c] += 1;
-                if (M > H.best_score[c]) {
+                H.accepted[c] = nacc0 + 1;
+                if (M > best0) {
                     H.best_score[c] = M;
                     imp = 1;
                 }
@@ -418,7 +432,8 @@ __global__ __launch_bounds__(kStepWaves * 64) void k_chain_step(const TabView *_
             }
             if (H.flags) H.flags[(int64_t)c * H.iterations + (t - H.t_first - 1)] = (uint8_t)acc;
             const int64_t kk = t - H.t_first;
-            if (H.trace && kk % H.trace_every == 0) H.trace[(int64_t)c * H.trace_len + kk / H.trace_every] = H.score[c];
+            if (H.trace && kk % H.trace_every == 0)
+                H.trace[(int64_t)c * H.trace_len + kk / H.trace_every] = acc ? nv : score0;   // the chain's score now
         }
     }
     acc = __shfl(acc, 0, 64);
@@ -427,7 +442,7 @@ __global__ __launch_bounds__(kStepWaves * 64) void k_chain_step(const TabView *_
     if (slot >= 0 && lane < n) {
         // raw features of the order before the move (current caches)
         float *f = H.hv_feat + (((int64_t)c * H.hv_cap + slot) * n + lane) * kF;
-        const double best = H.node_m[row + lane], sec = H.node_sec[row + lane];
+        const double best = m0, sec = s0;   // the caches before this step's update
         f[0] = (float)s_posc[lane] / (float)n;
         f[1] = (float)best;
         f[2] = isinf(sec) ? 0.f : (float)(best - sec);
