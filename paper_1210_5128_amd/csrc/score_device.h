@@ -131,19 +131,26 @@ __device__ __forceinline__ float fold_shift(float best) { return fmaxf(best, kSc
 __device__ __forceinline__ void acc_fold4(Acc &a, float &t, const float (&x)[4], const uint64_t (&mk)[4])
 {
 #pragma clang fp contract(off)     // t_old - t_new must subtract the two rounded shifts
-    const float b = fmaxf(fmaxf(x[0], x[1]), fmaxf(x[2], x[3]));
+    const float m01 = fmaxf(x[0], x[1]), n01 = fminf(x[0], x[1]);
+    const float m23 = fmaxf(x[2], x[3]), n23 = fminf(x[2], x[3]);
+    const float b = fmaxf(m01, m23);
     a.sec = fmaxf(a.sec, b);
     if (b > a.best) {
-        const int i = x[0] == b ? 0 : (x[1] == b ? 1 : (x[2] == b ? 2 : 3));
-        float o = -INFINITY;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) o = (e != i) ? fmaxf(o, x[e]) : o;
+        // o: the largest of the other three entries (b again if b occurs twice);
+        // the argmax: the first entry holding b
+        const float o = fmaxf(fminf(m01, m23), fmaxf(n01, n23));
+        uint64_t k0 = mk[0], k1 = mk[1], k2 = mk[2], k3 = mk[3];
+        asm volatile("" : "+v"(k0), "+v"(k1), "+v"(k2), "+v"(k3));   // selects in registers, not an indexed copy
+        uint64_t bmk = k3;
+        bmk = x[2] == b ? k2 : bmk;
+        bmk = x[1] == b ? k1 : bmk;
+        bmk = x[0] == b ? k0 : bmk;
         const float tn = b * kLog2e;
         a.s *= __builtin_amdgcn_exp2f(t - tn);               // 0 when nothing was held
         t = tn;
         a.sec = fmaxf(a.best, o);
         a.best = b;
-        a.bm = i == 0 ? mk[0] : (i == 1 ? mk[1] : (i == 2 ? mk[2] : mk[3]));
+        a.bm = bmk;
     }
     const float e0 = __builtin_amdgcn_exp2f(fmaf(x[0], kLog2e, -t)), e1 = __builtin_amdgcn_exp2f(fmaf(x[1], kLog2e, -t));
     const float e2 = __builtin_amdgcn_exp2f(fmaf(x[2], kLog2e, -t)), e3 = __builtin_amdgcn_exp2f(fmaf(x[3], kLog2e, -t));
