@@ -151,8 +151,9 @@ __global__ __launch_bounds__(kScoreThreads) void k_gather(ScoreArgs A, const int
 // Orders per block: a block folds every streamed entry into this many order states.
 int pick_bt(const TableT *t, int B)
 {
-    // 4 orders per block for 4 or more (measured: 256 chains at n=40 and 60 step 8-16% faster
-    // than with 8, whose 84 registers per lane leave 6 wavefronts per SIMD resident instead of 8)
+    // 4 orders per block for 4 or more (256 chains at n=40 step 4-8% faster than with 8, whose
+    // 95 registers per lane leave 5 wavefronts per SIMD resident instead of 7; at n=60 8 is 3-5%
+    // faster, which the autotuners pick per table and batch-size bucket)
     int bt = B >= 4 ? 4 : (B >= 2 ? 2 : 1);
     // autotuned choice for the batch-size bucket, if any
     const int k = TableT::bucket(B);
