@@ -242,12 +242,24 @@ __device__ __forceinline__ void chain_cut_wave(const TabView *__restrict__ tview
     const int node = (int)(gn - node_base[k]);
     if (!H.cuts || !((H.wmask[c] >> node) & 1ull)) return;  // uniform
     const int n = H.n;
+    const int64_t ci = (int64_t)c * n + node;
+    // Once the chain holds an adopted order (after its first iteration in this
+    // call), the node's best parent set in that order and its score are cached;
+    // if the proposal still allows that set, its score bounds the proposal's best
+    // from below, often far more tightly than the listed candidates (the node's
+    // predecessors change by at most the two swapped nodes).  The three reads are
+    // issued with the positions' and used only once the caches are valid.
+    const bool cached = H.t[c] > H.t_first;
+    const uint64_t bset = H.node_best[ci];
+    const double bscore = H.node_m[ci];                      // an FP32 score held in FP64: exact
     const uint8_t *pp = H.ppos + (int64_t)c * n;
     const int pv = pp[node];
     const int pu = pp[lane < n ? lane : n - 1];              // every lane loads (no branch)
     const uint64_t pred = __ballot(lane < n && pu < pv);
-    const float cut = wave_bound_cut(tviews[k], node, ~pred, lane);
-    if (lane == 0) H.cuts[(int64_t)c * n + node] = cut;
+    const bool use = cached && (bset & ~pred) == 0ull;
+    const float cut = wave_bound_cut(tviews[k], node, ~pred, lane, use ? (float)bscore : -INFINITY,
+                                     use ? bset : ~0ull);
+    if (lane == 0) H.cuts[ci] = cut;
 }
 
 // One launch per iteration before the scoring: blocks below the total node count

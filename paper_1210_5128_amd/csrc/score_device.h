@@ -518,8 +518,12 @@ __device__ __forceinline__ float bound_cut(float cv, uint64_t cm, uint64_t np, i
 // The cut of one (order, node) pair computed by one wavefront alone (lane l
 // holds candidates l, l + 64, l + 128, l + 192), for launches that compute
 // every pair's cut before the scoring launch: the same candidates and the same
-// top two, so the same value as bound_cut.
-__device__ __forceinline__ float wave_bound_cut(const TabView &V, int node, uint64_t np, int lane)
+// top two, so the same value as bound_cut.  A caller that knows one more usable
+// entry of the row (score kv, node-space mask km; kv = -inf: none) adds it: the
+// candidate with the same mask is left out, so the top two stay two distinct
+// entries and both bounds stay bounds.
+__device__ __forceinline__ float wave_bound_cut(const TabView &V, int node, uint64_t np, int lane,
+                                                float kv = -INFINITY, uint64_t km = ~0ull)
 {
     float t1 = -INFINITY, t2 = -INFINITY;      // this lane's top two usable candidates
 #pragma unroll
@@ -527,9 +531,13 @@ __device__ __forceinline__ float wave_bound_cut(const TabView &V, int node, uint
         const uint32_t c = (uint32_t)node * kBoundSlots + (uint32_t)(i * 64 + lane);   // < 2^14
         const uint64_t cm = V.cmask[c];
         const float cs = V.cscore[c];
-        const float x = ((cm & np) == 0ull) ? cs : -INFINITY;
+        const float x = ((cm & np) == 0ull && cm != km) ? cs : -INFINITY;
         t2 = fmaxf(t2, fminf(t1, x));
         t1 = fmaxf(t1, x);
+    }
+    if (lane == 0) {
+        t2 = fmaxf(t2, fminf(t1, kv));
+        t1 = fmaxf(t1, kv);
     }
     const float m1 = wave_max_f32(t1);
     const uint64_t at = __ballot(t1 == m1);
