@@ -275,8 +275,10 @@ __global__ __launch_bounds__(kListThreads) void k_worklist(const TabView *__rest
     const int64_t nodes = node_base[T];
     const int64_t blk = blockIdx.x;
     if (blk < nodes) worklist_block(views, node_base, T, blk);   // uniform per block
-    else chain_cut_wave(tviews, views, node_base, T, C, (blk - nodes) * (kListThreads / 64) + (threadIdx.x >> 6),
-                        threadIdx.x & 63);
+    else   // the wavefront index read as uniform, so the pair's reads go through scalar loads
+        chain_cut_wave(tviews, views, node_base, T, C,
+                       (blk - nodes) * (kListThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+                       threadIdx.x & 63);
 }
 
 // Offer graph g (lane i holds node i's parent mask) with max score M to chain

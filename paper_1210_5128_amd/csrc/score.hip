@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kMergeWaves * 64) void k_merge(ScoreArgs A)
 // (a node's row is streamed by many blocks).
 __global__ __launch_bounds__(kScoreThreads) void k_bound_pre(ScoreArgs A)
 {
-    const int64_t g = (int64_t)blockIdx.x * (kScoreThreads / 64) + (threadIdx.x >> 6);
+    const int64_t g = (int64_t)blockIdx.x * (kScoreThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int n = A.n;
     if (g >= (int64_t)A.B * n) return;            // uniform per wavefront
