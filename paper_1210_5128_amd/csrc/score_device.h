@@ -605,7 +605,7 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     __shared__ int s_ord[BT];
     const int b0 = group * BT;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar order and list reads
     const int n = V.n;
     // orders this block folds: slots b0..b0+BT-1 of the plain batch or of node's work list
     const int count = V.wl_count ? V.wl_count[node] : V.B;
