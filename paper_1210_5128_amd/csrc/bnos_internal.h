@@ -23,6 +23,18 @@ constexpr int kScoreThreads = 256;
 constexpr int kEntriesPerStep = 1024;
 constexpr int kMaxStepsPerChunk = 16;
 
+// Place of the summaries (tile AND, sub-tile ANDs, tile maximum) of tile w of
+// step s of a row inside that row's summary arrays.  The row's steps form C
+// chunks of the longest chunk length P (the row padding), chunk c holding steps
+// c, c + C, c + 2C, ... as the scoring blocks take them; a chunk's summaries are
+// stored together (its i-th step's tile w at (c P + i) 4 + w), so the blocks of
+// that launch shape read theirs from one run of memory.  A permutation of the
+// row's tiles: only where the summaries sit changes, not what they hold.
+__host__ __device__ inline int64_t summary_pos(int64_t s, int w, int64_t C, int P)
+{
+    return ((s % C) * P + s / C) * 4 + w;
+}
+
 // Score bound of the streaming pass: a block first takes, for each of its
 // orders, lower bounds on the best and the second-best consistent entry of its
 // node from entries it knows the order can use (the empty set, the singletons

@@ -597,15 +597,20 @@ __global__ __launch_bounds__(1024) void k_node_stats(const float *__restrict__ s
 }
 
 // AND of the masks of every 256-entry tile and of its four 64-entry sub-tiles,
-// and the tile's largest score (one wavefront per tile).
+// and the tile's largest score (one wavefront per tile), stored at the tile's
+// summary place (summary_pos: row_tiles tiles per row, in sum_chunks chunks of
+// sum_steps steps).
 __global__ __launch_bounds__(256) void k_tile_and(const uint64_t *__restrict__ masks,
                                                   const float *__restrict__ scores, int64_t tiles,
+                                                  int64_t row_tiles, int64_t sum_chunks, int sum_steps,
                                                   uint64_t *__restrict__ tand, uint64_t *__restrict__ tsub,
                                                   float *__restrict__ tmax)
 {
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (tile >= tiles) return;                       // uniform per wavefront
+    const int64_t row = tile / row_tiles, r = tile - row * row_tiles;
+    const int64_t at = row * row_tiles + summary_pos(r >> 2, (int)(r & 3), sum_chunks, sum_steps);
     const uint64_t *p = masks + tile * 256 + lane * 4;
     const float *q = scores + tile * 256 + lane * 4;
     uint64_t v = p[0] & p[1] & p[2] & p[3];
@@ -613,14 +618,14 @@ __global__ __launch_bounds__(256) void k_tile_and(const uint64_t *__restrict__ m
     // lanes 16s .. 16s+15 hold sub-tile s (entries 64s .. 64s+63)
 #pragma unroll
     for (int off = 1; off <= 8; off <<= 1) v &= (uint64_t)__shfl_xor((unsigned long long)v, off, 64);
-    if ((lane & 15) == 0) tsub[tile * 4 + (lane >> 4)] = v;
+    if ((lane & 15) == 0) tsub[at * 4 + (lane >> 4)] = v;
 #pragma unroll
     for (int off = 16; off <= 32; off <<= 1) v &= (uint64_t)__shfl_xor((unsigned long long)v, off, 64);
 #pragma unroll
     for (int off = 1; off <= 32; off <<= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
     if (lane == 0) {
-        tand[tile] = v;
-        tmax[tile] = x;
+        tand[at] = v;
+        tmax[at] = x;
     }
 }
 
@@ -1123,8 +1128,10 @@ extern "C" bnos_status bnos_build_score_table(const int8_t *data, int64_t N, int
     CK(hipGetLastError());
     {
         const int64_t tiles = (int64_t)n * (t->S_pad / 256);
+        const int64_t row_tiles = t->S_pad / 256;
         hipLaunchKernelGGL(k_tile_and, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, t->d_masks,
-                           t->d_scores, tiles, t->d_tand, t->d_tsub, t->d_tmax);
+                           t->d_scores, tiles, row_tiles, row_tiles / (4 * (int64_t)t->pad_steps), t->pad_steps,
+                           t->d_tand, t->d_tsub, t->d_tmax);
         CK(hipGetLastError());
         hipLaunchKernelGGL(k_bound_cands, dim3(n), dim3(1024), 0, st, t->d_masks, t->d_scores, n, K, t->S,
                            t->S_pad, t->d_cmask, t->d_cscore);

@@ -736,6 +736,8 @@ static bnos_status run_chains_impl(const bnos_table *hs, int32_t T, const bnos_c
         V.S_pad = t->S_pad;
         V.chunks = t->chain_chunks_for(C);
         V.chunk_entries = t->chain_chunk_entries_for(C);
+        V.sum_chunks = t->S_pad / ((int64_t)t->pad_steps * kEntriesPerStep);
+        V.sum_steps = t->pad_steps;
         V.n = n;
         V.B = C;
         V.orders = H.prop;

@@ -236,6 +236,8 @@ ScoreArgs score_args(const TableT *t, const int32_t *orders, int B, double *lse,
     A.S_pad = t->S_pad;
     A.chunks = t->chunks_for(B);
     A.chunk_entries = t->chunk_entries_for(B);
+    A.sum_chunks = t->S_pad / ((int64_t)t->pad_steps * kEntriesPerStep);
+    A.sum_steps = t->pad_steps;
     A.orders = orders;
     A.B = B;
     A.n = t->n;

@@ -370,6 +370,8 @@ struct ScoreArgs {
     const float *scores;
     int64_t S_pad;
     int chunks, chunk_entries;
+    int64_t sum_chunks;      // the summaries' layout: chunks of sum_steps steps per row (summary_pos)
+    int sum_steps;
     const int32_t *orders;
     int B, n;
     Partial *part;          // [B][chunks][n]
@@ -398,6 +400,8 @@ struct TabView {
     const float *scores;
     int64_t S_pad;
     int chunks, chunk_entries, n;
+    int64_t sum_chunks;         // the summaries' layout: chunks of sum_steps steps per row (summary_pos)
+    int sum_steps;
     int B;                      // orders (chains) of this table; row stride of wl_list
     const int32_t *orders;      // [B][n]
     Partial *part;              // [B][chunks][n]
@@ -621,13 +625,21 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     const int64_t trow = row >> 8;                            // and first tile
     // each wavefront owns local tiles wave + 4*i, i < steps (the block's steps: chunk + i * chunks)
     auto gtile = [&](int tl) -> int64_t { return ((chunk + (int64_t)(tl >> 2) * chunks) << 2) + (tl & 3); };
+    // where the summaries of this wavefront's tile of the block's step i sit: one
+    // run per block when the launch takes the longest chunks
+    auto spos = [&](int i) -> int64_t {
+        return trow + (chunks == V.sum_chunks ? ((int64_t)chunk * V.sum_steps + i) * 4 + wave
+                                              : summary_pos(chunk + (int64_t)i * chunks, wave, V.sum_chunks,
+                                                            V.sum_steps));
+    };
+    const int64_t tpos = spos(lane < steps ? lane : 0);
     // this wavefront's tile summaries, requested before the predecessor masks so the latencies overlap
     uint64_t tsum = 0;
-    if (V.tand && lane < steps) tsum = V.tand[trow + gtile(lane * 4 + wave)];
+    if (V.tand && lane < steps) tsum = V.tand[tpos];
     // sub-tile summaries (one order per block): lane i holds the 4 of this wavefront's tile i
     u64x2 tsl01 = {0ull, 0ull}, tsl23 = {0ull, 0ull};
     if (BT == 1 && V.tand && lane < steps) {
-        const u64x2 *tp = reinterpret_cast<const u64x2 *>(V.tsub + (trow + gtile(lane * 4 + wave)) * 4);
+        const u64x2 *tp = reinterpret_cast<const u64x2 *>(V.tsub + tpos * 4);
         tsl01 = tp[0];
         tsl23 = tp[1];
     }
@@ -640,7 +652,7 @@ __device__ __forceinline__ void score_block(const TabView &V, int node, int chun
     float tmx = 0.f, cv = -INFINITY;
     uint64_t cm = ~0ull;
     if (bound) {
-        if (lane < steps) tmx = V.tmax[trow + gtile(lane * 4 + wave)];
+        if (lane < steps) tmx = V.tmax[tpos];
         if (!pre) bound_candidate(V, node, wave, lane, cv, cm);
     }
 
@@ -879,6 +891,8 @@ __device__ __forceinline__ TabView view_of(const ScoreArgs &A)
     V.S_pad = A.S_pad;
     V.chunks = A.chunks;
     V.chunk_entries = A.chunk_entries;
+    V.sum_chunks = A.sum_chunks;
+    V.sum_steps = A.sum_steps;
     V.n = A.n;
     V.B = A.B;
     V.orders = A.orders;
@@ -945,7 +959,8 @@ __global__ __launch_bounds__(kScoreThreads) void k_count_tiles(ScoreArgs A, unsi
     unsigned c = 0;
     if (b0 < count) {
         for (int it = 0; it < steps; ++it) {
-            const int64_t tile = trow + ((chunk + (int64_t)it * A.chunks) << 2) + wave;   // as in score_block
+            const int64_t tile = trow + summary_pos(chunk + (int64_t)it * A.chunks, wave, A.sum_chunks,
+                                                    A.sum_steps);   // the summaries score_block reads
             const uint64_t sm = A.tand[tile];
             const float tm = bound ? A.tmax[tile] : 0.f;
             bool any = false;
